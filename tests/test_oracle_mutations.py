@@ -1,0 +1,114 @@
+"""Planted mistakes in the oracle must each fail at least one pin.
+
+Every mutation below is a plausible slip (a dropped term, a wrong sign, a swapped index or
+a transposed operand).  It is patched into the oracle module on the CPU, the fast pins of
+``test_oracle_pins`` are run against the mutated oracle, and at least one must fail.
+"""
+import numpy as np
+import pytest
+
+import test_oracle_pins as pins
+from oracle import nlpr_oracle as o
+
+FAST_PINS = [
+    pins.test_shift_and_difference_operator_brute_force,
+    pins.test_blur_brute_force_and_adjoint,
+    pins.test_adjointness_of_every_operator,
+    pins.test_weights_brute_force_from_patch_vectors,
+    pins.test_weights_invariants,
+    pins.test_regulariser_patch_form_equals_filter_form,
+    pins.test_denominator_closed_form,
+    pins.test_soft_threshold_is_prox_of_weighted_l1,
+    pins.test_p1_update_solves_its_normal_equation,
+    pins.test_p2_update_zeroes_its_gradient,
+    pins.test_admm_step_subproblem_optimality,
+    pins.test_two_iteration_band_form_equals_full_iteration,
+    lambda: pins.test_x_update_equals_dense_solve(6, 8, 1, 1),
+    lambda: pins.test_lambda2_zero_with_square_R_gives_the_least_squares_solution(0, 0.5, 500),
+]
+
+_orig = {name: getattr(o, name) for name in dir(o) if callable(getattr(o, name))}
+
+
+def _mut_D(X, tau, k):               # wrong sign of tau
+    return o.shift(X, k) - o.shift(X, (k[0] - tau[0], k[1] - tau[1]))
+
+
+def _mut_DT(Y, tau, k):              # adjoint shifts the wrong way
+    return o.shift(Y, k) - o.shift(Y, (tau[0] + k[0], tau[1] + k[1]))
+
+
+def _mut_blurT(Y, b):                # B^T taken as B
+    return _orig["blur"](Y, b)
+
+
+def _mut_den(p, q, b, window, K):    # dropped |P| factor
+    return _orig["denominator"](p, q, b, window, 0) if K else _orig["denominator"](p, q, b, window, 1)
+
+
+def _mut_p2_matrix(pr):              # lambda1 / rho inverted
+    return np.linalg.inv(np.eye(pr.L) + (pr.rho / pr.lam1) * (pr.R @ pr.R.T))
+
+
+def _mut_p1(BX, Lam1, Yl, pr):       # (1 + rho) replaced by rho on the sampled pixels
+    M = o.sampling_mask(pr.p, pr.q, pr.d)[None]
+    StYl = o.decimate_T(Yl, pr.d, pr.p, pr.q)
+    return M * (pr.rho * BX + StYl - pr.rho * Lam1) / pr.rho + (1 - M) * (BX - Lam1)
+
+
+def _mut_soft(x, mu):                # half threshold
+    return np.sign(x) * np.maximum(np.abs(x) - 0.5 * mu, 0.0)
+
+
+def _mut_weights(Yh, window, K, h, unweighted=False):   # h instead of h^2
+    if unweighted:
+        return np.ones((len(window),) + Yh.shape[-2:])
+    return np.stack([np.exp(-o.patch_distance(Yh, t, K) / h) for t in window])
+
+
+def _mut_shift(X, t):                # shift in the wrong direction
+    return np.roll(X, shift=(-t[0], -t[1]), axis=(-2, -1))
+
+
+def _mut_rhs(st, pr):                # dropped Lambda2 from the right-hand side
+    C = o.blur_T(st.P1 + st.Lam1, pr.b) + st.P2
+    for n, t in enumerate(pr.window):
+        for m, k in enumerate(pr.patch):
+            C += o.D_T(st.Q[n, m] + st.Sig[n, m], t, k)
+    return C
+
+
+def _mut_spectral(X, R):             # bands of R taken in reverse order
+    p, q = X.shape[-2:]
+    return o.from_mat(o.to_mat(X) @ R[::-1], p, q)
+
+
+MUTATIONS = {
+    "D": _mut_D, "D_T": _mut_DT, "blur_T": _mut_blurT, "denominator": _mut_den,
+    "p2_matrix": _mut_p2_matrix, "p1_update": _mut_p1, "soft_threshold": _mut_soft,
+    "weights": _mut_weights, "shift": _mut_shift, "rhs": _mut_rhs, "spectral": _mut_spectral,
+}
+
+
+def _admm_dual_sign(st, Yl, Yh, pr, den, mu, F):      # dual update with the wrong sign
+    X, nst = _orig["admm_step"](st, Yl, Yh, pr, den, mu, F)
+    BX = o.blur(X, pr.b)
+    nst.Lam1 = st.Lam1 + (BX - nst.P1)
+    return X, nst
+
+
+MUTATIONS["admm_step"] = _admm_dual_sign
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    monkeypatch.setattr(o, name, MUTATIONS[name])
+    failures = 0
+    for pin in FAST_PINS:
+        try:
+            pin()
+        except AssertionError:
+            failures += 1
+        except Exception:             # a crash under the mutation also counts as caught
+            failures += 1
+    assert failures >= 1, f"no pin caught the planted mistake in {name}"
