@@ -1,0 +1,215 @@
+/*
+ * nlpr.h - C ABI of libnlpr, an MI355X (gfx950) implementation of the ADMM solver of
+ * guided nonlocal patch-regularised (NLPR) multiband fusion:
+ *
+ *   Unni V. S., P. Nair, K. N. Chaudhury, "Guided Nonlocal Patch Regularization and
+ *   Efficient Filtering-Based Inversion for Multiband Fusion", arXiv 2210.04184.
+ *
+ * Problem (Sec. "Variational models", eqs. (model), (mainoptim); Sec. "Definition",
+ * eqs. (reg1), (wts)): recover Z (n_h pixels x L bands) from
+ *     Y_l = S B Z + N_l   (L bands, decimated by d, blurred by the circular kernel b)
+ *     Y_h = Z R + N_h     (L_h bands at full resolution; R is L x L_h)
+ * by minimising
+ *     1/2 ||Y_l - S B Z||^2 + lambda1/2 ||Y_h - Z R||^2
+ *       + lambda * sum_i sum_{tau in W} omega_{i tau} ||P_{i tau}(Z)||_1,
+ *     omega_{i tau} = exp(-||P_{i tau}(Y_h)||_2^2 / h^2),
+ * where P_{i tau} is the difference of the (2K+1)x(2K+1) patches at i and i - tau on the
+ * periodic image domain and W = [-Sw, Sw]^2.  The solver runs the ADMM iteration of
+ * Sec. "Optimization" (eqs. (inv), (Qh_update), (Qm_update), (Qj_main),
+ * (dualvar1_main)-(dualvar3_main)) with E = I (Z coincides with the paper's X).
+ *
+ * Conventions shared by every entry point
+ *   - Images are planar, band-major, row-major float32: element (c, i1, i2) of an image
+ *     with p rows and q columns lives at [(c * p + i1) * q + i2].
+ *   - Device pointers are HIP device allocations on the device that was current when the
+ *     plan was created.  Host pointers are plain host memory.  The caller owns every
+ *     buffer it passes; the library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).
+ *     Work is enqueued asynchronously; completion is observed by synchronising the
+ *     stream.
+ *   - Every function returns an nlpr_status.  No C++ exception crosses the ABI.  On error
+ *     nlpr_last_error() returns a message for the calling thread.
+ *   - Functions are thread-safe for distinct plans.  Calls that share a plan or a
+ *     workspace must not overlap.
+ */
+#ifndef NLPR_H
+#define NLPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nlpr_status {
+  NLPR_OK = 0,
+  NLPR_ERR_INVALID_ARG = 1,        /* null pointer, negative size, host pointer where a device one is needed */
+  NLPR_ERR_UNSUPPORTED_SHAPE = 2,  /* a size outside the limits documented at nlpr_params              */
+  NLPR_ERR_WORKSPACE_TOO_SMALL = 3,/* ws_bytes < nlpr_workspace_size()                                  */
+  NLPR_ERR_HIP = 4,                /* a HIP runtime call or a kernel launch failed                      */
+  NLPR_ERR_NUMERICAL = 5,          /* NaN or Inf found in the result (NLPR_CHECK_FINITE)                */
+  NLPR_ERR_NOT_ENABLED = 6         /* the plan was not created with the option this call needs          */
+} nlpr_status;
+
+/* nlpr_params.flags */
+enum {
+  NLPR_INIT_ZERO = 1u << 0,     /* start every ADMM variable at 0 instead of the default start:
+                                   X0 = nearest-neighbour upsample of Y_l, P1 = B X0, P2 = X0,
+                                   Q = Sigma = Lambda1 = Lambda2 = 0 (the paper names but does not
+                                   give the initial values, Sec. "Optimization")                       */
+  NLPR_STATE_IN = 1u << 1,      /* resume: the workspace holds the state left by an earlier
+                                   nlpr_solve with the same plan; run `iters` more iterations          */
+  NLPR_UNWEIGHTED = 1u << 2,    /* omega = 1 (ablation cases C2 / C4 of the paper)                    */
+  NLPR_LOCAL_WINDOW = 1u << 3,  /* W = {0, +-e1, +-e2}: local pixel differences (ablation C5);
+                                   requires Sw == 1                                                  */
+  NLPR_CHECK_FINITE = 1u << 4,  /* nlpr_solve checks Z for NaN/Inf at the end; this synchronises
+                                   the stream and may return NLPR_ERR_NUMERICAL                      */
+  NLPR_TIMING = 1u << 5         /* record HIP events around every stage; read with nlpr_stage_time   */
+};
+
+/*
+ * Problem size and parameters.  Limits (else NLPR_ERR_UNSUPPORTED_SHAPE):
+ *   p, q       : image rows / columns, each of the form 2^a 3^b, 8 <= p, q <= 4096, q % 4 == 0;
+ *                p % d == 0 and q % d == 0.
+ *   L          : bands of Y_l and Z, 1 <= L <= 4096.
+ *   Lh         : bands of Y_h, 1 <= Lh <= 16.
+ *   d          : decimation factor >= 1; S keeps the pixels (d*m1, d*m2).
+ *   blur_radius: r, the blur kernel is (2r+1) x (2r+1), centred, 0 <= r <= 16.
+ *   K          : patch radius, P = [-K, K]^2, 0 <= K <= 4.
+ *   Sw         : search radius, W = [-Sw, Sw]^2, 0 <= Sw <= 8, Sw < p and Sw < q.
+ *   iters      : ADMM iterations, >= 0.
+ *   lambda     : regulariser weight lambda_2 >= 0.  The soft-threshold of eq. (Qj_main) is
+ *                lambda * omega / rho.
+ *   lambda1    : weight of the Y_h term, > 0.
+ *   rho        : ADMM penalty, > 0.
+ *   h          : width of the guide weights of eq. (wts), > 0 (ignored with NLPR_UNWEIGHTED).
+ */
+typedef struct nlpr_params {
+  int32_t p, q;
+  int32_t L, Lh;
+  int32_t d;
+  int32_t blur_radius;
+  int32_t K, Sw;
+  int32_t iters;
+  uint32_t flags;
+  double lambda;
+  double lambda1;
+  double rho;
+  double h;
+} nlpr_params;
+
+typedef struct nlpr_plan nlpr_plan;
+
+/*
+ * Create a plan on the current HIP device: validate the parameters, upload the blur taps
+ * and R, and precompute the tables the iteration reuses (Sec. "Computational details"):
+ * the inverse Fourier denominator 1/(1 + |b^|^2 + |P| sum_{tau in W} |d^_{tau 0}|^2) of
+ * eq. (inv), computed in FP64 and stored FP32, the FFT twiddles, and the L_h x L_h
+ * matrix G = (rho/lambda1 I + R^T R)^{-1} (FP64) with which the P2-update of
+ * eq. (Qm_update) applies F = (I + lambda1/rho R R^T)^{-1} = I - R G R^T.
+ *   blur_host : host, (2r+1)^2 floats, row-major, tap b(m1, m2) at [(m1 + r)(2r+1) + m2 + r];
+ *               B X (i) = sum_m b(m) X(i - m), circular.
+ *   R_host    : host, L x Lh floats, row-major (R[c][h] at [c * Lh + h]).
+ *   E_host    : must be NULL (E = I); a subspace basis is not supported yet.
+ *   out       : receives the plan.  The plan owns its small device tables only.
+ * Allocates device memory for the tables (a few MB at 512 x 512).
+ */
+int nlpr_plan_create(const nlpr_params* params, const float* blur_host, const float* R_host,
+                     const float* E_host, nlpr_plan** out);
+
+/* Bytes of device workspace nlpr_solve needs for this plan.  The dominant part is the
+ * dual state Sigma' (see nlpr_workspace_region): 4 * Npairs * (2K+1)^2 * L * p * q bytes. */
+int nlpr_workspace_size(const nlpr_plan* plan, size_t* bytes);
+
+/*
+ * Run params.iters ADMM iterations and write Z = X^(iters).
+ *   Yl : device, [L][p/d][q/d]     low-resolution observation.
+ *   Yh : device, [Lh][p][q]        high-resolution guide observation.
+ *   Z  : device, [L][p][q]         output; also used as the X iterate during the solve.
+ *   ws : device workspace of at least nlpr_workspace_size() bytes, 256-byte aligned.  It
+ *        holds the ADMM state on return, so a later call with NLPR_STATE_IN continues the
+ *        iteration (T1 iterations then T2 resumed iterations give the same Z, bit for bit,
+ *        as T1 + T2 iterations at once).
+ * Never allocates device memory.  Asynchronous on `stream` unless NLPR_CHECK_FINITE is set.
+ */
+int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void* ws,
+               size_t ws_bytes, void* stream);
+
+/* Release the plan and its device tables.  NULL is accepted. */
+int nlpr_plan_destroy(nlpr_plan* plan);
+
+/* Static description of a status code. */
+const char* nlpr_status_string(int status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* nlpr_last_error(void);
+
+/*
+ * The half window W+ = {tau in W : tau1 > 0, or tau1 == 0 and tau2 > 0} in the order the
+ * library stores it.  By the antisymmetry omega_{i-tau,-tau} = omega_{i tau} and
+ * D_{-tau,k} X(i - tau) = -D_{tau k} X(i), the duals of -tau are minus the duals of tau
+ * and tau = 0 contributes nothing, so only W+ is stored.
+ *   tau : host, receives 2 * min(cap, Npairs) int32 (tau1, tau2 pairs);   n : receives Npairs.
+ */
+int nlpr_half_window(const nlpr_plan* plan, int32_t* tau, int32_t cap, int32_t* n);
+
+/* Workspace regions (byte offset and size inside ws). */
+typedef enum nlpr_region {
+  NLPR_REGION_SIGMA = 0,  /* Sigma' [Npairs][(2K+1)^2][L][p][q]: the dual of eq. (dualvar3_main) for
+                             tau in W+ (order of nlpr_half_window) and k in P (k1 major, then k2,
+                             each from -K to K), stored source-aligned: Sigma'_{tau k}(j) =
+                             Sigma_{tau k}(j + k).                                                   */
+  NLPR_REGION_MU = 1,     /* mu [Npairs][p][q] = lambda * omega_{i tau} / rho, the thresholds         */
+  NLPR_REGION_C = 2,      /* C [L][p][q], right-hand side of eq. (x_linear_system_main)                */
+  NLPR_REGION_LAMBDA1 = 3,/* Lambda1 [L][p][q]                                                       */
+  NLPR_REGION_LAMBDA2 = 4,/* Lambda2 [L][p][q]                                                       */
+  NLPR_REGION_COUNT = 5
+} nlpr_region;
+int nlpr_workspace_region(const nlpr_plan* plan, int region, size_t* offset, size_t* bytes);
+
+/*
+ * Run one step of the iteration on caller buffers (per-kernel testing).  bufs holds device
+ * pointers in the order listed; `ws` means a workspace of nlpr_workspace_size() bytes used
+ * as scratch.
+ *   NLPR_STAGE_WEIGHTS     {Yh, mu}                   mu = lambda omega / rho for tau in W+ (eq. (wts))
+ *   NLPR_STAGE_XSOLVE      {C, X, ws}                 X = IDFT(DFT(C) / den) per band (eq. (inv))
+ *   NLPR_STAGE_BLUR        {X, BX}                    BX = B X
+ *   NLPR_STAGE_BLUR_T      {Y, BtY}                   BtY = B^T Y
+ *   NLPR_STAGE_PUPDATE     {X, BX, Yl, Yh, Lambda1, Lambda2, W1, W2}
+ *                          P1 by eq. (Qh_update), P2 by eq. (Qm_update), then eqs.
+ *                          (dualvar1_main), (dualvar2_main) update Lambda1, Lambda2 in place;
+ *                          W1 = P1 + Lambda1 and W2 = P2 + Lambda2 with the new duals.
+ *   NLPR_STAGE_SWEEP       {X, mu, Sigma', Creg, ws}  Q-update (eq. (Qj_main)) and Sigma-update
+ *                          (eq. (dualvar3_main)) for every tau in W, k in P, in place on Sigma';
+ *                          Creg = sum_{tau in W} sum_k D_{tau k}^T (Q_{tau k} + Sigma_{tau k}).
+ *   NLPR_STAGE_SWEEP_FIRST same, with Sigma' taken as 0 on input (only written).
+ *   NLPR_STAGE_ASSEMBLE    {W1, W2, Creg, C}          C = B^T W1 + W2 + Creg
+ *   NLPR_STAGE_INIT        {Yl, X0, W1, W2, Lambda1, Lambda2, C}   the initial values and C^(0)
+ */
+enum {
+  NLPR_STAGE_WEIGHTS = 1,
+  NLPR_STAGE_XSOLVE = 2,
+  NLPR_STAGE_BLUR = 3,
+  NLPR_STAGE_BLUR_T = 4,
+  NLPR_STAGE_PUPDATE = 5,
+  NLPR_STAGE_SWEEP = 6,
+  NLPR_STAGE_SWEEP_FIRST = 7,
+  NLPR_STAGE_ASSEMBLE = 8,
+  NLPR_STAGE_INIT = 9,
+  NLPR_STAGE_COUNT = 10
+};
+int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbufs, void* stream);
+
+/*
+ * Accumulated device time of one stage over the solves since the last reset, from the HIP
+ * events recorded on the solve's stream (plans created with NLPR_TIMING only).
+ * Synchronises on the recorded events.  ms_total: sum of launch durations in ms;
+ * launches: number of timed launches.  reset != 0 clears the totals after reading.
+ */
+int nlpr_stage_time(nlpr_plan* plan, int stage, double* ms_total, int64_t* launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLPR_H */

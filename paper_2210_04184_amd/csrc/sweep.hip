@@ -1,0 +1,262 @@
+// The regulariser sweep: the Q-update (eq. (Qj_main)), the Sigma-update (eq. (dualvar3_main))
+// and the regulariser part of the next right-hand side (after eq. (x_linear_system_main)),
+// fused into one pass over the dual state.  This is where nearly all HBM traffic of an
+// iteration goes: every Sigma value is read once and written once.
+//
+// Reduced form used here (all identities are exact):
+//  * Q-elimination.  With V = D_{tau k} X - Sigma_{tau k}, the soft-threshold gives
+//    Q+ = V - clip(V, +-mu) and then Sigma+ = Sigma - (D X - Q+) = -clip(V, +-mu), so Q
+//    need not be stored and Q+ + Sigma+ = V - 2 clip(V, +-mu).
+//  * Half window.  omega_{i-tau,-tau} = omega_{i tau} and D_{-tau,k} X(i - tau) = -D_{tau k} X(i),
+//    so from Sigma = 0 the duals of -tau stay minus those of tau (shifted by tau) and the
+//    adjoint terms of tau and -tau are equal; tau = 0 contributes nothing.  Only the half
+//    window W+ is visited and its adjoint terms count twice.
+//  * Source alignment.  D_{tau k} X(i) = g_tau(i - k) with g_tau = X - X(. - tau) (the shift
+//    property of the difference filters).  Storing Sigma'_{tau k}(j) = Sigma_{tau k}(j + k)
+//    makes every update at j read g_tau(j) and the threshold mu(j + k, tau), and turns
+//    sum_k D_{tau k}^T U_{tau k} into A_tau(j) - A_tau(j + tau) with A_tau = sum_k U'_{tau k}.
+// So, per band and pixel j:   Creg(j) = 2 sum_{tau in W+} [A_tau(j) - A_tau(j + tau)].
+//
+// Work decomposition.  A workgroup owns a tile of `rows` full image rows of one band and
+// loops over tau in W+.  Per tau it stages the thresholds mu(., tau) of the tile plus a K
+// halo in LDS, forms g_tau from the X tile in LDS, then streams the (2K+1)^2 planes of
+// Sigma' for its tile with 16-byte loads and stores, issuing all loads of one patch row
+// before any compute.  A_tau is added to the thread's own pixels in registers and
+// subtracted at j - tau in an LDS accumulator that spans the tile plus `halo` rows above
+// it; since j -> j - tau is one-to-one, the LDS updates of one tau never collide.  The rows
+// above the tile go to a small halo buffer that the right-hand-side assembly folds in, so
+// the result is deterministic (no atomics).
+#include "nlpr_internal.h"
+
+namespace nlpr {
+namespace {
+
+constexpr int PADW = 4;  // mu rows in LDS are padded by one float4 on each side (K <= 4)
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float* p) {
+  const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_nt(float* p, float4 v) {
+  v4f w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p));
+}
+__device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v, -m), m); }
+
+template <int K, int ITEMS, int NT, bool FIRST>
+__global__ void __launch_bounds__(NT)
+sweep_kernel(const float* __restrict__ X, const float* __restrict__ mu, float* __restrict__ sig,
+             float* __restrict__ creg, float* __restrict__ halo, const int2* __restrict__ taus,
+             int p, int q, int L, int npairs, int R, int ntiles, int H) {
+  constexpr int KW = 2 * K + 1;
+  constexpr int NP = KW * KW;
+  extern __shared__ float4 lds4[];
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int q4 = q >> 2;
+  const int ms = q + 2 * PADW;          // row stride of the mu tile
+  float* Ms = lds;                      // (R + 2K) x ms       mu(., tau), rows r0-K .. r0+R+K-1
+  float* Xs = Ms + (R + 2 * K) * ms;    // (R + H) x q         X rows r0-H .. r0+R-1
+  float* Cs = Xs + (R + H) * q;         // (R + H) x q         adjoint accumulator
+
+  const int tile = blockIdx.x / L;
+  const int c = blockIdx.x - tile * L;
+  const int r0 = tile * R;
+  const int rows = min(R, p - r0);
+  const size_t plane = (size_t)p * q;
+  const float* Xc = X + (size_t)c * plane;
+
+  for (int e = threadIdx.x; e < (R + H) * q4; e += NT) {
+    const int rr = e / q4, c4 = e - rr * q4;
+    int gr = (r0 - H + rr) % p;
+    if (gr < 0) gr += p;
+    reinterpret_cast<float4*>(Xs)[e] = reinterpret_cast<const float4*>(Xc + (size_t)gr * q)[c4];
+    reinterpret_cast<float4*>(Cs)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+
+  int row[ITEMS], col[ITEMS];
+  bool ok[ITEMS];
+  float4 xv[ITEMS], cp[ITEMS];
+#pragma unroll
+  for (int m = 0; m < ITEMS; ++m) {
+    const int it = threadIdx.x + NT * m;
+    row[m] = it / q4;
+    col[m] = (it - row[m] * q4) * 4;
+    ok[m] = row[m] < rows;
+    xv[m] = ok[m] ? *reinterpret_cast<const float4*>(Xs + (row[m] + H) * q + col[m])
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    cp[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+
+  const size_t kstride = (size_t)L * plane;       // between patch offsets
+  const size_t tstride = (size_t)NP * kstride;    // between shifts
+  float* sig_tile = sig + (size_t)c * plane + (size_t)r0 * q;
+
+  for (int n = 0; n < npairs; ++n) {
+    const int2 t = taus[n];
+    __syncthreads();  // the previous shift's reads of Ms and updates of Cs are done
+    {
+      const float* mun = mu + (size_t)n * plane;
+      const int ms4 = ms >> 2;
+      for (int e = threadIdx.x; e < (R + 2 * K) * ms4; e += NT) {
+        const int rr = e / ms4, c4 = e - rr * ms4 - 1;  // c4 in [-1, q4]
+        int gr = (r0 - K + rr) % p;
+        if (gr < 0) gr += p;
+        const int gc4 = c4 < 0 ? c4 + q4 : (c4 >= q4 ? c4 - q4 : c4);
+        reinterpret_cast<float4*>(Ms)[e] =
+            reinterpret_cast<const float4*>(mun + (size_t)gr * q)[gc4];
+      }
+    }
+    __syncthreads();
+
+    float4 g[ITEMS], A[ITEMS];
+#pragma unroll
+    for (int m = 0; m < ITEMS; ++m) {
+      const float* xr = Xs + (row[m] + H - t.x) * q;
+      float sh[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int cc = col[m] + e - t.y;
+        cc = cc < 0 ? cc + q : (cc >= q ? cc - q : cc);
+        sh[e] = xr[cc];
+      }
+      g[m] = make_float4(xv[m].x - sh[0], xv[m].y - sh[1], xv[m].z - sh[2], xv[m].w - sh[3]);
+      A[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+
+    float* sig_n = sig_tile + (size_t)n * tstride;
+#pragma unroll
+    for (int k1 = -K; k1 <= K; ++k1) {
+      // thresholds mu(j + k, tau) for k2 in [-K, K]: columns col-4 .. col+7 of row + k1
+      float mw[ITEMS][12];
+#pragma unroll
+      for (int m = 0; m < ITEMS; ++m) {
+        const float4* mr = reinterpret_cast<const float4*>(Ms + (row[m] + K + k1) * ms + col[m]);
+        const float4 a = mr[0], b = mr[1], d = mr[2];  // padded: column index col - 4 + 4*s
+        mw[m][0] = a.x; mw[m][1] = a.y; mw[m][2] = a.z; mw[m][3] = a.w;
+        mw[m][4] = b.x; mw[m][5] = b.y; mw[m][6] = b.z; mw[m][7] = b.w;
+        mw[m][8] = d.x; mw[m][9] = d.y; mw[m][10] = d.z; mw[m][11] = d.w;
+      }
+      float4 s[KW][ITEMS];
+      if (!FIRST) {
+#pragma unroll
+        for (int k2 = 0; k2 < KW; ++k2) {
+          const float* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
+#pragma unroll
+          for (int m = 0; m < ITEMS; ++m)
+            s[k2][m] = ok[m] ? ld_nt(base + (size_t)row[m] * q + col[m])
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < KW; ++k2) {
+        float* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
+#pragma unroll
+        for (int m = 0; m < ITEMS; ++m) {
+          if (!ok[m]) continue;
+          const float4 sv = FIRST ? make_float4(0.f, 0.f, 0.f, 0.f) : s[k2][m];
+          const int o = 4 + (k2 - K);  // window index of column col + (k2 - K)
+          float4 v, cl;
+          v.x = g[m].x - sv.x; cl.x = clampf(v.x, mw[m][o + 0]);
+          v.y = g[m].y - sv.y; cl.y = clampf(v.y, mw[m][o + 1]);
+          v.z = g[m].z - sv.z; cl.z = clampf(v.z, mw[m][o + 2]);
+          v.w = g[m].w - sv.w; cl.w = clampf(v.w, mw[m][o + 3]);
+          A[m].x += v.x - 2.f * cl.x;
+          A[m].y += v.y - 2.f * cl.y;
+          A[m].z += v.z - 2.f * cl.z;
+          A[m].w += v.w - 2.f * cl.w;
+          st_nt(base + (size_t)row[m] * q + col[m], make_float4(-cl.x, -cl.y, -cl.z, -cl.w));
+        }
+      }
+    }
+
+#pragma unroll
+    for (int m = 0; m < ITEMS; ++m) {
+      if (!ok[m]) continue;
+      cp[m].x += A[m].x; cp[m].y += A[m].y; cp[m].z += A[m].z; cp[m].w += A[m].w;
+      float* cr = Cs + (row[m] + H - t.x) * q;
+      const float a4[4] = {A[m].x, A[m].y, A[m].z, A[m].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int cc = col[m] + e - t.y;
+        cc = cc < 0 ? cc + q : (cc >= q ? cc - q : cc);
+        cr[cc] -= a4[e];
+      }
+    }
+  }
+  __syncthreads();
+
+  float* cregc = creg + (size_t)c * plane + (size_t)r0 * q;
+#pragma unroll
+  for (int m = 0; m < ITEMS; ++m) {
+    if (!ok[m]) continue;
+    const float4 acc = *reinterpret_cast<const float4*>(Cs + (row[m] + H) * q + col[m]);
+    *reinterpret_cast<float4*>(cregc + (size_t)row[m] * q + col[m]) =
+        make_float4(2.f * (cp[m].x + acc.x), 2.f * (cp[m].y + acc.y), 2.f * (cp[m].z + acc.z),
+                    2.f * (cp[m].w + acc.w));
+  }
+  if (H > 0) {
+    float* hb = halo + ((size_t)c * ntiles + tile) * H * q;
+    for (int e = threadIdx.x; e < H * q4; e += NT) {
+      const float4 v = reinterpret_cast<const float4*>(Cs)[e];
+      reinterpret_cast<float4*>(hb)[e] = make_float4(2.f * v.x, 2.f * v.y, 2.f * v.z, 2.f * v.w);
+    }
+  }
+}
+
+constexpr int kThreads = 256;
+constexpr int kItems = 4;
+
+template <int K, bool FIRST>
+int launch_k(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
+             float* halo, hipStream_t s) {
+  const SweepShape& sh = P.sweep;
+  auto kern = sweep_kernel<K, kItems, kThreads, FIRST>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  dim3 grid(sh.ntiles * P.prm.L);
+  hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh.lds, s, X, mu, sigma, creg, halo, P.d_taus,
+                     P.prm.p, P.prm.q, P.prm.L, P.npairs, sh.rows, sh.ntiles, sh.halo);
+  NLPR_LAUNCH_CHECK("sweep_kernel");
+  return NLPR_OK;
+}
+
+}  // namespace
+
+SweepShape choose_sweep_shape(int p, int q, int K, int halo) {
+  SweepShape sh{};
+  sh.threads = kThreads;
+  sh.items = kItems;
+  const int per_block = kThreads * kItems * 4;  // pixels per workgroup
+  sh.rows = std::max(1, std::min(p, per_block / q));
+  sh.ntiles = ceil_div(p, sh.rows);
+  sh.halo = halo;
+  sh.lds = (size_t)((sh.rows + 2 * K) * (q + 2 * PADW) + 2 * (sh.rows + halo) * q) * sizeof(float);
+  return sh;
+}
+
+int launch_sweep(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
+                 float* halo, bool first, hipStream_t s) {
+  switch (P.prm.K) {
+#define NLPR_SW(KK)                                                                   \
+  case KK:                                                                            \
+    return first ? launch_k<KK, true>(P, X, mu, sigma, creg, halo, s)                 \
+                 : launch_k<KK, false>(P, X, mu, sigma, creg, halo, s);
+    NLPR_SW(0)
+    NLPR_SW(1)
+    NLPR_SW(2)
+    NLPR_SW(3)
+    NLPR_SW(4)
+#undef NLPR_SW
+    default:
+      set_error("sweep: unsupported patch radius");
+      return NLPR_ERR_UNSUPPORTED_SHAPE;
+  }
+}
+
+}  // namespace nlpr

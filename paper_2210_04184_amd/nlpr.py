@@ -1,0 +1,226 @@
+"""Python binding of libnlpr (ctypes).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  PyTorch
+supplies device memory and the stream.  The binding fails loudly when the library is not
+built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlpr.so")
+
+# status codes and flags (include/nlpr.h)
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_UNSUPPORTED_SHAPE = 2
+ERR_WORKSPACE_TOO_SMALL = 3
+ERR_HIP = 4
+ERR_NUMERICAL = 5
+ERR_NOT_ENABLED = 6
+
+INIT_ZERO = 1 << 0
+STATE_IN = 1 << 1
+UNWEIGHTED = 1 << 2
+LOCAL_WINDOW = 1 << 3
+CHECK_FINITE = 1 << 4
+TIMING = 1 << 5
+
+STAGE_WEIGHTS = 1
+STAGE_XSOLVE = 2
+STAGE_BLUR = 3
+STAGE_BLUR_T = 4
+STAGE_PUPDATE = 5
+STAGE_SWEEP = 6
+STAGE_SWEEP_FIRST = 7
+STAGE_ASSEMBLE = 8
+STAGE_INIT = 9
+STAGE_NAMES = {STAGE_WEIGHTS: "weights", STAGE_XSOLVE: "xsolve", STAGE_BLUR: "blur",
+               STAGE_BLUR_T: "blur_t", STAGE_PUPDATE: "pupdate", STAGE_SWEEP: "sweep",
+               STAGE_SWEEP_FIRST: "sweep_first", STAGE_ASSEMBLE: "assemble", STAGE_INIT: "init"}
+
+REGION_SIGMA = 0
+REGION_MU = 1
+REGION_C = 2
+REGION_LAMBDA1 = 3
+REGION_LAMBDA2 = 4
+
+EXPORTED = ["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlpr_plan_destroy",
+            "nlpr_status_string", "nlpr_last_error", "nlpr_half_window",
+            "nlpr_workspace_region", "nlpr_debug_stage", "nlpr_stage_time"]
+
+
+class NlprError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"nlpr status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("Lh", ctypes.c_int32), ("d", ctypes.c_int32), ("blur_radius", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("Sw", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("lam", ctypes.c_double), ("lam1", ctypes.c_double),
+                ("rho", ctypes.c_double), ("h", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libnlpr.so (once).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libnlpr.so not found at {path}; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.nlpr_plan_create.argtypes = [ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(vp)]
+    lib.nlpr_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.nlpr_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.nlpr_plan_destroy.argtypes = [vp]
+    lib.nlpr_status_string.argtypes = [ctypes.c_int]
+    lib.nlpr_status_string.restype = ctypes.c_char_p
+    lib.nlpr_last_error.argtypes = []
+    lib.nlpr_last_error.restype = ctypes.c_char_p
+    lib.nlpr_half_window.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+    lib.nlpr_workspace_region.argtypes = [vp, ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.nlpr_debug_stage.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), i32, vp]
+    lib.nlpr_stage_time.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    for name in EXPORTED:
+        if name not in ("nlpr_status_string", "nlpr_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load()
+        raise NlprError(rc, f"{lib.nlpr_status_string(rc).decode()}: {lib.nlpr_last_error().decode()}")
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Plan:
+    """A solver plan: problem sizes, parameters and the precomputed device tables."""
+
+    def __init__(self, p: int, q: int, L: int, Lh: int, d: int, blur: np.ndarray,
+                 R: np.ndarray, K: int, Sw: int, iters: int, lam: float, rho: float, h: float,
+                 lam1: float = 1.0, flags: int = 0):
+        lib = load()
+        blur = np.ascontiguousarray(blur, dtype=np.float32)
+        R = np.ascontiguousarray(R, dtype=np.float32).reshape(L, Lh)
+        r = blur.shape[0] // 2
+        if blur.shape != (2 * r + 1, 2 * r + 1):
+            raise ValueError("blur must be (2r+1) x (2r+1)")
+        self.params = Params(p, q, L, Lh, d, r, K, Sw, iters, flags, lam, lam1, rho, h)
+        self.shape = (L, p, q)
+        self._blur, self._R = blur, R
+        handle = ctypes.c_void_p()
+        _check(lib.nlpr_plan_create(ctypes.byref(self.params), blur.ctypes.data_as(ctypes.c_void_p),
+                                    R.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(handle)))
+        self.handle = handle
+
+    @classmethod
+    def from_scene(cls, scene, flags: int = 0, **over) -> "Plan":
+        s = scene.spec
+        kw = dict(p=s.p, q=s.q, L=s.L, Lh=scene.R.shape[1], d=s.d, blur=scene.blur, R=scene.R,
+                  K=s.K, Sw=s.Sw, iters=s.iters, lam=s.lam, rho=s.rho, h=scene.h, lam1=s.lam1,
+                  flags=flags)
+        kw.update(over)
+        return cls(**kw)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().nlpr_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(load().nlpr_workspace_size(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def half_window(self) -> Sequence[Tuple[int, int]]:
+        n = ctypes.c_int32()
+        _check(load().nlpr_half_window(self.handle, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_int32 * (2 * max(n.value, 1)))()
+        _check(load().nlpr_half_window(self.handle, buf, n.value, ctypes.byref(n)))
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
+
+    def region(self, which: int) -> Tuple[int, int]:
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().nlpr_workspace_region(self.handle, which, ctypes.byref(off), ctypes.byref(nb)))
+        return off.value, nb.value
+
+    def region_view(self, ws, which: int):
+        """A float32 view of one workspace region (ws is a uint8 device tensor)."""
+        off, nb = self.region(which)
+        return ws[off:off + nb].view(dtype=__import__("torch").float32)
+
+    def alloc_workspace(self):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+
+    def solve(self, Yl, Yh, Z=None, ws=None, stream=None):
+        import torch
+        if Z is None:
+            Z = torch.empty(self.shape, dtype=torch.float32, device=Yl.device)
+        if ws is None:
+            ws = self.alloc_workspace()
+        _check(load().nlpr_solve(self.handle, _ptr(Yl), _ptr(Yh), _ptr(Z), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream_handle(stream)))
+        return Z, ws
+
+    def stage(self, stage: int, bufs, stream=None):
+        arr = (ctypes.c_void_p * len(bufs))(*[_ptr(b) for b in bufs])
+        _check(load().nlpr_debug_stage(self.handle, stage, arr, len(bufs), _stream_handle(stream)))
+
+    def stage_time(self, stage: int, reset: bool = False) -> Tuple[float, int]:
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(load().nlpr_stage_time(self.handle, stage, ctypes.byref(ms), ctypes.byref(n),
+                                      1 if reset else 0))
+        return ms.value, n.value
+
+
+def fuse(Yl, Yh, blur, R, d: int, lam: float, K: int, Sw: int, rho: float, iters: int, h: float,
+         lam1: float = 1.0, flags: int = 0, stream=None):
+    """Fuse Y_l [L][p/d][q/d] and Y_h [Lh][p][q] (float32 device tensors); returns Z [L][p][q]."""
+    L, pd, qd = Yl.shape
+    Lh, p, q = Yh.shape
+    plan = Plan(p, q, L, Lh, d, blur, R, K, Sw, iters, lam, rho, h, lam1, flags)
+    try:
+        Z, _ = plan.solve(Yl.contiguous(), Yh.contiguous(), stream=stream)
+    finally:
+        plan.close()
+    return Z

@@ -1,0 +1,303 @@
+"""GPU parity: every step of the HIP path, and the whole solve, against the FP64 oracle.
+
+Inputs are the seeded synthetic scenes (rounded once to float32); the oracle reads the same
+float32 values as float64.  Shapes cover radix 2/3/4/8 transforms, several sweep tiles with
+a ragged last tile, a tile shorter than the halo, odd band counts and 1..4 guide bands.
+
+Tolerances.  The spec bar for the solve is a relative RMSE of 1e-4 on Z.  Single
+steps are held to what FP32 arithmetic gives: a few ulps times the depth of the sums.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import nlpr_oracle as o
+from paper_2210_04184_amd import nlpr
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {
+    # name: (p, q, L, Lh, d, blur_radius, K, Sw)
+    "c1": (64, 64, 8, 1, 4, 3, 1, 2),
+    "ragged": (72, 96, 5, 2, 4, 2, 2, 3),
+    "radix3": (48, 36, 3, 3, 2, 1, 1, 1),
+    "wide": (64, 512, 2, 4, 4, 4, 1, 3),
+    "thin": (8, 2048, 2, 1, 2, 1, 0, 3),
+}
+
+
+def scene_for(name, iters=10, seed=5, **kw):
+    p, q, L, Lh, d, r, K, Sw = SHAPES[name]
+    if name == "c1":
+        spec = synth.config("c1", iters=iters, **kw)
+    else:
+        spec = synth.small_spec(p=p, q=q, L=L, Lh=Lh, d=d, blur_radius=r, K=K, Sw=Sw,
+                                iters=iters, seed=seed, tile=8, **kw)
+    return synth.make_scene(spec)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_rmse(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def problem(sc, **kw):
+    return o.Problem.from_scene(sc, **kw)
+
+
+def half_window_index(plan, pr):
+    W = pr.window
+    return [W.index(t) for t in plan.half_window()]
+
+
+# ------------------------------------------------------------------------------ stages
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_weights_stage(name):
+    sc = scene_for(name)
+    plan = nlpr.Plan.from_scene(sc)
+    pr = problem(sc)
+    idx = half_window_index(plan, pr)
+    mu = torch.empty((len(idx), sc.spec.p, sc.spec.q), device="cuda")
+    plan.stage(nlpr.STAGE_WEIGHTS, [dev(sc.Yh), mu])
+    om = o.weights(sc.Yh.astype(np.float64), pr.window, pr.K, pr.h)
+    want = pr.lam * om[idx] / pr.rho
+    got = host(mu)
+    np.testing.assert_allclose(got, want, rtol=2e-5, atol=1e-12 * want.max())
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_xsolve_stage(name):
+    sc = scene_for(name)
+    plan = nlpr.Plan.from_scene(sc)
+    pr = problem(sc)
+    rng = np.random.default_rng(1)
+    C = f32(rng.standard_normal((sc.spec.L, sc.spec.p, sc.spec.q)) * 3.0)
+    X = torch.empty_like(dev(C))
+    ws = plan.alloc_workspace()
+    plan.stage(nlpr.STAGE_XSOLVE, [dev(C), X, ws])
+    want = o.x_update(C, o.denominator(pr.p, pr.q, pr.b, pr.window, pr.K))
+    assert rel_rmse(host(X), want) < 2e-6
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_blur_stages(name):
+    sc = scene_for(name)
+    plan = nlpr.Plan.from_scene(sc)
+    pr = problem(sc)
+    X = f32(np.random.default_rng(2).uniform(-1, 1, (sc.spec.L, sc.spec.p, sc.spec.q)))
+    out = torch.empty_like(dev(X))
+    plan.stage(nlpr.STAGE_BLUR, [dev(X), out])
+    assert rel_rmse(host(out), o.blur(X, pr.b)) < 1e-6
+    plan.stage(nlpr.STAGE_BLUR_T, [dev(X), out])
+    assert rel_rmse(host(out), o.blur_T(X, pr.b)) < 1e-6
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_pupdate_stage(name):
+    sc = scene_for(name)
+    plan = nlpr.Plan.from_scene(sc)
+    pr = problem(sc)
+    rng = np.random.default_rng(3)
+    shp = (sc.spec.L, sc.spec.p, sc.spec.q)
+    X, BX, L1, L2 = (f32(rng.uniform(0, 1, shp)) for _ in range(4))
+    L1 *= 0.1
+    L2 *= 0.1
+    Yl, Yh = f32(sc.Yl), f32(sc.Yh)
+    tX, tBX, tL1, tL2 = dev(X), dev(BX), dev(L1), dev(L2)
+    W1, W2 = torch.empty_like(tX), torch.empty_like(tX)
+    plan.stage(nlpr.STAGE_PUPDATE, [tX, tBX, dev(Yl), dev(Yh), tL1, tL2, W1, W2])
+    P1 = o.p1_update(BX, L1, Yl, pr)
+    P2 = o.p2_update(X, L2, Yh, pr)
+    L1n = L1 - (BX - P1)
+    L2n = L2 - (X - P2)
+    for got, want in ((tL1, L1n), (tL2, L2n), (W1, P1 + L1n), (W2, P2 + L2n)):
+        g = host(got)
+        scale = max(np.abs(want).max(), 1.0)
+        assert np.abs(g - want).max() <= 5e-6 * scale * max(1.0, pr.lam1 / pr.rho) ** 0.5
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_sweep_stage_two_steps(name):
+    """Two successive sweeps (first from Sigma = 0, then reading Sigma') against the
+    oracle's literal Q/Sigma updates over the full window."""
+    sc = scene_for(name)
+    plan = nlpr.Plan.from_scene(sc)
+    pr = problem(sc)
+    W, P = pr.window, pr.patch
+    idx = half_window_index(plan, pr)
+    rng = np.random.default_rng(4)
+    shp = (sc.spec.L, sc.spec.p, sc.spec.q)
+    om = o.weights(f32(sc.Yh), W, pr.K, pr.h)
+    mu = pr.lam * om / pr.rho
+    tmu = torch.empty((len(idx),) + shp[1:], device="cuda")
+    plan.stage(nlpr.STAGE_WEIGHTS, [dev(sc.Yh), tmu])
+    ws = plan.alloc_workspace()
+    sig = torch.full((len(idx), len(P)) + shp, float("nan"), device="cuda")  # never read when first
+    creg = torch.empty(shp, device="cuda")
+    Sig = np.zeros((len(W), len(P)) + shp)
+    for step in range(2):
+        X = f32(rng.uniform(0, 1, shp) * 0.3)
+        plan.stage(nlpr.STAGE_SWEEP_FIRST if step == 0 else nlpr.STAGE_SWEEP,
+                   [dev(X), tmu, sig, creg, ws])
+        Cw = np.zeros(shp)
+        newSig = np.empty_like(Sig)
+        for a, t in enumerate(W):
+            for m, k in enumerate(P):
+                DX = o.D(X, t, k)
+                Q = o.soft_threshold(DX - Sig[a, m], mu[a][None])
+                newSig[a, m] = Sig[a, m] - (DX - Q)
+                Cw += o.D_T(Q + newSig[a, m], t, k)
+        Sig = newSig
+        gs = host(sig)
+        scale = mu.max()
+        for n, a in enumerate(idx):
+            for m, k in enumerate(P):
+                want = o.shift(Sig[a, m], (-k[0], -k[1]))      # Sigma'(j) = Sigma(j + k)
+                assert np.abs(gs[n, m] - want).max() <= 1e-6 * max(scale, 1e-3), (step, n, m)
+        assert rel_rmse(host(creg), Cw) < 2e-5, step
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_assemble_and_init_stages(name):
+    sc = scene_for(name)
+    plan = nlpr.Plan.from_scene(sc)
+    pr = problem(sc)
+    rng = np.random.default_rng(6)
+    shp = (sc.spec.L, sc.spec.p, sc.spec.q)
+    W1, W2, Cr = (f32(rng.standard_normal(shp)) for _ in range(3))
+    C = torch.empty(shp, device="cuda")
+    plan.stage(nlpr.STAGE_ASSEMBLE, [dev(W1), dev(W2), dev(Cr), C])
+    assert rel_rmse(host(C), o.blur_T(W1, pr.b) + W2 + Cr) < 1e-6
+    X0, tW1, tW2, tL1, tL2 = (torch.empty(shp, device="cuda") for _ in range(5))
+    plan.stage(nlpr.STAGE_INIT, [dev(sc.Yl), X0, tW1, tW2, tL1, tL2, C])
+    Xo, st = o.initial_state(f32(sc.Yl), pr)
+    np.testing.assert_array_equal(host(X0), Xo)
+    assert rel_rmse(host(tW1), st.P1 + st.Lam1) < 1e-6
+    np.testing.assert_array_equal(host(tW2), st.P2 + st.Lam2)
+    assert not host(tL1).any() and not host(tL2).any()
+    assert rel_rmse(host(C), o.rhs(st, pr)) < 1e-6
+
+
+# ----------------------------------------------------------------------------- solves
+def solve_gpu(sc, flags=0, **over):
+    plan = nlpr.Plan.from_scene(sc, flags=flags, **over)
+    Z, ws = plan.solve(dev(sc.Yl), dev(sc.Yh))
+    return host(Z), plan, ws
+
+
+def solve_oracle(sc, init="upsample", **kw):
+    pr = problem(sc, **kw)
+    return o.solve(f32(sc.Yl), f32(sc.Yh), pr, sc.spec.iters, init=init).X
+
+
+def test_solve_c1_matches_oracle():
+    """The small pansharpening workload: 64x64x8, 7x7 blur, d = 4, patch 3x3, window 5x5,
+    50 iterations."""
+    sc = synth.make_scene(synth.config("c1"))
+    z, _, _ = solve_gpu(sc)
+    ref = solve_oracle(sc)
+    assert rel_rmse(z, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["ragged", "radix3", "wide", "thin"])
+def test_solve_shapes_match_oracle(name):
+    sc = scene_for(name, iters=12)
+    z, _, _ = solve_gpu(sc)
+    assert rel_rmse(z, solve_oracle(sc)) <= 1e-4
+
+
+@pytest.mark.parametrize("variant", ["unweighted", "local", "pixel", "zero_init", "no_reg",
+                                     "lambda0", "no_window"])
+def test_solve_variants_match_oracle(variant):
+    sc = scene_for("ragged", iters=10)
+    flags, over, okw, init = 0, {}, {}, "upsample"
+    if variant == "unweighted":          # ablation C2: omega = 1
+        flags, okw = nlpr.UNWEIGHTED, dict(unweighted=True)
+    elif variant == "local":             # ablation C5: 4-neighbour window
+        flags, over, okw = nlpr.LOCAL_WINDOW, dict(Sw=1), dict(local=True, S=1)
+    elif variant == "pixel":             # ablation C3: pixels instead of patches
+        over, okw = dict(K=0), dict(K=0)
+    elif variant == "zero_init":
+        flags, init = nlpr.INIT_ZERO, "zero"
+    elif variant == "no_reg":            # lambda > 0 but the window holds only tau = 0
+        over, okw = dict(Sw=0), dict(S=0)
+    elif variant == "lambda0":
+        over, okw = dict(lam=0.0), dict(lam=0.0)
+    elif variant == "no_window":
+        over, okw = dict(Sw=1, K=0), dict(S=1, K=0)
+    z, _, _ = solve_gpu(sc, flags=flags, **over)
+    assert rel_rmse(z, solve_oracle(sc, init=init, **okw)) <= 1e-4
+
+
+def test_solve_is_deterministic_and_resumable():
+    sc = scene_for("ragged", iters=9)
+    z1, _, _ = solve_gpu(sc)
+    z2, _, _ = solve_gpu(sc)
+    np.testing.assert_array_equal(z1, z2)
+    Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+    p4 = nlpr.Plan.from_scene(sc, iters=4)
+    Z, ws = p4.solve(Yl, Yh)
+    p5 = nlpr.Plan.from_scene(sc, iters=5, flags=nlpr.STATE_IN)
+    Z, ws = p5.solve(Yl, Yh, Z=Z, ws=ws)
+    np.testing.assert_array_equal(host(Z), z1)
+
+
+def test_sigma_stays_within_thresholds_and_shrink_branch_is_exercised():
+    """|Sigma| <= mu after every update (Sigma+ = -clip(V, +-mu)), and at the end a fair
+    share of the entries sits on the threshold (|V| > mu, Q != 0): both branches of the
+    soft-threshold are in use."""
+    sc = synth.make_scene(synth.config("c1"))
+    z, plan, ws = solve_gpu(sc)
+    npairs = len(plan.half_window())
+    sig = host(plan.region_view(ws, nlpr.REGION_SIGMA)).reshape(npairs, -1, *z.shape)
+    mu = host(plan.region_view(ws, nlpr.REGION_MU)).reshape(npairs, *z.shape[1:])
+    on_bound = []
+    for m, k in enumerate(o.patch_offsets(sc.spec.K)):
+        bound = np.stack([o.shift(mu[n], (-k[0], -k[1])) for n in range(npairs)])[:, None]
+        assert np.all(np.abs(sig[:, m]) <= bound * (1 + 1e-6))
+        on_bound.append(np.abs(np.abs(sig[:, m]) - bound) <= 1e-7 * bound)
+    frac = float(np.mean(on_bound))
+    assert 0.05 <= frac <= 0.95, frac
+
+
+def test_host_checks_on_device_buffers():
+    sc = scene_for("radix3")
+    plan = nlpr.Plan.from_scene(sc)
+    Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+    small = torch.empty(plan.workspace_bytes - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(nlpr.NlprError) as e:
+        plan.solve(Yl, Yh, ws=small)
+    assert e.value.status == nlpr.ERR_WORKSPACE_TOO_SMALL
+    lib = nlpr.load()
+    hostbuf = np.zeros(16, np.float32)
+    ws = plan.alloc_workspace()
+    Z = torch.empty((sc.spec.L, sc.spec.p, sc.spec.q), device="cuda")
+    import ctypes
+    rc = lib.nlpr_solve(plan.handle, hostbuf.ctypes.data_as(ctypes.c_void_p), Yh.data_ptr(),
+                        Z.data_ptr(), ws.data_ptr(), ws.numel(), None)
+    assert rc == nlpr.ERR_INVALID_ARG
+
+
+def test_check_finite_reports_nan_input():
+    sc = scene_for("radix3", iters=3)
+    plan = nlpr.Plan.from_scene(sc, flags=nlpr.CHECK_FINITE)
+    Yl = sc.Yl.copy()
+    Yl[0, 0, 0] = np.nan
+    with pytest.raises(nlpr.NlprError) as e:
+        plan.solve(dev(Yl), dev(sc.Yh))
+    assert e.value.status == nlpr.ERR_NUMERICAL
+    Z, _ = plan.solve(dev(sc.Yl), dev(sc.Yh))
+    assert np.isfinite(host(Z)).all()
