@@ -1,0 +1,169 @@
+"""Throughput of the NLPR fusion ADMM on one MI355X.
+
+One step = one whole solve of the hot path on one synthetic scene already resident in HBM:
+guide weights, initial values and `iters` ADMM iterations (X-update by FFT, blur, P1/P2/dual
+update, the fused Q/Sigma sweep, right-hand-side assembly).  The default workload is the
+512 x 512 x 128-band HS+MS scene (4-band MS guide, 9x9 blur, d = 4, patch 5x5, window 11x11,
+100 iterations).
+
+Prints one JSON line: pixel*band*iteration/s over the timed steps, the roofline of the
+dominant kernel (the sweep, timed with HIP events on the solve's stream inside the timed
+region) and the FP64 oracle's throughput on a bounded sample (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_name(spec) -> str:
+    kind = {"c1": "pansharpening", "c2": "hs+pan", "c3": "hs+ms"}.get(spec.name, spec.name)
+    return (f"{kind} {spec.p}x{spec.q}x{spec.L}, Lh={spec.Lh}, d={spec.d}, "
+            f"blur {2 * spec.blur_radius + 1}x{2 * spec.blur_radius + 1}, patch "
+            f"{2 * spec.K + 1}x{2 * spec.K + 1}, window {2 * spec.Sw + 1}x{2 * spec.Sw + 1}, "
+            f"{spec.iters} iterations")
+
+
+def sweep_bytes_per_launch(spec, npairs: int) -> int:
+    """Algorithmic HBM bytes of one sweep launch: Sigma' read + write (8 B per pair, patch
+    offset, pixel and band), X read and C write (8 B per pixel and band), thresholds mu read
+    once (4 B per pair and pixel)."""
+    npatch = (2 * spec.K + 1) ** 2
+    n = spec.p * spec.q
+    return (8 * npairs * npatch + 8) * n * spec.L + 4 * npairs * n
+
+
+def cpu_baseline(seconds_target: float = 15.0):
+    """The FP64 oracle on a sample of the same workload: a 64 x 64 x 16-band scene from the
+    same generator with the same guide bands, blur, decimation, patch and window."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import nlpr_oracle as o
+
+    spec = synth.config("c3", p=64, q=64, L=16, iters=1)
+    sc = synth.make_scene(spec)
+    pr = o.Problem.from_scene(sc)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        iters = 0
+        X, st = o.initial_state(sc.Yl.astype(np.float64), pr)
+        den = o.denominator(pr.p, pr.q, pr.b, pr.window, pr.K)
+        mu = pr.lam * o.weights(sc.Yh.astype(np.float64), pr.window, pr.K, pr.h) / pr.rho
+        F = o.p2_matrix(pr)
+        while True:
+            X, st = o.admm_step(st, sc.Yl.astype(np.float64), sc.Yh.astype(np.float64), pr, den,
+                                mu, F)
+            iters += 1
+            if time.perf_counter() - t0 >= seconds_target:
+                break
+        dt = time.perf_counter() - t0
+    return {"value": spec.p * spec.q * spec.L * iters / dt, "unit": "pixel*band*iter/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"literal FP64 oracle, 64x64x16 bands, Lh=4, patch 5x5, window 11x11, "
+                      f"{iters} iterations incl. weights/setup in {dt:.1f} s, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--iters", type=int, default=None, help="override the iteration count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the solve of one scene is "
+                          "not split across GPUs; run with --gpus 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2210_04184_amd import nlpr
+
+    spec = synth.config(args.config)
+    if args.iters is not None:
+        spec = spec.replace(iters=args.iters)
+    log(f"[bench] generating {workload_name(spec)}")
+    sc = synth.make_scene(spec)
+    dev = torch.device("cuda:0")
+    Yl = torch.from_numpy(sc.Yl).to(dev)
+    Yh = torch.from_numpy(sc.Yh).to(dev)
+    plan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING)
+    npairs = len(plan.half_window())
+    ws = plan.alloc_workspace()
+    Z = torch.empty((spec.L, spec.p, spec.q), dtype=torch.float32, device=dev)
+    log(f"[bench] workspace {plan.workspace_bytes / 1e9:.1f} GB; warmup {args.warmup}")
+    for i in range(args.warmup):
+        plan.solve(Yl, Yh, Z=Z, ws=ws)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1} done")
+    for st in nlpr.STAGE_NAMES:
+        plan.stage_time(st, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plan.solve(Yl, Yh, Z=Z, ws=ws)
+        torch.cuda.synchronize()
+        log(f"[bench] step {i + 1} done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = {}
+    for st, name in nlpr.STAGE_NAMES.items():
+        ms, n = plan.stage_time(st)
+        if n:
+            stages[name] = {"ms_total": round(ms, 3), "launches": n, "ms_avg": round(ms / n, 4)}
+    finite = bool(torch.isfinite(Z).all().item())
+
+    pbi = spec.p * spec.q * spec.L * spec.iters * args.steps
+    value = pbi / elapsed
+    sw = stages.get("sweep")
+    roof = None
+    if sw:
+        bytes_launch = sweep_bytes_per_launch(spec, npairs)
+        achieved = bytes_launch / (sw["ms_avg"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "sweep_kernel", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_launch": bytes_launch, "ms_per_launch": sw["ms_avg"]}
+    loop_ms = sum(v["ms_total"] for k, v in stages.items() if k not in ("weights", "init"))
+    out = {
+        "metric": "ADMM pixel*band*iter/s (+ % HBM roofline) at <=1e-4 rel. RMSE vs FP64 oracle",
+        "value": value, "unit": "pixel*band*iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload_name(spec), "p": spec.p, "q": spec.q, "L": spec.L,
+                   "Lh": spec.Lh, "d": spec.d, "blur": 2 * spec.blur_radius + 1,
+                   "patch": 2 * spec.K + 1, "window": 2 * spec.Sw + 1, "iters": spec.iters,
+                   "lambda": spec.lam, "rho": spec.rho, "seed": spec.seed},
+        "roofline": roof,
+        "loop_pbi_per_s": spec.p * spec.q * spec.L * spec.iters * args.steps / (loop_ms * 1e-3)
+        if loop_ms else None,
+        "stages": stages, "finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

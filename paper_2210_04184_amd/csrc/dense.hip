@@ -227,8 +227,13 @@ conv_kernel(const float* __restrict__ in, float* __restrict__ out, const float* 
 // One thread per pixel; bands are visited twice.  With E = I:
 //   P1 = (rho BX + Y_l - rho Lambda1) / (1 + rho)  on sampled pixels (S^T S = 1)
 //   P1 = BX - Lambda1                              elsewhere            (eq. (Qh_update))
-//   A  = X - Lambda2 + lambda1/rho (Y_h R^T)
-//   P2 = A F = A - (A R) G R^T,  F = (I + lambda1/rho R R^T)^{-1}       (eq. (Qm_update))
+//   P2 = (X - Lambda2 + lambda1/rho Y_h R^T) F,  F = (I + lambda1/rho R R^T)^{-1}
+//                                                                       (eq. (Qm_update))
+// P2 is evaluated as  P2 = A0 + (Y_h - A0 R) G R^T  with A0 = X - Lambda2 and
+// G = (rho/lambda1 I + R^T R)^{-1}: Woodbury gives F = I - R G R^T and the push-through
+// identity R^T F = (I + lambda1/rho R^T R)^{-1} R^T turns lambda1/rho Y_h R^T F into
+// Y_h G R^T.  The rearrangement is exact and keeps every FP32 term O(|X|) instead of
+// O(lambda1/rho |Y_h|), which avoids a large cancellation.
 //   Lambda1 -= BX - P1,  Lambda2 -= X - P2;  W1 = P1 + Lambda1,  W2 = P2 + Lambda2
 template <int LHM>
 __global__ void __launch_bounds__(256)
@@ -236,7 +241,7 @@ pupdate_kernel(const float* __restrict__ X, const float* __restrict__ BX,
                const float* __restrict__ Yl, const float* __restrict__ Yh,
                float* __restrict__ L1, float* __restrict__ L2, float* __restrict__ W1,
                float* __restrict__ W2, const float* __restrict__ R, const float* __restrict__ G,
-               int p, int q, int L, int Lh, int d, float rho, float lam1_rho, float inv_1prho) {
+               int p, int q, int L, int Lh, int d, float rho, float inv_1prho) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const size_t plane = (size_t)p * q;
   if (j >= (int)plane) return;
@@ -244,43 +249,34 @@ pupdate_kernel(const float* __restrict__ X, const float* __restrict__ BX,
   const bool sampled = (i1 % d == 0) && (i2 % d == 0);
   const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
   const size_t lplane = (size_t)(p / d) * (q / d);
-  float yh[LHM], ar[LHM];
+  float res[LHM];
 #pragma unroll
-  for (int h = 0; h < LHM; ++h) {
-    yh[h] = (h < Lh) ? Yh[h * plane + j] : 0.f;
-    ar[h] = 0.f;
-  }
+  for (int h = 0; h < LHM; ++h) res[h] = (h < Lh) ? Yh[h * plane + j] : 0.f;
+  // res = Y_h - A0 R
   for (int c = 0; c < L; ++c) {
-    float yr = 0.f;
+    const float a0 = X[c * plane + j] - L2[c * plane + j];
 #pragma unroll
     for (int h = 0; h < LHM; ++h)
-      if (h < Lh) yr += yh[h] * R[c * Lh + h];
-    const float a = X[c * plane + j] - L2[c * plane + j] + lam1_rho * yr;
-#pragma unroll
-    for (int h = 0; h < LHM; ++h)
-      if (h < Lh) ar[h] += a * R[c * Lh + h];
+      if (h < Lh) res[h] -= a0 * R[c * Lh + h];
   }
-  float tg[LHM];
+  // u = res G
+  float u[LHM];
 #pragma unroll
   for (int h2 = 0; h2 < LHM; ++h2) {
     float s = 0.f;
 #pragma unroll
     for (int h = 0; h < LHM; ++h)
-      if (h < Lh && h2 < Lh) s += ar[h] * G[h * Lh + h2];
-    tg[h2] = s;
+      if (h < Lh && h2 < Lh) s += res[h] * G[h * Lh + h2];
+    u[h2] = s;
   }
   for (int c = 0; c < L; ++c) {
     const size_t o = c * plane + j;
-    float yr = 0.f, corr = 0.f;
+    float corr = 0.f;
 #pragma unroll
     for (int h = 0; h < LHM; ++h)
-      if (h < Lh) {
-        yr += yh[h] * R[c * Lh + h];
-        corr += tg[h] * R[c * Lh + h];
-      }
+      if (h < Lh) corr += u[h] * R[c * Lh + h];
     const float x = X[o], l2 = L2[o];
-    const float a = x - l2 + lam1_rho * yr;
-    const float p2 = a - corr;
+    const float p2 = (x - l2) + corr;
     const float l2n = l2 - (x - p2);
     L2[o] = l2n;
     W2[o] = p2 + l2n;
@@ -364,12 +360,11 @@ int launch_pupdate(const Plan& P, const float* X, const float* BX, const float* 
   const int p = P.prm.p, q = P.prm.q;
   const int n = p * q;
   const float rho = (float)P.prm.rho;
-  const float lr = (float)(P.prm.lambda1 / P.prm.rho);
   const float inv = (float)(1.0 / (1.0 + P.prm.rho));
   dim3 grid(ceil_div(n, 256));
 #define NLPR_PU(LHM)                                                                         \
   hipLaunchKernelGGL(pupdate_kernel<LHM>, grid, dim3(256), 0, s, X, BX, Yl, Yh, Lam1, Lam2, W1, \
-                     W2, P.d_R, P.d_G, p, q, P.prm.L, P.prm.Lh, P.prm.d, rho, lr, inv)
+                     W2, P.d_R, P.d_G, p, q, P.prm.L, P.prm.Lh, P.prm.d, rho, inv)
   if (P.prm.Lh == 1) NLPR_PU(1);
   else if (P.prm.Lh <= 4) NLPR_PU(4);
   else NLPR_PU(16);

@@ -1,0 +1,86 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+The FP64 oracle cannot hold the dual state of a 512 x 512 x 128 solve with an 11 x 11
+window and 5 x 5 patches (about 1.6 TB in its literal form), so at these sizes:
+  * the first two iterations are compared on sampled bands: with Q = Sigma = 0 at the
+    start, X^(2) of band c needs the regulariser term of band c only, and the oracle
+    computes it band by band (``two_iterations_bands``);
+  * the full 100-iteration solve is checked by properties that hold at any size:
+    finiteness, |Sigma| <= mu for every stored dual, both soft-threshold branches in use,
+    and bit-for-bit repeatability.
+"""
+import gc
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import nlpr_oracle as o
+from paper_2210_04184_amd import nlpr
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def release():
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("cfg,bands", [("c3", [5, 127]), ("c2", [50])])
+def test_full_size_two_iterations_on_sampled_bands(cfg, bands):
+    spec = synth.config(cfg, iters=2)
+    sc = synth.make_scene(spec)
+    print(f"[fullsize] {cfg} {spec.p}x{spec.q}x{spec.L} two iterations, bands {bands}", flush=True)
+    plan = nlpr.Plan.from_scene(sc)
+    try:
+        Z, ws = plan.solve(dev(sc.Yl), dev(sc.Yh))
+        z = Z[bands].cpu().numpy().astype(np.float64)
+        del Z, ws
+    finally:
+        plan.close()
+        release()
+    pr = o.Problem.from_scene(sc)
+    ref = o.two_iterations_bands(sc.Yl.astype(np.float64), sc.Yh.astype(np.float64), pr, bands)
+    rel = float(np.linalg.norm(z - ref) / np.linalg.norm(ref))
+    print(f"[fullsize] {cfg} relRMSE = {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
+def test_full_size_solve_properties():
+    """The benchmark workload (512 x 512 x 128, window 11 x 11, patch 5 x 5, 100 iterations)."""
+    spec = synth.config("c3")
+    sc = synth.make_scene(spec)
+    plan = nlpr.Plan.from_scene(sc, flags=nlpr.CHECK_FINITE)
+    try:
+        Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+        ws = plan.alloc_workspace()
+        Z1, _ = plan.solve(Yl, Yh, ws=ws)
+        Z2, _ = plan.solve(Yl, Yh, ws=ws)
+        assert torch.equal(Z1, Z2)
+        npairs = len(plan.half_window())
+        npatch = (2 * spec.K + 1) ** 2
+        sig = plan.region_view(ws, nlpr.REGION_SIGMA).view(npairs, npatch, spec.L, spec.p, spec.q)
+        mu = plan.region_view(ws, nlpr.REGION_MU).view(npairs, spec.p, spec.q)
+        rng = np.random.default_rng(0)
+        fracs = []
+        P = o.patch_offsets(spec.K)
+        for _ in range(6):
+            n, m, c = int(rng.integers(npairs)), int(rng.integers(npatch)), int(rng.integers(spec.L))
+            s = sig[n, m, c].cpu().numpy().astype(np.float64)
+            k = P[m]
+            bound = o.shift(mu[n].cpu().numpy().astype(np.float64), (-k[0], -k[1]))
+            assert np.all(np.abs(s) <= bound * (1 + 1e-6) + 1e-30)
+            fracs.append(np.mean(np.abs(np.abs(s) - bound) <= 1e-7 * bound))
+        frac = float(np.mean(fracs))
+        print(f"[fullsize] fraction of duals on the threshold: {frac:.3f}", flush=True)
+        assert 0.02 <= frac <= 0.98
+        del sig, mu, ws, Z1, Z2
+    finally:
+        plan.close()
+        release()
