@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+SWEEP_SRC = os.path.join(ROOT, "paper_2210_04184_amd", "csrc", "sweep.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c3_traffic.json")
 
 
 def log(*a):
@@ -43,6 +45,47 @@ def sweep_bytes_per_launch(spec, npairs: int) -> int:
     npatch = (2 * spec.K + 1) ** 2
     n = spec.p * spec.q
     return (8 * npairs * npatch + 8) * n * spec.L + 4 * npairs * n
+
+
+def measured_traffic(config: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it was
+    taken on the current sweep source and workload; else None."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(SWEEP_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("sweep_source_sha256") != sha or rec.get("config") != config:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def hbm_reference(gib: float):
+    """Plain torch copy and in-place negation over `gib` GiB buffers, event-timed: the
+    practical HBM ceiling for a streaming read+write, and the copy kernel of known size whose
+    FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures."""
+    import torch
+    n = int(gib * 1024 ** 3) // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn in (("copy", lambda: y.copy_(x)), ("inplace_rmw", lambda: x.neg_())):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(3):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        out[name + "_GBs"] = round(2 * 4 * n * 3 / (s.elapsed_time(e) * 1e-3) / 1e9, 1)
+    out["bytes_each_way"] = 4 * n
+    del x, y
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(seconds_target: float = 15.0):
@@ -85,6 +128,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--iters", type=int, default=None, help="override the iteration count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-gib", type=float, default=4.0,
+                    help="size of the reference copy (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -102,6 +147,9 @@ def main():
     spec = synth.config(args.config)
     if args.iters is not None:
         spec = spec.replace(iters=args.iters)
+    ref = hbm_reference(args.calib_gib) if args.calib_gib > 0 else None
+    if ref:
+        log(f"[bench] reference streams: {ref}")
     log(f"[bench] generating {workload_name(spec)}")
     sc = synth.make_scene(spec)
     dev = torch.device("cuda:0")
@@ -142,7 +190,8 @@ def main():
         achieved = bytes_launch / (sw["ms_avg"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": "sweep_kernel", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": bytes_launch, "ms_per_launch": sw["ms_avg"]}
+                "traffic": measured_traffic(args.config), "bytes_per_launch": bytes_launch,
+                "ms_per_launch": sw["ms_avg"]}
     loop_ms = sum(v["ms_total"] for k, v in stages.items() if k not in ("weights", "init"))
     out = {
         "metric": "ADMM pixel*band*iter/s (+ % HBM roofline) at <=1e-4 rel. RMSE vs FP64 oracle",
@@ -157,7 +206,7 @@ def main():
         "roofline": roof,
         "loop_pbi_per_s": spec.p * spec.q * spec.L * spec.iters * args.steps / (loop_ms * 1e-3)
         if loop_ms else None,
-        "stages": stages, "finite": finite,
+        "stages": stages, "finite": finite, "hbm_reference": ref,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a sample")

@@ -78,6 +78,10 @@ enum {
  *   blur_radius: r, the blur kernel is (2r+1) x (2r+1), centred, 0 <= r <= 16.
  *   K          : patch radius, P = [-K, K]^2, 0 <= K <= 4.
  *   Sw         : search radius, W = [-Sw, Sw]^2, 0 <= Sw <= 8, Sw < p and Sw < q.
+ *   The sweep keeps full image rows in LDS: with R = max(1, 1024 * items / q) rows per tile
+ *   (items = 1, 2 or 4, the smallest with 1024 * items >= q),
+ *   4 * ((R + 2K)(q + 8) + 2 (R + Sw) q) must not exceed 160 KiB (e.g. q <= 2048 for
+ *   K = 2, Sw = 5).
  *   iters      : ADMM iterations, >= 0.
  *   lambda     : regulariser weight lambda_2 >= 0.  The soft-threshold of eq. (Qj_main) is
  *                lambda * omega / rho.
@@ -119,7 +123,7 @@ int nlpr_plan_create(const nlpr_params* params, const float* blur_host, const fl
                      const float* E_host, nlpr_plan** out);
 
 /* Bytes of device workspace nlpr_solve needs for this plan.  The dominant part is the
- * dual state Sigma' (see nlpr_workspace_region): 4 * Npairs * (2K+1)^2 * L * p * q bytes. */
+ * dual state Sigma' (see nlpr_workspace_region): about 4 * Npairs * (2K+1)^2 * L * p * q bytes. */
 int nlpr_workspace_size(const nlpr_plan* plan, size_t* bytes);
 
 /*
@@ -154,12 +158,27 @@ const char* nlpr_last_error(void);
  */
 int nlpr_half_window(const nlpr_plan* plan, int32_t* tau, int32_t cap, int32_t* n);
 
+/* Geometry of a plan that callers need to read the dual state. */
+typedef struct nlpr_plan_info {
+  int32_t npairs;       /* |W+|, number of stored shifts                                    */
+  int32_t npatch;       /* |P| = (2K+1)^2                                                   */
+  int32_t tile_rows;    /* R: image rows per sweep tile                                      */
+  int32_t ntiles;       /* ceil(p / R)                                                      */
+  int32_t halo_rows;    /* largest tau1 in W+ (rows the adjoint scatter reaches above a tile) */
+  int32_t reserved;
+  size_t sigma_elems;   /* floats in the Sigma' region (= L * ntiles * npairs * npatch * R * q) */
+} nlpr_plan_info;
+int nlpr_plan_get_info(const nlpr_plan* plan, nlpr_plan_info* info);
+
 /* Workspace regions (byte offset and size inside ws). */
 typedef enum nlpr_region {
-  NLPR_REGION_SIGMA = 0,  /* Sigma' [Npairs][(2K+1)^2][L][p][q]: the dual of eq. (dualvar3_main) for
-                             tau in W+ (order of nlpr_half_window) and k in P (k1 major, then k2,
-                             each from -K to K), stored source-aligned: Sigma'_{tau k}(j) =
-                             Sigma_{tau k}(j + k).                                                   */
+  NLPR_REGION_SIGMA = 0,  /* Sigma', the dual of eq. (dualvar3_main) for tau in W+ (order of
+                             nlpr_half_window) and k in P (k1 major, then k2, each from -K to
+                             K), stored source-aligned: Sigma'_{tau k}(j) = Sigma_{tau k}(j + k).
+                             Layout [L][ntiles][Npairs][|P|][R][q] (nlpr_plan_get_info): image
+                             row i of band c lives in tile i / R at row i % R, so one sweep
+                             workgroup streams one contiguous block; rows past p in a ragged
+                             last tile are unused.                                            */
   NLPR_REGION_MU = 1,     /* mu [Npairs][p][q] = lambda * omega_{i tau} / rho, the thresholds         */
   NLPR_REGION_C = 2,      /* C [L][p][q], right-hand side of eq. (x_linear_system_main)                */
   NLPR_REGION_LAMBDA1 = 3,/* Lambda1 [L][p][q]                                                       */
@@ -181,7 +200,8 @@ int nlpr_workspace_region(const nlpr_plan* plan, int region, size_t* offset, siz
  *                          (dualvar1_main), (dualvar2_main) update Lambda1, Lambda2 in place;
  *                          W1 = P1 + Lambda1 and W2 = P2 + Lambda2 with the new duals.
  *   NLPR_STAGE_SWEEP       {X, mu, Sigma', Creg, ws}  Q-update (eq. (Qj_main)) and Sigma-update
- *                          (eq. (dualvar3_main)) for every tau in W, k in P, in place on Sigma';
+ *                          (eq. (dualvar3_main)) for every tau in W, k in P, in place on Sigma'
+ *                          (sigma_elems floats, layout of NLPR_REGION_SIGMA);
  *                          Creg = sum_{tau in W} sum_k D_{tau k}^T (Q_{tau k} + Sigma_{tau k}).
  *   NLPR_STAGE_SWEEP_FIRST same, with Sigma' taken as 0 on input (only written).
  *   NLPR_STAGE_ASSEMBLE    {W1, W2, Creg, C}          C = B^T W1 + W2 + Creg

@@ -94,6 +94,12 @@ int validate(const nlpr_params& q) {
   if (!(q.rho > 0.0) || !std::isfinite(q.rho)) return fail(NLPR_ERR_INVALID_ARG, "rho must be > 0");
   if (!(q.flags & NLPR_UNWEIGHTED) && !(q.h > 0.0 && std::isfinite(q.h)))
     return fail(NLPR_ERR_INVALID_ARG, "h must be > 0");
+  // the sweep keeps full image rows of X, mu and its accumulator in LDS
+  const int halo = (q.flags & NLPR_LOCAL_WINDOW) ? 1 : q.Sw;
+  const SweepShape sh = choose_sweep_shape(q.p, q.q, q.K, halo);
+  if (sh.lds > kMaxSweepLds)
+    return bad("q too large for the patch / search radii: the sweep tile needs " +
+               std::to_string(sh.lds) + " bytes of LDS (max " + std::to_string(kMaxSweepLds) + ")");
   return NLPR_OK;
 }
 
@@ -233,7 +239,7 @@ int nlpr_plan_create(const nlpr_params* params, const float* blur_host, const fl
     return o;
   };
   P.sz_plane = plane * L * sizeof(float);
-  P.sz_sigma = (size_t)P.npairs * P.npatch * P.sz_plane;
+  P.sz_sigma = sweep_sigma_bytes(P.sweep, q, L, P.npairs, P.npatch);
   P.sz_mu = (size_t)P.npairs * plane * sizeof(float);
   P.sz_F = (size_t)((L + 1) / 2) * plane * sizeof(float2);
   P.sz_halo = (size_t)L * P.sweep.ntiles * P.sweep.halo * q * sizeof(float);
@@ -276,6 +282,19 @@ int nlpr_half_window(const nlpr_plan* plan, int32_t* tau, int32_t cap, int32_t* 
     tau[2 * i] = P.taus[2 * i];
     tau[2 * i + 1] = P.taus[2 * i + 1];
   }
+  return NLPR_OK;
+}
+
+int nlpr_plan_get_info(const nlpr_plan* plan, nlpr_plan_info* info) {
+  if (!plan || !info) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  const Plan& P = plan->P;
+  info->npairs = P.npairs;
+  info->npatch = P.npatch;
+  info->tile_rows = P.sweep.rows;
+  info->ntiles = P.sweep.ntiles;
+  info->halo_rows = P.sweep.halo;
+  info->reserved = 0;
+  info->sigma_elems = P.sz_sigma / sizeof(float);
   return NLPR_OK;
 }
 

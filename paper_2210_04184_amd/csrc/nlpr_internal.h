@@ -18,6 +18,7 @@ constexpr int kMaxSw = 8;
 constexpr int kMaxBlurRadius = 16;
 constexpr int kMaxFFTFactors = 24;
 constexpr int kMaxFFTLen = 4096;
+constexpr size_t kMaxSweepLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 // One-dimensional FFT of length n = product of fac[] (each 2, 3, 4 or 8); passed to
 // kernels by value.  tw[m] = exp(-2 pi i m / n), m in [0, n).
@@ -107,6 +108,7 @@ int launch_xsolve(const Plan& P, const float* C, float* X, float2* F, hipStream_
 
 // ---- sweep (sweep.hip)
 SweepShape choose_sweep_shape(int p, int q, int K, int halo);
+size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npatch);
 int launch_sweep(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
                  float* halo, bool first, hipStream_t s);
 

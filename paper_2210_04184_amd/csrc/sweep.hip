@@ -33,14 +33,27 @@ namespace {
 
 constexpr int PADW = 4;  // mu rows in LDS are padded by one float4 on each side (K <= 4)
 
+// Sigma' is touched once per iteration: stream it with non-temporal loads and stores so it
+// does not evict X and mu from the caches.
+#ifndef NLPR_SWEEP_NT
+#define NLPR_SWEEP_NT 1
+#endif
 typedef float v4f __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float4 ld_nt(const float* p) {
+#if NLPR_SWEEP_NT
   const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+#else
+  const v4f v = *reinterpret_cast<const v4f*>(p);
+#endif
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void st_nt(float* p, float4 v) {
   v4f w = {v.x, v.y, v.z, v.w};
+#if NLPR_SWEEP_NT
   __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p));
+#else
+  *reinterpret_cast<v4f*>(p) = w;
+#endif
 }
 __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v, -m), m); }
 
@@ -89,9 +102,11 @@ sweep_kernel(const float* __restrict__ X, const float* __restrict__ mu, float* _
     cp[m] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
 
-  const size_t kstride = (size_t)L * plane;       // between patch offsets
-  const size_t tstride = (size_t)NP * kstride;    // between shifts
-  float* sig_tile = sig + (size_t)c * plane + (size_t)r0 * q;
+  // Sigma' as [L][tiles][Npairs][|P|][R][q]: the whole state of one workgroup is one
+  // contiguous stream, each (tau, k) slab of it R*q floats.
+  const size_t kstride = (size_t)R * q;             // between patch offsets
+  const size_t tstride = (size_t)NP * kstride;      // between shifts
+  float* sig_tile = sig + ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
 
   for (int n = 0; n < npairs; ++n) {
     const int2 t = taus[n];
@@ -205,14 +220,24 @@ sweep_kernel(const float* __restrict__ X, const float* __restrict__ mu, float* _
   }
 }
 
-constexpr int kThreads = 256;
-constexpr int kItems = 4;
+#ifndef NLPR_SWEEP_THREADS
+#define NLPR_SWEEP_THREADS 256
+#endif
+#ifndef NLPR_SWEEP_MIN_ITEMS
+#define NLPR_SWEEP_MIN_ITEMS 1
+#endif
+// Workgroup size and the smallest number of float4 items per thread.  One item per thread
+// (tiles of 2 rows at q = 512, 90 VGPRs, three workgroups per CU) streamed Sigma' fastest
+// among 1, 2 and 4 items and 256 / 512 / 1024 threads; wider images take 2 or 4 items so
+// that one workgroup covers at least one full row.
+constexpr int kThreads = NLPR_SWEEP_THREADS;
+constexpr int kMinItems = NLPR_SWEEP_MIN_ITEMS;
 
-template <int K, bool FIRST>
+template <int K, int ITEMS, bool FIRST>
 int launch_k(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
              float* halo, hipStream_t s) {
   const SweepShape& sh = P.sweep;
-  auto kern = sweep_kernel<K, kItems, kThreads, FIRST>;
+  auto kern = sweep_kernel<K, ITEMS, kThreads, FIRST>;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -226,13 +251,25 @@ int launch_k(const Plan& P, const float* X, const float* mu, float* sigma, float
   return NLPR_OK;
 }
 
+template <int K, bool FIRST>
+int launch_items(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
+                 float* halo, hipStream_t s) {
+  switch (P.sweep.items) {
+    case 1: return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST>(P, X, mu, sigma, creg, halo, s);
+    case 2: return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST>(P, X, mu, sigma, creg, halo, s);
+    default: return launch_k<K, 4, FIRST>(P, X, mu, sigma, creg, halo, s);
+  }
+}
+
 }  // namespace
 
 SweepShape choose_sweep_shape(int p, int q, int K, int halo) {
   SweepShape sh{};
   sh.threads = kThreads;
-  sh.items = kItems;
-  const int per_block = kThreads * kItems * 4;  // pixels per workgroup
+  int items = kMinItems;
+  while (items < 4 && kThreads * items * 4 < q) items *= 2;
+  sh.items = items;
+  const int per_block = kThreads * items * 4;  // pixels per workgroup
   sh.rows = std::max(1, std::min(p, per_block / q));
   sh.ntiles = ceil_div(p, sh.rows);
   sh.halo = halo;
@@ -240,13 +277,17 @@ SweepShape choose_sweep_shape(int p, int q, int K, int halo) {
   return sh;
 }
 
+size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npatch) {
+  return (size_t)L * sh.ntiles * npairs * npatch * sh.rows * q * sizeof(float);
+}
+
 int launch_sweep(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
                  float* halo, bool first, hipStream_t s) {
   switch (P.prm.K) {
 #define NLPR_SW(KK)                                                                   \
   case KK:                                                                            \
-    return first ? launch_k<KK, true>(P, X, mu, sigma, creg, halo, s)                 \
-                 : launch_k<KK, false>(P, X, mu, sigma, creg, halo, s);
+    return first ? launch_items<KK, true>(P, X, mu, sigma, creg, halo, s)             \
+                 : launch_items<KK, false>(P, X, mu, sigma, creg, halo, s);
     NLPR_SW(0)
     NLPR_SW(1)
     NLPR_SW(2)

@@ -50,9 +50,10 @@ REGION_C = 2
 REGION_LAMBDA1 = 3
 REGION_LAMBDA2 = 4
 
-EXPORTED = ["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlpr_plan_destroy",
-            "nlpr_status_string", "nlpr_last_error", "nlpr_half_window",
-            "nlpr_workspace_region", "nlpr_debug_stage", "nlpr_stage_time"]
+EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlpr_plan_destroy",
+                   "nlpr_status_string", "nlpr_last_error", "nlpr_half_window",
+                   "nlpr_workspace_region", "nlpr_debug_stage", "nlpr_stage_time",
+                   "nlpr_plan_get_info"])
 
 
 class NlprError(RuntimeError):
@@ -67,6 +68,13 @@ class Params(ctypes.Structure):
                 ("K", ctypes.c_int32), ("Sw", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("lam", ctypes.c_double), ("lam1", ctypes.c_double),
                 ("rho", ctypes.c_double), ("h", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("npairs", ctypes.c_int32), ("npatch", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("ntiles", ctypes.c_int32),
+                ("halo_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma_elems", ctypes.c_size_t)]
 
 
 _lib = None
@@ -90,6 +98,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_last_error.argtypes = []
     lib.nlpr_last_error.restype = ctypes.c_char_p
     lib.nlpr_half_window.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+    lib.nlpr_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.nlpr_workspace_region.argtypes = [vp, ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.nlpr_debug_stage.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), i32, vp]
     lib.nlpr_stage_time.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -177,6 +186,24 @@ class Plan:
         buf = (ctypes.c_int32 * (2 * max(n.value, 1)))()
         _check(load().nlpr_half_window(self.handle, buf, n.value, ctypes.byref(n)))
         return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
+
+    def info(self) -> PlanInfo:
+        inf = PlanInfo()
+        _check(load().nlpr_plan_get_info(self.handle, ctypes.byref(inf)))
+        return inf
+
+    def alloc_sigma(self, fill: float = float("nan")):
+        """A standalone Sigma' buffer (layout of the workspace region) for the sweep stage."""
+        import torch
+        return torch.full((self.info().sigma_elems,), fill, dtype=torch.float32, device="cuda")
+
+    def sigma_logical(self, sig):
+        """Sigma' (tile-major, as stored) rearranged to [Npairs][|P|][L][p][q]."""
+        inf = self.info()
+        L, p, q = self.shape
+        t = sig.view(L, inf.ntiles, inf.npairs, inf.npatch, inf.tile_rows, q)
+        t = t.permute(2, 3, 0, 1, 4, 5).reshape(inf.npairs, inf.npatch, L, inf.ntiles * inf.tile_rows, q)
+        return t[:, :, :, :p, :]
 
     def region(self, which: int) -> Tuple[int, int]:
         off, nb = ctypes.c_size_t(), ctypes.c_size_t()

@@ -225,3 +225,26 @@ def small_spec(p=64, q=64, L=8, Lh=1, d=4, blur_radius=3, K=1, Sw=2, iters=20, s
                      snr_l=kw.pop("snr_l", 30.0), snr_h=kw.pop("snr_h", 30.0),
                      n_end=kw.pop("n_end", 5), tile=kw.pop("tile", 16), corr=kw.pop("corr", 8.0),
                      K=K, Sw=Sw, iters=iters, seed=seed, **kw)
+
+
+def batch_specs(n: int = 48, seed: int = 1000, iters: int = 100):
+    """The multi-scene workload: ``n`` independent scenes with sizes drawn from
+    {128, 192, 256, 384, 512}^2, band counts from {4, 8, 31, 64, 128}, decimation 4 or 8
+    and a PAN (1 band) or 4-band MS guide, 30 dB noise, patch 3x3 and window 3x3.  The blur
+    is 9x9 with sigma 2.5 for d = 4 and 17x17 with sigma 5 for d = 8.  Scene s is drawn
+    with seed ``seed + s``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n):
+        side = int(rng.choice([128, 192, 256, 384, 512]))
+        L = int(rng.choice([4, 8, 31, 64, 128]))
+        d = int(rng.choice([4, 8]))
+        pan = bool(rng.integers(0, 2))
+        Lh = 1 if pan else 4
+        kind = "bell1" if pan else ("gauss4" if L >= 8 else "random")
+        r, sig = (4, 2.5) if d == 4 else (8, 5.0)
+        out.append(SceneSpec(name=f"b{s}", p=side, q=side, L=L, d=d, blur_radius=r,
+                             blur_sigma=sig, R_kind=kind, Lh=Lh, snr_l=30.0, snr_h=30.0,
+                             n_end=8, tile=16, corr=8.0, K=1, Sw=1, iters=iters,
+                             seed=seed + s))
+    return out

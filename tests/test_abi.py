@@ -81,6 +81,7 @@ def _create(**over):
     (dict(iters=-1), nlpr.ERR_INVALID_ARG),
     (dict(d=0), nlpr.ERR_INVALID_ARG),
     (dict(rho=float("nan")), nlpr.ERR_INVALID_ARG),
+    (dict(p=64, q=4096, K=4, Sw=8, d=1), nlpr.ERR_UNSUPPORTED_SHAPE),   # sweep tile exceeds LDS
 ])
 def test_invalid_parameters_are_rejected_on_the_host(over, code):
     rc, h, msg = _create(**over)

@@ -65,14 +65,16 @@ def test_full_size_solve_properties():
         assert torch.equal(Z1, Z2)
         npairs = len(plan.half_window())
         npatch = (2 * spec.K + 1) ** 2
-        sig = plan.region_view(ws, nlpr.REGION_SIGMA).view(npairs, npatch, spec.L, spec.p, spec.q)
+        inf = plan.info()
+        sig = plan.region_view(ws, nlpr.REGION_SIGMA).view(spec.L, inf.ntiles, npairs, npatch,
+                                                            inf.tile_rows, spec.q)
         mu = plan.region_view(ws, nlpr.REGION_MU).view(npairs, spec.p, spec.q)
         rng = np.random.default_rng(0)
         fracs = []
         P = o.patch_offsets(spec.K)
         for _ in range(6):
             n, m, c = int(rng.integers(npairs)), int(rng.integers(npatch)), int(rng.integers(spec.L))
-            s = sig[n, m, c].cpu().numpy().astype(np.float64)
+            s = sig[c, :, n, m].reshape(-1, spec.q)[:spec.p].cpu().numpy().astype(np.float64)
             k = P[m]
             bound = o.shift(mu[n].cpu().numpy().astype(np.float64), (-k[0], -k[1]))
             assert np.all(np.abs(s) <= bound * (1 + 1e-6) + 1e-30)

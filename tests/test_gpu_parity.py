@@ -145,7 +145,7 @@ def test_sweep_stage_two_steps(name):
     tmu = torch.empty((len(idx),) + shp[1:], device="cuda")
     plan.stage(nlpr.STAGE_WEIGHTS, [dev(sc.Yh), tmu])
     ws = plan.alloc_workspace()
-    sig = torch.full((len(idx), len(P)) + shp, float("nan"), device="cuda")  # never read when first
+    sig = plan.alloc_sigma(float("nan"))  # never read by the first sweep
     creg = torch.empty(shp, device="cuda")
     Sig = np.zeros((len(W), len(P)) + shp)
     for step in range(2):
@@ -161,7 +161,7 @@ def test_sweep_stage_two_steps(name):
                 newSig[a, m] = Sig[a, m] - (DX - Q)
                 Cw += o.D_T(Q + newSig[a, m], t, k)
         Sig = newSig
-        gs = host(sig)
+        gs = host(plan.sigma_logical(sig))
         scale = mu.max()
         for n, a in enumerate(idx):
             for m, k in enumerate(P):
@@ -262,7 +262,7 @@ def test_sigma_stays_within_thresholds_and_shrink_branch_is_exercised():
     sc = synth.make_scene(synth.config("c1"))
     z, plan, ws = solve_gpu(sc)
     npairs = len(plan.half_window())
-    sig = host(plan.region_view(ws, nlpr.REGION_SIGMA)).reshape(npairs, -1, *z.shape)
+    sig = host(plan.sigma_logical(plan.region_view(ws, nlpr.REGION_SIGMA)))
     mu = host(plan.region_view(ws, nlpr.REGION_MU)).reshape(npairs, *z.shape[1:])
     on_bound = []
     for m, k in enumerate(o.patch_offsets(sc.spec.K)):
