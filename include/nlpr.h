@@ -65,7 +65,12 @@ enum {
                                    requires Sw == 1                                                  */
   NLPR_CHECK_FINITE = 1u << 4,  /* nlpr_solve checks Z for NaN/Inf at the end; this synchronises
                                    the stream and may return NLPR_ERR_NUMERICAL                      */
-  NLPR_TIMING = 1u << 5         /* record HIP events around every stage; read with nlpr_stage_time   */
+  NLPR_TIMING = 1u << 5,        /* record HIP events around every stage; read with nlpr_stage_time   */
+  NLPR_GRAPH = 1u << 6          /* capture the whole solve (weights, start, all iterations) in a HIP
+                                   graph on the first call and replay it on later calls; ignored
+                                   with NLPR_TIMING.  The graph reads buffer addresses from a
+                                   device descriptor written before each launch, so later calls
+                                   may pass other buffers.                                          */
 };
 
 /*
@@ -228,6 +233,34 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
  * launches: number of timed launches.  reset != 0 clears the totals after reading.
  */
 int nlpr_stage_time(nlpr_plan* plan, int stage, double* ms_total, int64_t* launches, int reset);
+
+/*
+ * Batches: many independent scenes solved together (the multi-scene workload).  Every stage
+ * of the iteration is one kernel launch over all scenes: a table of (scene, block) work
+ * items maps each workgroup to a scene, whose sizes, tables and buffers a device
+ * descriptor holds.  With NLPR_GRAPH the whole batched solve is one HIP graph.
+ *   n        : number of scenes >= 1.
+ *   params   : host array of n parameter sets.  Scenes may differ in every size and
+ *              parameter, but must share iters and the flags NLPR_INIT_ZERO,
+ *              NLPR_STATE_IN, NLPR_CHECK_FINITE, NLPR_TIMING and NLPR_GRAPH
+ *              (else NLPR_ERR_INVALID_ARG).
+ *   blur_host, R_host : host arrays of n host pointers, as for nlpr_plan_create.
+ * The workspace of a batch is the concatenation of the scenes' workspaces;
+ * nlpr_batch_region gives a region of one scene (offset from the start of ws).
+ * nlpr_batch_solve takes host arrays of n device pointers Yl[s], Yh[s], Z[s] laid out as
+ * for nlpr_solve; it never allocates device memory.
+ */
+typedef struct nlpr_batch nlpr_batch;
+int nlpr_batch_create(int32_t n, const nlpr_params* params, const float* const* blur_host,
+                      const float* const* R_host, nlpr_batch** out);
+int nlpr_batch_workspace_size(const nlpr_batch* batch, size_t* bytes);
+int nlpr_batch_region(const nlpr_batch* batch, int32_t scene, int region, size_t* offset,
+                      size_t* bytes);
+int nlpr_batch_solve(nlpr_batch* batch, const float* const* Yl, const float* const* Yh,
+                     float* const* Z, void* ws, size_t ws_bytes, void* stream);
+int nlpr_batch_stage_time(nlpr_batch* batch, int stage, double* ms_total, int64_t* launches,
+                          int reset);
+int nlpr_batch_destroy(nlpr_batch* batch);
 
 #ifdef __cplusplus
 }

@@ -1,5 +1,5 @@
-// C ABI of libnlpr: plan creation, workspace layout, the ADMM solve loop, per-stage entry
-// points for testing, and stage timing.  See include/nlpr.h for the contract.
+// C ABI of libnlpr: plans and batches, workspace layout, the ADMM solve sequence, per-stage
+// entry points for testing, stage timing and graph capture.  See include/nlpr.h.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -9,7 +9,10 @@
 #include "nlpr_internal.h"
 
 struct nlpr_plan {
-  nlpr::Plan P;
+  nlpr::Batch B;
+};
+struct nlpr_batch {
+  nlpr::Batch B;
 };
 
 namespace nlpr {
@@ -18,6 +21,9 @@ static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 namespace {
+
+constexpr uint32_t kBatchFlags = NLPR_INIT_ZERO | NLPR_STATE_IN | NLPR_CHECK_FINITE |
+                                 NLPR_TIMING | NLPR_GRAPH;
 
 bool factor_23(int n, LineFFT& f) {
   f.n = n;
@@ -60,18 +66,6 @@ struct DeviceGuard {
   }
 };
 
-void free_plan(Plan& P) {
-  hipFree(P.d_taus);
-  hipFree(P.d_invden);
-  hipFree(P.d_tw_p);
-  hipFree(P.d_tw_q);
-  hipFree(P.d_blur);
-  hipFree(P.d_R);
-  hipFree(P.d_G);
-  for (hipEvent_t e : P.ev_pool) hipEventDestroy(e);
-  P.ev_pool.clear();
-}
-
 int validate(const nlpr_params& q) {
   auto bad = [](const std::string& m) { return fail(NLPR_ERR_UNSUPPORTED_SHAPE, m); };
   LineFFT tmp{};
@@ -103,42 +97,474 @@ int validate(const nlpr_params& q) {
   return NLPR_OK;
 }
 
-// Timing: events bracket each launch group when the plan was created with NLPR_TIMING.
+// ---------------------------------------------------------------------------- scenes
+void scene_free(Plan* P) {
+  if (!P) return;
+  hipFree(P->d_taus);
+  hipFree(P->d_invden);
+  hipFree(P->d_tw_p);
+  hipFree(P->d_tw_q);
+  hipFree(P->d_blur);
+  hipFree(P->d_R);
+  hipFree(P->d_G);
+  delete P;
+}
+
+// Validate, upload the blur taps and R, precompute the tables, tune the FFT shapes and lay
+// out the scene's part of the workspace.
+int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_host, Plan** out) {
+  *out = nullptr;
+  int rc = validate(prm);
+  if (rc) return rc;
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) return fail(NLPR_ERR_INVALID_ARG, "out of host memory");
+  P->prm = prm;
+  const int p = prm.p, q = prm.q, L = prm.L, Lh = prm.Lh, r = prm.blur_radius;
+  // W+ in storage order: (0, 1..S), then tau1 = 1..S with tau2 = -S..S
+  if (prm.flags & NLPR_LOCAL_WINDOW) {
+    P->taus = {0, 1, 1, 0};
+  } else {
+    const int S = prm.Sw;
+    for (int b = 1; b <= S; ++b) { P->taus.push_back(0); P->taus.push_back(b); }
+    for (int a = 1; a <= S; ++a)
+      for (int b = -S; b <= S; ++b) { P->taus.push_back(a); P->taus.push_back(b); }
+  }
+  P->npairs = (int)P->taus.size() / 2;
+  P->npatch = (2 * prm.K + 1) * (2 * prm.K + 1);
+  int hrows = 0;
+  for (int n = 0; n < P->npairs; ++n) hrows = std::max(hrows, P->taus[2 * n]);
+  factor_23(p, P->fp);
+  factor_23(q, P->fq);
+  P->sweep = choose_sweep_shape(p, q, prm.K, hrows);
+  auto cleanup = [&](int code) {
+    scene_free(P);
+    return code;
+  };
+  const size_t plane = (size_t)p * q;
+  if (hipMalloc(&P->d_taus, std::max<size_t>(1, P->npairs) * sizeof(int2)) != hipSuccess ||
+      hipMalloc(&P->d_invden, plane * sizeof(float)) != hipSuccess ||
+      hipMalloc(&P->d_tw_p, p * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&P->d_tw_q, q * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&P->d_blur, (2 * r + 1) * (2 * r + 1) * sizeof(float)) != hipSuccess ||
+      hipMalloc(&P->d_R, (size_t)L * Lh * sizeof(float)) != hipSuccess ||
+      hipMalloc(&P->d_G, (size_t)Lh * Lh * sizeof(float)) != hipSuccess) {
+    set_error("hipMalloc of plan tables failed");
+    return cleanup(NLPR_ERR_HIP);
+  }
+  P->fp.tw = P->d_tw_p;
+  P->fq.tw = P->d_tw_q;
+  if ((P->npairs && hipMemcpy(P->d_taus, P->taus.data(), P->npairs * sizeof(int2),
+                              hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(P->d_blur, blur_host, (2 * r + 1) * (2 * r + 1) * sizeof(float),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->d_R, R_host, (size_t)L * Lh * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("upload of the plan tables failed");
+    return cleanup(NLPR_ERR_HIP);
+  }
+  if ((rc = launch_precompute(*P))) return cleanup(rc);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    set_error("plan precompute failed");
+    return cleanup(NLPR_ERR_HIP);
+  }
+  if ((rc = autotune_fft(*P))) return cleanup(rc);
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](int slot, size_t bytes) {
+    P->off[slot] = off;
+    P->sz[slot] = bytes;
+    off = align256(off + std::max<size_t>(bytes, 4));
+  };
+  const size_t pl = plane * L * sizeof(float);
+  take(B_SIGMA, sweep_sigma_bytes(P->sweep, q, L, P->npairs, P->npatch));
+  take(B_MU, (size_t)P->npairs * plane * sizeof(float));
+  take(B_C, pl);
+  take(B_L1, pl);
+  take(B_L2, pl);
+  take(B_BX, pl);
+  take(B_W1, pl);
+  take(B_W2, pl);
+  take(B_F, (size_t)((L + 1) / 2) * plane * sizeof(float2));
+  take(B_HALO, (size_t)L * P->sweep.ntiles * P->sweep.halo * q * sizeof(float));
+  P->ws_bytes = off;
+  *out = P;
+  return NLPR_OK;
+}
+
+SceneDesc static_desc(const Plan& P) {
+  SceneDesc d;
+  std::memset(&d, 0, sizeof(d));   // padding included: descriptors are compared bytewise
+  const nlpr_params& q = P.prm;
+  d.p = q.p;
+  d.q = q.q;
+  d.L = q.L;
+  d.Lh = q.Lh;
+  d.d = q.d;
+  d.r = q.blur_radius;
+  d.K = q.K;
+  d.npairs = P.npairs;
+  d.npatch = P.npatch;
+  d.rows = P.sweep.rows;
+  d.ntiles = P.sweep.ntiles;
+  d.halo = P.sweep.halo;
+  d.fq_tpl = P.fft.q_tpl;
+  d.fq_lpb = P.fft.q_lpb;
+  d.fp_tpl = P.fft.p_tpl;
+  d.fp_cb = P.fft.p_cb;
+  d.init_zero = (q.flags & NLPR_INIT_ZERO) ? 1 : 0;
+  d.unweighted = (q.flags & NLPR_UNWEIGHTED) ? 1 : 0;
+  d.rho = (float)q.rho;
+  d.inv_1prho = (float)(1.0 / (1.0 + q.rho));
+  d.mu_scale = (float)(q.lambda / q.rho);
+  d.inv_h2 = (q.flags & NLPR_UNWEIGHTED) ? 0.f : (float)(1.0 / (q.h * q.h));
+  d.fp = P.fp;
+  d.fq = P.fq;
+  d.taus = P.d_taus;
+  d.invden = P.d_invden;
+  d.blur = P.d_blur;
+  d.R = P.d_R;
+  d.G = P.d_G;
+  return d;
+}
+
+// ----------------------------------------------------------------------------- batches
+void batch_release(Batch& B) {
+  for (int k = 0; k < KD_COUNT; ++k) {
+    for (Group& g : B.groups[k]) hipFree(g.d_items);
+    B.groups[k].clear();
+  }
+  if (B.upload_ev) hipEventSynchronize(B.upload_ev);
+  hipFree(B.d_desc);
+  if (B.h_desc) hipHostFree(B.h_desc);
+  hipFree(B.d_flag);
+  if (B.upload_ev) hipEventDestroy(B.upload_ev);
+  if (B.graph) hipGraphExecDestroy(B.graph);
+  for (hipEvent_t e : B.ev_pool) hipEventDestroy(e);
+  B.ev_pool.clear();
+  for (Plan* P : B.scenes) scene_free(P);
+  B.scenes.clear();
+  B.d_desc = nullptr;
+  B.h_desc = nullptr;
+  B.d_flag = nullptr;
+  B.upload_ev = nullptr;
+  B.graph = nullptr;
+}
+
+int add_group(Batch& B, Kind kind, const std::vector<int2>& items, int block, size_t lds, int k0,
+              int k1) {
+  Group g;
+  g.nitems = (int)items.size();
+  g.block = block;
+  g.lds = lds;
+  g.key0 = k0;
+  g.key1 = k1;
+  if (g.nitems) {
+    NLPR_HIP_TRY(hipMalloc(&g.d_items, items.size() * sizeof(int2)));
+    NLPR_HIP_TRY(hipMemcpy(g.d_items, items.data(), items.size() * sizeof(int2),
+                           hipMemcpyHostToDevice));
+  }
+  B.groups[kind].push_back(g);
+  return NLPR_OK;
+}
+
+int block256(const Plan&) { return 256; }
+int rows_block(const Plan& P) { return fft_block(P.fft.q_tpl); }
+int cols_block(const Plan& P) { return fft_block(P.fft.p_tpl); }
+size_t no_lds(const Plan&) { return 0; }
+
+// Work-item tables of every launch kind, descriptors, events.
+int batch_build(Batch& B) {
+  const int n = (int)B.scenes.size();
+  B.base.resize(n);
+  size_t off = 0;
+  for (int s = 0; s < n; ++s) {
+    B.base[s] = off;
+    off = align256(off + B.scenes[s]->ws_bytes);
+  }
+  B.ws_bytes = off;
+  auto simple = [&](Kind kind, int (*count)(const Plan&), size_t (*lds)(const Plan&),
+                    int (*block)(const Plan&)) -> int {
+    std::vector<int2> it;
+    size_t l = 0;
+    int bs = 256;
+    for (int s = 0; s < n; ++s) {
+      const Plan& P = *B.scenes[s];
+      if (kind == KD_WEIGHTS && P.npairs == 0) continue;
+      const int c = count(P);
+      for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+      l = std::max(l, lds(P));
+      bs = std::max(bs, block(P));
+    }
+    return add_group(B, kind, it, bs, l, 0, 0);
+  };
+  int rc;
+  if ((rc = simple(KD_WEIGHTS, weights_blocks, weights_lds, block256))) return rc;
+  if ((rc = simple(KD_PLANE, plane_blocks, no_lds, block256))) return rc;
+  if ((rc = simple(KD_CONV, conv_blocks, conv_lds, block256))) return rc;
+  for (int cls : {1, 4, kMaxLh}) {
+    std::vector<int2> it;
+    for (int s = 0; s < n; ++s) {
+      const Plan& P = *B.scenes[s];
+      if (lh_class(P.prm.Lh) != cls) continue;
+      const int c = pixel_blocks(P);
+      for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+    }
+    if (!it.empty() && (rc = add_group(B, KD_PIXEL, it, 256, 0, cls, 0))) return rc;
+  }
+  if ((rc = simple(KD_ROWS, rows_blocks, rows_lds, rows_block))) return rc;
+  if ((rc = simple(KD_COLS, cols_blocks, cols_lds, cols_block))) return rc;
+  // the sweep: one launch per (patch radius, items per thread)
+  for (int K = 0; K <= kMaxK; ++K)
+    for (int items = 1; items <= 4; items *= 2) {
+      std::vector<int2> it;
+      size_t l = 0;
+      for (int s = 0; s < n; ++s) {
+        const Plan& P = *B.scenes[s];
+        if (P.npairs == 0 || P.prm.K != K || P.sweep.items != items) continue;
+        const int c = sweep_blocks(P);
+        for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+        l = std::max(l, P.sweep.lds);
+      }
+      if (it.empty()) continue;
+      if ((rc = add_group(B, KD_SWEEP, it, 256, l, K, items))) return rc;
+      if ((rc = sweep_prepare(K, items))) return rc;
+    }
+  NLPR_HIP_TRY(hipMalloc(&B.d_desc, n * sizeof(SceneDesc)));
+  NLPR_HIP_TRY(hipHostMalloc(&B.h_desc, n * sizeof(SceneDesc)));
+  NLPR_HIP_TRY(hipMalloc(&B.d_flag, 256));
+  NLPR_HIP_TRY(hipEventCreateWithFlags(&B.upload_ev, hipEventDisableTiming));
+  B.uploaded.resize(n);
+  B.desc_valid = false;
+  return NLPR_OK;
+}
+
+// Write the descriptors (sizes, tables, buffers) to the device if they changed.  The pinned
+// staging copy is rewritten only after the previous upload from it has completed.
+int upload_desc(Batch& B, const std::vector<SceneDesc>& descs, hipStream_t s) {
+  const size_t n = descs.size();
+  if (B.desc_valid && std::memcmp(B.uploaded.data(), descs.data(), n * sizeof(SceneDesc)) == 0)
+    return NLPR_OK;
+  NLPR_HIP_TRY(hipEventSynchronize(B.upload_ev));
+  std::memcpy(B.h_desc, descs.data(), n * sizeof(SceneDesc));
+  NLPR_HIP_TRY(hipMemcpyAsync(B.d_desc, B.h_desc, n * sizeof(SceneDesc), hipMemcpyHostToDevice, s));
+  NLPR_HIP_TRY(hipEventRecord(B.upload_ev, s));
+  std::memcpy(B.uploaded.data(), descs.data(), n * sizeof(SceneDesc));
+  B.desc_valid = true;
+  return NLPR_OK;
+}
+
+// Timing: events bracket each launch group when the batch was created with NLPR_TIMING.
 struct StageTimer {
-  Plan& P;
+  Batch& B;
   hipStream_t s;
   int stage;
   size_t a = 0;
   bool on = false;
-  StageTimer(Plan& p, hipStream_t st, int sg) : P(p), s(st), stage(sg) {
-    if (!P.timing || P.ev_used + 2 > P.ev_pool.size()) return;
-    a = P.ev_used;
-    if (hipEventRecord(P.ev_pool[a], s) == hipSuccess) {
+  StageTimer(Batch& b, hipStream_t st, int sg) : B(b), s(st), stage(sg) {
+    if (!B.timing || B.ev_used + 2 > B.ev_pool.size()) return;
+    a = B.ev_used;
+    if (hipEventRecord(B.ev_pool[a], s) == hipSuccess) {
       on = true;
-      P.ev_used += 2;
+      B.ev_used += 2;
     }
   }
   ~StageTimer() {
     if (!on) return;
-    hipEventRecord(P.ev_pool[a + 1], s);
-    P.recs.push_back({stage, a, a + 1});
+    hipEventRecord(B.ev_pool[a + 1], s);
+    B.recs.push_back({stage, a, a + 1});
   }
 };
 
-int ensure_events(Plan& P) {
-  if (!P.timing) return NLPR_OK;
-  const size_t need = 2 * (size_t)(6 * std::max(P.prm.iters, 1) + 16);
-  while (P.ev_pool.size() < need + P.ev_used) {
+int ensure_events(Batch& B) {
+  if (!B.timing) return NLPR_OK;
+  const size_t need = 2 * (size_t)(6 * std::max(B.iters, 1) + 16);
+  while (B.ev_pool.size() < need + B.ev_used) {
     hipEvent_t e;
     NLPR_HIP_TRY(hipEventCreate(&e));
-    P.ev_pool.push_back(e);
+    B.ev_pool.push_back(e);
   }
   return NLPR_OK;
 }
 
-template <typename T>
-T* region(void* ws, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+// The solve: weights, initial values, then per iteration the X-update, the blur, the
+// P/Lambda update, the sweep and the right-hand-side assembly.
+int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
+  int rc;
+  bool reg = false;
+  for (const Plan* P : B.scenes) reg = reg || P->npairs > 0;
+  {
+    StageTimer tm(B, s, NLPR_STAGE_WEIGHTS);
+    if ((rc = launch_weights(B, B_YH, B_MU, s))) return rc;
+  }
+  if (!resume) {
+    StageTimer tm(B, s, NLPR_STAGE_INIT);
+    // X0 into Z, W2 = P2 + Lambda2 = X0, Lambda = 0, W1 = P1 + Lambda1 = B X0, C = B^T W1 + W2
+    if ((rc = launch_init(B, B_YL, B_Z, B_L1, B_L2, B_W2, s))) return rc;
+    if ((rc = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return rc;
+    if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s))) return rc;
+  }
+  for (int t = 0; t < B.iters; ++t) {
+    {
+      StageTimer tm(B, s, NLPR_STAGE_XSOLVE);
+      if ((rc = launch_xsolve(B, B_C, B_Z, B_F, s))) return rc;
+    }
+    {
+      StageTimer tm(B, s, NLPR_STAGE_BLUR);
+      if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
+    }
+    {
+      StageTimer tm(B, s, NLPR_STAGE_PUPDATE);
+      if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
+    }
+    if (reg) {
+      const bool first = (t == 0 && !resume);
+      StageTimer tm(B, s, first ? NLPR_STAGE_SWEEP_FIRST : NLPR_STAGE_SWEEP);
+      if ((rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, first, s))) return rc;
+    }
+    {
+      StageTimer tm(B, s, NLPR_STAGE_ASSEMBLE);
+      if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
+    }
+  }
+  return NLPR_OK;
+}
+
+int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float* const* Z,
+                void* ws, size_t ws_bytes, hipStream_t s) {
+  const int n = (int)B.scenes.size();
+  int rc;
+  if ((rc = check_device_ptr(ws, "ws"))) return rc;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NLPR_ERR_INVALID_ARG, "ws must be 256-byte aligned");
+  if (ws_bytes < B.ws_bytes)
+    return fail(NLPR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than the required size");
+  std::vector<SceneDesc> descs(n);
+  for (int i = 0; i < n; ++i) {
+    if ((rc = check_device_ptr(Yl[i], "Yl")) || (rc = check_device_ptr(Yh[i], "Yh")) ||
+        (rc = check_device_ptr(Z[i], "Z")))
+      return rc;
+    const Plan& P = *B.scenes[i];
+    SceneDesc d = static_desc(P);
+    char* base = static_cast<char*>(ws) + B.base[i];
+    for (int k : {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO})
+      d.buf[k] = base + P.off[k];
+    d.buf[B_YL] = const_cast<float*>(Yl[i]);
+    d.buf[B_YH] = const_cast<float*>(Yh[i]);
+    d.buf[B_Z] = Z[i];
+    d.buf[B_TMP] = base + P.off[B_BX];
+    descs[i] = d;
+  }
+  DeviceGuard dg(B.device);
+  if ((rc = ensure_events(B))) return rc;
+  if ((rc = upload_desc(B, descs, s))) return rc;
+  const bool resume = (B.flags & NLPR_STATE_IN) != 0;
+  if (B.use_graph && !B.timing) {
+    const uint32_t key = (resume ? 1u : 0u) | ((uint32_t)B.iters << 1) | 0x80000000u;
+    if (!B.graph || B.graph_key != key) {
+      if (B.graph) {
+        hipGraphExecDestroy(B.graph);
+        B.graph = nullptr;
+      }
+      // capture on a private stream (the caller's may be the legacy default stream, which
+      // cannot be captured), then launch the instantiated graph on the caller's stream
+      hipStream_t cs;
+      NLPR_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        rc = enqueue_solve(B, resume, cs);
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+      }
+      hipStreamDestroy(cs);
+      if (rc || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        if (rc) return rc;
+        return fail(NLPR_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      }
+      e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        B.graph = nullptr;
+        return fail(NLPR_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+      B.graph_key = key;
+    }
+    NLPR_HIP_TRY(hipGraphLaunch(B.graph, s));
+  } else {
+    if ((rc = enqueue_solve(B, resume, s))) return rc;
+  }
+  if (B.flags & NLPR_CHECK_FINITE) {
+    if ((rc = launch_finite(B, B_Z, B.d_flag, s))) return rc;
+    int hflag = 0;
+    NLPR_HIP_TRY(hipMemcpyAsync(&hflag, B.d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    NLPR_HIP_TRY(hipStreamSynchronize(s));
+    if (hflag) return fail(NLPR_ERR_NUMERICAL, "NaN or Inf in Z");
+  }
+  return NLPR_OK;
+}
+
+int batch_stage_time(Batch& B, int stage, double* ms_total, int64_t* launches, int reset) {
+  if (!ms_total || !launches) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  if (!B.timing) return fail(NLPR_ERR_NOT_ENABLED, "created without NLPR_TIMING");
+  if (stage < 1 || stage >= NLPR_STAGE_COUNT) return fail(NLPR_ERR_INVALID_ARG, "unknown stage");
+  DeviceGuard dg(B.device);
+  for (const auto& r : B.recs) {
+    NLPR_HIP_TRY(hipEventSynchronize(B.ev_pool[r.b]));
+    float ms = 0.f;
+    NLPR_HIP_TRY(hipEventElapsedTime(&ms, B.ev_pool[r.a], B.ev_pool[r.b]));
+    B.acc_ms[r.stage] += ms;
+    B.acc_n[r.stage] += 1;
+  }
+  B.recs.clear();
+  B.ev_used = 0;
+  *ms_total = B.acc_ms[stage];
+  *launches = B.acc_n[stage];
+  if (reset) {
+    std::fill(std::begin(B.acc_ms), std::end(B.acc_ms), 0.0);
+    std::fill(std::begin(B.acc_n), std::end(B.acc_n), int64_t(0));
+  }
+  return NLPR_OK;
+}
+
+int region_of(const Plan& P, int region, size_t* offset, size_t* bytes) {
+  static const int slot_of[NLPR_REGION_COUNT] = {B_SIGMA, B_MU, B_C, B_L1, B_L2};
+  if (region < 0 || region >= NLPR_REGION_COUNT) return fail(NLPR_ERR_INVALID_ARG, "unknown workspace region");
+  *offset = P.off[slot_of[region]];
+  *bytes = P.sz[slot_of[region]];
+  return NLPR_OK;
+}
+
+// Create a batch from scene parameters (n >= 1).
+int batch_create(Batch& B, int n, const nlpr_params* params, const float* const* blur,
+                 const float* const* R) {
+  if (n < 1 || !params || !blur || !R) return fail(NLPR_ERR_INVALID_ARG, "NULL argument or n < 1");
+  const uint32_t bf = params[0].flags & kBatchFlags;
+  for (int i = 0; i < n; ++i) {
+    if (!blur[i] || !R[i]) return fail(NLPR_ERR_INVALID_ARG, "NULL blur taps or R");
+    if ((params[i].flags & kBatchFlags) != bf || params[i].iters != params[0].iters)
+      return fail(NLPR_ERR_INVALID_ARG,
+                  "scenes of a batch must share iters and the flags INIT_ZERO, STATE_IN, "
+                  "CHECK_FINITE, TIMING and GRAPH");
+    int rc = validate(params[i]);
+    if (rc) return rc;
+  }
+  if (hipGetDevice(&B.device) != hipSuccess) return fail(NLPR_ERR_HIP, "no HIP device");
+  B.flags = bf;
+  B.iters = params[0].iters;
+  B.timing = (bf & NLPR_TIMING) != 0;
+  B.use_graph = (bf & NLPR_GRAPH) != 0;
+  for (int i = 0; i < n; ++i) {
+    Plan* P = nullptr;
+    int rc = scene_create(params[i], blur[i], R[i], &P);
+    if (rc) {
+      batch_release(B);
+      return rc;
+    }
+    B.scenes.push_back(P);
+  }
+  int rc = batch_build(B);
+  if (!rc) rc = ensure_events(B);
+  if (rc) batch_release(B);
+  return rc;
 }
 
 }  // namespace
@@ -172,111 +598,32 @@ int nlpr_plan_create(const nlpr_params* params, const float* blur_host, const fl
   if (rc) return rc;
   nlpr_plan* h = new (std::nothrow) nlpr_plan();
   if (!h) return fail(NLPR_ERR_INVALID_ARG, "out of host memory");
-  Plan& P = h->P;
-  P.prm = *params;
-  P.timing = (params->flags & NLPR_TIMING) != 0;
-  if (hipGetDevice(&P.device) != hipSuccess) {
+  rc = batch_create(h->B, 1, params, &blur_host, &R_host);
+  if (rc) {
     delete h;
-    return fail(NLPR_ERR_HIP, "no HIP device");
+    return rc;
   }
-  const int p = P.prm.p, q = P.prm.q, L = P.prm.L, Lh = P.prm.Lh, r = P.prm.blur_radius;
-  // W+ in storage order: (0, 1..S), then tau1 = 1..S with tau2 = -S..S
-  if (P.prm.flags & NLPR_LOCAL_WINDOW) {
-    P.taus = {0, 1, 1, 0};
-  } else {
-    const int S = P.prm.Sw;
-    for (int b = 1; b <= S; ++b) { P.taus.push_back(0); P.taus.push_back(b); }
-    for (int a = 1; a <= S; ++a)
-      for (int b = -S; b <= S; ++b) { P.taus.push_back(a); P.taus.push_back(b); }
-  }
-  P.npairs = (int)P.taus.size() / 2;
-  P.npatch = (2 * P.prm.K + 1) * (2 * P.prm.K + 1);
-  int hrows = 0;
-  for (int n = 0; n < P.npairs; ++n) hrows = std::max(hrows, P.taus[2 * n]);
-  factor_23(p, P.fp);
-  factor_23(q, P.fq);
-  P.sweep = choose_sweep_shape(p, q, P.prm.K, hrows);
-
-  auto cleanup = [&](int code) {
-    free_plan(P);
-    delete h;
-    return code;
-  };
-  const size_t plane = (size_t)p * q;
-  if (hipMalloc(&P.d_taus, std::max<size_t>(1, P.npairs) * sizeof(int2)) != hipSuccess ||
-      hipMalloc(&P.d_invden, plane * sizeof(float)) != hipSuccess ||
-      hipMalloc(&P.d_tw_p, p * sizeof(float2)) != hipSuccess ||
-      hipMalloc(&P.d_tw_q, q * sizeof(float2)) != hipSuccess ||
-      hipMalloc(&P.d_blur, (2 * r + 1) * (2 * r + 1) * sizeof(float)) != hipSuccess ||
-      hipMalloc(&P.d_R, (size_t)L * Lh * sizeof(float)) != hipSuccess ||
-      hipMalloc(&P.d_G, (size_t)Lh * Lh * sizeof(float)) != hipSuccess) {
-    set_error("hipMalloc of plan tables failed");
-    return cleanup(NLPR_ERR_HIP);
-  }
-  P.fp.tw = P.d_tw_p;
-  P.fq.tw = P.d_tw_q;
-  if (P.npairs &&
-      hipMemcpy(P.d_taus, P.taus.data(), P.npairs * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
-    set_error("upload of the window failed");
-    return cleanup(NLPR_ERR_HIP);
-  }
-  if (hipMemcpy(P.d_blur, blur_host, (2 * r + 1) * (2 * r + 1) * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(P.d_R, R_host, (size_t)L * Lh * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-    set_error("upload of blur taps / R failed");
-    return cleanup(NLPR_ERR_HIP);
-  }
-  rc = launch_precompute(P, nullptr);
-  if (rc) return cleanup(rc);
-  if (hipDeviceSynchronize() != hipSuccess) {
-    set_error("plan precompute failed");
-    return cleanup(NLPR_ERR_HIP);
-  }
-  // workspace layout
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t o = off;
-    off = align256(off + bytes);
-    return o;
-  };
-  P.sz_plane = plane * L * sizeof(float);
-  P.sz_sigma = sweep_sigma_bytes(P.sweep, q, L, P.npairs, P.npatch);
-  P.sz_mu = (size_t)P.npairs * plane * sizeof(float);
-  P.sz_F = (size_t)((L + 1) / 2) * plane * sizeof(float2);
-  P.sz_halo = (size_t)L * P.sweep.ntiles * P.sweep.halo * q * sizeof(float);
-  P.off_sigma = take(P.sz_sigma);
-  P.off_mu = take(P.sz_mu);
-  P.off_C = take(P.sz_plane);
-  P.off_L1 = take(P.sz_plane);
-  P.off_L2 = take(P.sz_plane);
-  P.off_BX = take(P.sz_plane);
-  P.off_W1 = take(P.sz_plane);
-  P.off_W2 = take(P.sz_plane);
-  P.off_F = take(P.sz_F);
-  P.off_halo = take(std::max<size_t>(P.sz_halo, 4));
-  P.off_flag = take(256);
-  P.ws_bytes = off;
-  if (int e = ensure_events(P)) return cleanup(e);
   *out = h;
   return NLPR_OK;
 }
 
 int nlpr_plan_destroy(nlpr_plan* plan) {
   if (!plan) return NLPR_OK;
-  DeviceGuard g(plan->P.device);
-  free_plan(plan->P);
+  DeviceGuard g(plan->B.device);
+  batch_release(plan->B);
   delete plan;
   return NLPR_OK;
 }
 
 int nlpr_workspace_size(const nlpr_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
-  *bytes = plan->P.ws_bytes;
+  *bytes = plan->B.ws_bytes;
   return NLPR_OK;
 }
 
 int nlpr_half_window(const nlpr_plan* plan, int32_t* tau, int32_t cap, int32_t* n) {
   if (!plan || !n || (cap > 0 && !tau)) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
-  const Plan& P = plan->P;
+  const Plan& P = *plan->B.scenes[0];
   *n = P.npairs;
   for (int i = 0; i < std::min(cap, P.npairs); ++i) {
     tau[2 * i] = P.taus[2 * i];
@@ -287,176 +634,156 @@ int nlpr_half_window(const nlpr_plan* plan, int32_t* tau, int32_t cap, int32_t* 
 
 int nlpr_plan_get_info(const nlpr_plan* plan, nlpr_plan_info* info) {
   if (!plan || !info) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
-  const Plan& P = plan->P;
+  const Plan& P = *plan->B.scenes[0];
   info->npairs = P.npairs;
   info->npatch = P.npatch;
   info->tile_rows = P.sweep.rows;
   info->ntiles = P.sweep.ntiles;
   info->halo_rows = P.sweep.halo;
   info->reserved = 0;
-  info->sigma_elems = P.sz_sigma / sizeof(float);
+  info->sigma_elems = P.sz[B_SIGMA] / sizeof(float);
   return NLPR_OK;
 }
 
 int nlpr_workspace_region(const nlpr_plan* plan, int region, size_t* offset, size_t* bytes) {
   if (!plan || !offset || !bytes) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
-  const Plan& P = plan->P;
-  switch (region) {
-    case NLPR_REGION_SIGMA: *offset = P.off_sigma; *bytes = P.sz_sigma; break;
-    case NLPR_REGION_MU: *offset = P.off_mu; *bytes = P.sz_mu; break;
-    case NLPR_REGION_C: *offset = P.off_C; *bytes = P.sz_plane; break;
-    case NLPR_REGION_LAMBDA1: *offset = P.off_L1; *bytes = P.sz_plane; break;
-    case NLPR_REGION_LAMBDA2: *offset = P.off_L2; *bytes = P.sz_plane; break;
-    default: return fail(NLPR_ERR_INVALID_ARG, "unknown workspace region");
-  }
-  return NLPR_OK;
+  return region_of(*plan->B.scenes[0], region, offset, bytes);
 }
 
 int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void* ws,
                size_t ws_bytes, void* stream) {
   if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
-  Plan& P = plan->P;
-  int rc;
-  if ((rc = check_device_ptr(Yl, "Yl")) || (rc = check_device_ptr(Yh, "Yh")) ||
-      (rc = check_device_ptr(Z, "Z")) || (rc = check_device_ptr(ws, "ws")))
-    return rc;
-  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NLPR_ERR_INVALID_ARG, "ws must be 256-byte aligned");
-  if (ws_bytes < P.ws_bytes)
-    return fail(NLPR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than nlpr_workspace_size()");
-  DeviceGuard dg(P.device);
-  if ((rc = ensure_events(P))) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  float* sigma = region<float>(ws, P.off_sigma);
-  float* mu = region<float>(ws, P.off_mu);
-  float* C = region<float>(ws, P.off_C);
-  float* L1 = region<float>(ws, P.off_L1);
-  float* L2 = region<float>(ws, P.off_L2);
-  float* BX = region<float>(ws, P.off_BX);
-  float* W1 = region<float>(ws, P.off_W1);
-  float* W2 = region<float>(ws, P.off_W2);
-  float2* F = region<float2>(ws, P.off_F);
-  float* halo = region<float>(ws, P.off_halo);
-  const bool resume = (P.prm.flags & NLPR_STATE_IN) != 0;
-  const bool reg = P.npairs > 0;
-  {
-    StageTimer tm(P, s, NLPR_STAGE_WEIGHTS);
-    if ((rc = launch_weights(P, Yh, mu, s))) return rc;
-  }
-  if (!resume) {
-    StageTimer tm(P, s, NLPR_STAGE_INIT);
-    // X0 into Z, W2 = P2 + Lambda2 = X0, Lambda = 0, W1 = P1 + Lambda1 = B X0, C = B^T W1 + W2
-    if ((rc = launch_init(P, Yl, Z, L1, L2, W2, s))) return rc;
-    if ((rc = launch_conv(P, Z, W1, false, nullptr, nullptr, nullptr, s))) return rc;
-    if ((rc = launch_conv(P, W1, C, true, W2, nullptr, nullptr, s))) return rc;
-  }
-  for (int t = 0; t < P.prm.iters; ++t) {
-    {
-      StageTimer tm(P, s, NLPR_STAGE_XSOLVE);
-      if ((rc = launch_xsolve(P, C, Z, F, s))) return rc;
-    }
-    {
-      StageTimer tm(P, s, NLPR_STAGE_BLUR);
-      if ((rc = launch_conv(P, Z, BX, false, nullptr, nullptr, nullptr, s))) return rc;
-    }
-    {
-      StageTimer tm(P, s, NLPR_STAGE_PUPDATE);
-      if ((rc = launch_pupdate(P, Z, BX, Yl, Yh, L1, L2, W1, W2, s))) return rc;
-    }
-    if (reg) {
-      const bool first = (t == 0 && !resume);
-      StageTimer tm(P, s, first ? NLPR_STAGE_SWEEP_FIRST : NLPR_STAGE_SWEEP);
-      if ((rc = launch_sweep(P, Z, mu, sigma, C, halo, first, s))) return rc;
-    }
-    {
-      StageTimer tm(P, s, NLPR_STAGE_ASSEMBLE);
-      if ((rc = launch_conv(P, W1, C, true, W2, reg ? C : nullptr, reg ? halo : nullptr, s)))
-        return rc;
-    }
-  }
-  if (P.prm.flags & NLPR_CHECK_FINITE) {
-    int* flag = region<int>(ws, P.off_flag);
-    if ((rc = launch_check_finite(P, Z, flag, s))) return rc;
-    int hflag = 0;
-    NLPR_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    NLPR_HIP_TRY(hipStreamSynchronize(s));
-    if (hflag) return fail(NLPR_ERR_NUMERICAL, "NaN or Inf in Z");
-  }
-  return NLPR_OK;
+  return batch_solve(plan->B, &Yl, &Yh, &Z, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbufs, void* stream) {
   if (!plan || !bufs) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
-  Plan& P = plan->P;
+  Batch& B = plan->B;
+  const Plan& P = *B.scenes[0];
   static const int need[NLPR_STAGE_COUNT] = {0, 2, 3, 2, 2, 8, 5, 5, 4, 7};
   if (stage < 1 || stage >= NLPR_STAGE_COUNT) return fail(NLPR_ERR_INVALID_ARG, "unknown stage");
   if (nbufs < need[stage]) return fail(NLPR_ERR_INVALID_ARG, "too few buffers for the stage");
   int rc;
   for (int i = 0; i < need[stage]; ++i)
     if ((rc = check_device_ptr(bufs[i], "stage buffer"))) return rc;
-  DeviceGuard dg(P.device);
+  DeviceGuard dg(B.device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  auto f = [&](int i) { return static_cast<float*>(bufs[i]); };
+  SceneDesc d = static_desc(P);
+  auto put = [&](int slot, int i) { d.buf[slot] = bufs[i]; };
+  auto scratch = [&](int slot, int wsi, int region) {
+    d.buf[slot] = static_cast<char*>(bufs[wsi]) + P.off[region];
+  };
+  std::vector<SceneDesc> descs(1);
+  auto run = [&](auto&& body) -> int {
+    descs[0] = d;
+    int r2 = upload_desc(B, descs, s);
+    if (r2) return r2;
+    return body();
+  };
   switch (stage) {
     case NLPR_STAGE_WEIGHTS:
-      return launch_weights(P, f(0), f(1), s);
+      put(B_YH, 0); put(B_MU, 1);
+      return run([&] { return launch_weights(B, B_YH, B_MU, s); });
     case NLPR_STAGE_XSOLVE:
-      return launch_xsolve(P, f(0), f(1), region<float2>(bufs[2], P.off_F), s);
+      put(B_C, 0); put(B_Z, 1); scratch(B_F, 2, B_F);
+      return run([&] { return launch_xsolve(B, B_C, B_Z, B_F, s); });
     case NLPR_STAGE_BLUR:
-      return launch_conv(P, f(0), f(1), false, nullptr, nullptr, nullptr, s);
     case NLPR_STAGE_BLUR_T:
-      return launch_conv(P, f(0), f(1), true, nullptr, nullptr, nullptr, s);
+      put(B_Z, 0); put(B_BX, 1);
+      return run([&] { return launch_conv(B, B_Z, B_BX, stage == NLPR_STAGE_BLUR_T, -1, -1, -1, 0, s); });
     case NLPR_STAGE_PUPDATE:
-      return launch_pupdate(P, f(0), f(1), f(2), f(3), f(4), f(5), f(6), f(7), s);
+      put(B_Z, 0); put(B_BX, 1); put(B_YL, 2); put(B_YH, 3); put(B_L1, 4); put(B_L2, 5);
+      put(B_W1, 6); put(B_W2, 7);
+      return run([&] { return launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s); });
     case NLPR_STAGE_SWEEP:
-    case NLPR_STAGE_SWEEP_FIRST: {
-      if (P.npairs == 0) {
-        NLPR_HIP_TRY(hipMemsetAsync(f(3), 0, P.sz_plane, s));
-        return NLPR_OK;
-      }
-      float* halo = region<float>(bufs[4], P.off_halo);
-      float* tmp = region<float>(bufs[4], P.off_BX);
-      if ((rc = launch_sweep(P, f(0), f(1), f(2), tmp, halo, stage == NLPR_STAGE_SWEEP_FIRST, s)))
-        return rc;
-      // Creg = own-tile part + halo fold: a conv with a zero kernel would do it; use the
-      // assembly kernel on zero W1 instead (W1 region of the scratch workspace).
-      float* zero = region<float>(bufs[4], P.off_W1);
-      NLPR_HIP_TRY(hipMemsetAsync(zero, 0, P.sz_plane, s));
-      return launch_conv(P, zero, f(3), true, tmp, nullptr, halo, s);
-    }
+    case NLPR_STAGE_SWEEP_FIRST:
+      // Creg = the sweep's own-tile part (scratch TMP) + the folded halo rows, assembled by
+      // the B^T kernel over a zero image
+      put(B_Z, 0); put(B_MU, 1); put(B_SIGMA, 2); put(B_C, 3);
+      scratch(B_HALO, 4, B_HALO);
+      scratch(B_W1, 4, B_W1);
+      scratch(B_TMP, 4, B_BX);
+      return run([&] {
+        int r2;
+        if (P.npairs == 0) return launch_fill(B, B_C, s);
+        if ((r2 = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_TMP, B_HALO,
+                               stage == NLPR_STAGE_SWEEP_FIRST, s)))
+          return r2;
+        if ((r2 = launch_fill(B, B_W1, s))) return r2;
+        return launch_conv(B, B_W1, B_C, true, B_TMP, -1, B_HALO, 1, s);
+      });
     case NLPR_STAGE_ASSEMBLE:
-      return launch_conv(P, f(0), f(3), true, f(1), f(2), nullptr, s);
-    case NLPR_STAGE_INIT: {
-      if ((rc = launch_init(P, f(0), f(1), f(4), f(5), f(3), s))) return rc;
-      if ((rc = launch_conv(P, f(1), f(2), false, nullptr, nullptr, nullptr, s))) return rc;
-      return launch_conv(P, f(2), f(6), true, f(3), nullptr, nullptr, s);
-    }
+      put(B_W1, 0); put(B_W2, 1); put(B_TMP, 2); put(B_C, 3);
+      return run([&] { return launch_conv(B, B_W1, B_C, true, B_W2, B_TMP, -1, 0, s); });
+    case NLPR_STAGE_INIT:
+      put(B_YL, 0); put(B_Z, 1); put(B_W1, 2); put(B_W2, 3); put(B_L1, 4); put(B_L2, 5);
+      put(B_C, 6);
+      return run([&] {
+        int r2;
+        if ((r2 = launch_init(B, B_YL, B_Z, B_L1, B_L2, B_W2, s))) return r2;
+        if ((r2 = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return r2;
+        return launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s);
+      });
     default:
       return fail(NLPR_ERR_INVALID_ARG, "unknown stage");
   }
 }
 
 int nlpr_stage_time(nlpr_plan* plan, int stage, double* ms_total, int64_t* launches, int reset) {
-  if (!plan || !ms_total || !launches) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
-  Plan& P = plan->P;
-  if (!P.timing) return fail(NLPR_ERR_NOT_ENABLED, "plan created without NLPR_TIMING");
-  if (stage < 1 || stage >= NLPR_STAGE_COUNT) return fail(NLPR_ERR_INVALID_ARG, "unknown stage");
-  DeviceGuard dg(P.device);
-  for (const auto& r : P.recs) {
-    NLPR_HIP_TRY(hipEventSynchronize(P.ev_pool[r.b]));
-    float ms = 0.f;
-    NLPR_HIP_TRY(hipEventElapsedTime(&ms, P.ev_pool[r.a], P.ev_pool[r.b]));
-    P.acc_ms[r.stage] += ms;
-    P.acc_n[r.stage] += 1;
+  if (!plan) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  return batch_stage_time(plan->B, stage, ms_total, launches, reset);
+}
+
+// ------------------------------------------------------------------------------ batch
+int nlpr_batch_create(int32_t n, const nlpr_params* params, const float* const* blur_host,
+                      const float* const* R_host, nlpr_batch** out) {
+  if (!out) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  nlpr_batch* h = new (std::nothrow) nlpr_batch();
+  if (!h) return fail(NLPR_ERR_INVALID_ARG, "out of host memory");
+  int rc = batch_create(h->B, n, params, blur_host, R_host);
+  if (rc) {
+    delete h;
+    return rc;
   }
-  P.recs.clear();
-  P.ev_used = 0;
-  *ms_total = P.acc_ms[stage];
-  *launches = P.acc_n[stage];
-  if (reset) {
-    std::fill(std::begin(P.acc_ms), std::end(P.acc_ms), 0.0);
-    std::fill(std::begin(P.acc_n), std::end(P.acc_n), int64_t(0));
-  }
+  *out = h;
   return NLPR_OK;
+}
+
+int nlpr_batch_destroy(nlpr_batch* batch) {
+  if (!batch) return NLPR_OK;
+  DeviceGuard g(batch->B.device);
+  batch_release(batch->B);
+  delete batch;
+  return NLPR_OK;
+}
+
+int nlpr_batch_workspace_size(const nlpr_batch* batch, size_t* bytes) {
+  if (!batch || !bytes) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  *bytes = batch->B.ws_bytes;
+  return NLPR_OK;
+}
+
+int nlpr_batch_region(const nlpr_batch* batch, int32_t scene, int region, size_t* offset,
+                      size_t* bytes) {
+  if (!batch || !offset || !bytes) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  const Batch& B = batch->B;
+  if (scene < 0 || scene >= (int)B.scenes.size()) return fail(NLPR_ERR_INVALID_ARG, "scene index out of range");
+  int rc = region_of(*B.scenes[scene], region, offset, bytes);
+  if (!rc) *offset += B.base[scene];
+  return rc;
+}
+
+int nlpr_batch_solve(nlpr_batch* batch, const float* const* Yl, const float* const* Yh,
+                     float* const* Z, void* ws, size_t ws_bytes, void* stream) {
+  if (!batch || !Yl || !Yh || !Z) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  return batch_solve(batch->B, Yl, Yh, Z, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int nlpr_batch_stage_time(nlpr_batch* batch, int stage, double* ms_total, int64_t* launches,
+                          int reset) {
+  if (!batch) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  return batch_stage_time(batch->B, stage, ms_total, launches, reset);
 }
 
 }  // extern "C"

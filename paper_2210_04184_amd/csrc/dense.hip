@@ -8,6 +8,8 @@
 //                the sweep (assembles C of eq. (x_linear_system_main))
 //   pupdate    : P1 (eq. (Qh_update)), P2 (eq. (Qm_update)) and the duals Lambda1, Lambda2
 //                (eqs. (dualvar1_main), (dualvar2_main))
+// All but the precompute run over a batch of scenes (see nlpr_internal.h).
+#include <algorithm>
 #include <cmath>
 
 #include "nlpr_internal.h"
@@ -20,6 +22,12 @@ __device__ __forceinline__ int wrapi(int x, int n) {
   return x < 0 ? x + n : x;
 }
 
+template <typename T>
+__device__ __forceinline__ T* slot(const SceneDesc& S, int k) {
+  return k < 0 ? nullptr : static_cast<T*>(S.buf[k]);
+}
+
+// ------------------------------------------------------------------------- precompute
 // tw[m] = exp(-2 pi i m / n), in FP64, stored FP32.
 __global__ void twiddle_kernel(float2* tw, int n) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -101,35 +109,41 @@ __global__ void g_kernel(const float* R, int L, int Lh, double ratio, float* G) 
 
 // ---------------------------------------------------------------------------- weights
 // mu_{i tau} = scale * exp(-inv_h2 * sum_{k in P} e_tau(i - k)),
-// e_tau(j) = sum_c (Y_c(j) - Y_c(j - tau))^2, for tau = taus[blockIdx.z].
-// Tile 16 x 64 per block; e on the tile plus a K halo, then separable box sums in LDS.
+// e_tau(j) = sum_c (Y_c(j) - Y_c(j - tau))^2.  Local block = (shift, tile row, tile col);
+// 16 x 64 tile, e on the tile plus a K halo, then separable box sums in LDS.
 constexpr int WT_Y = 16, WT_X = 64;
 __global__ void __launch_bounds__(256)
-weights_kernel(const float* __restrict__ Yh, float* __restrict__ mu, int p, int q, int Lh, int K,
-               const int2* __restrict__ taus, float scale, float inv_h2, int unweighted) {
+weights_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yh_s,
+               int mu_s) {
   extern __shared__ float wsh[];
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, K = S.K, Lh = S.Lh;
+  const int gx = ceil_div(q, WT_X), gy = ceil_div(p, WT_Y);
+  const int n = it.y / (gx * gy);
+  const int rem = it.y - n * gx * gy;
+  const int y0 = (rem / gx) * WT_Y, x0 = (rem % gx) * WT_X;
   const int EY = WT_Y + 2 * K, EX = WT_X + 2 * K;
   float* e = wsh;             // EY x EX
   float* hs = wsh + EY * EX;  // EY x WT_X
-  const int x0 = blockIdx.x * WT_X, y0 = blockIdx.y * WT_Y;
-  const int n = blockIdx.z;
-  const int2 t = taus[n];
-  float* mun = mu + (size_t)n * p * q;
-  if (unweighted) {
+  const int2 t = S.taus[n];
+  const float* Yh = slot<const float>(S, yh_s);
+  float* mun = slot<float>(S, mu_s) + (size_t)n * p * q;
+  if (S.unweighted) {
     for (int idx = threadIdx.x; idx < WT_Y * WT_X; idx += blockDim.x) {
       const int y = y0 + idx / WT_X, x = x0 + idx % WT_X;
-      if (y < p && x < q) mun[(size_t)y * q + x] = scale;
+      if (y < p && x < q) mun[(size_t)y * q + x] = S.mu_scale;
     }
     return;
   }
   const size_t plane = (size_t)p * q;
   for (int idx = threadIdx.x; idx < EY * EX; idx += blockDim.x) {
     const int yy = idx / EX, xx = idx % EX;
-    const int gy = wrapi(y0 - K + yy, p), gx = wrapi(x0 - K + xx, q);
-    const int sy = wrapi(gy - t.x, p), sx = wrapi(gx - t.y, q);
+    const int gyy = wrapi(y0 - K + yy, p), gxx = wrapi(x0 - K + xx, q);
+    const int sy = wrapi(gyy - t.x, p), sx = wrapi(gxx - t.y, q);
     float acc = 0.f;
     for (int c = 0; c < Lh; ++c) {
-      const float dlt = Yh[c * plane + (size_t)gy * q + gx] - Yh[c * plane + (size_t)sy * q + sx];
+      const float dlt = Yh[c * plane + (size_t)gyy * q + gxx] - Yh[c * plane + (size_t)sy * q + sx];
       acc += dlt * dlt;
     }
     e[idx] = acc;
@@ -146,80 +160,124 @@ weights_kernel(const float* __restrict__ Yh, float* __restrict__ mu, int p, int 
     const int y = idx / WT_X, x = idx % WT_X;
     float acc = 0.f;
     for (int dy = 0; dy <= 2 * K; ++dy) acc += hs[(y + dy) * WT_X + x];
-    if (y0 + y < p && x0 + x < q) mun[(size_t)(y0 + y) * q + x0 + x] = scale * expf(-acc * inv_h2);
+    if (y0 + y < p && x0 + x < q)
+      mun[(size_t)(y0 + y) * q + x0 + x] = S.mu_scale * expf(-acc * S.inv_h2);
   }
 }
 
-// ------------------------------------------------------------------------------- init
-__global__ void init_kernel(const float* __restrict__ Yl, float* __restrict__ X0,
-                            float* __restrict__ L1, float* __restrict__ L2,
-                            float* __restrict__ W2, int p, int q, int L, int d, int zero) {
-  const size_t total = (size_t)L * p * q;
-  const int qd = q / d, pd = p / d;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / ((size_t)p * q));
-    const int rem = (int)(e - (size_t)c * p * q);
-    const int i1 = rem / q, i2 = rem - i1 * q;
-    const float x = zero ? 0.f : Yl[((size_t)c * pd + i1 / d) * qd + i2 / d];
-    X0[e] = x;
-    W2[e] = x;
-    L1[e] = 0.f;
-    L2[e] = 0.f;
-  }
+// ------------------------------------------------------------------ elementwise planes
+// One thread per element of [L][p][q]; local block lb covers elements lb*256 .. +255.
+__global__ void __launch_bounds__(256)
+init_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yl_s, int x0_s,
+            int l1_s, int l2_s, int w2_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, d = S.d;
+  const size_t e = (size_t)it.y * 256 + threadIdx.x;
+  if (e >= (size_t)S.L * p * q) return;
+  const int c = (int)(e / ((size_t)p * q));
+  const int rem = (int)(e - (size_t)c * p * q);
+  const int i1 = rem / q, i2 = rem - i1 * q;
+  const float* Yl = slot<const float>(S, yl_s);
+  const float x = S.init_zero ? 0.f : Yl[((size_t)c * (p / d) + i1 / d) * (q / d) + i2 / d];
+  slot<float>(S, x0_s)[e] = x;
+  slot<float>(S, w2_s)[e] = x;
+  slot<float>(S, l1_s)[e] = 0.f;
+  slot<float>(S, l2_s)[e] = 0.f;
 }
+
+__global__ void __launch_bounds__(256)
+fill_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int s_) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const size_t e = (size_t)it.y * 256 + threadIdx.x;
+  if (e < (size_t)S.L * S.p * S.q) slot<float>(S, s_)[e] = 0.f;
+}
+
+// flag[0] |= 1 if any element of the slot is NaN or Inf (the flag is cleared beforehand by
+// a one-thread launch, so no memset is recorded into a captured graph)
+__global__ void __launch_bounds__(256)
+finite_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int z_s,
+              int* flag) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const size_t e = (size_t)it.y * 256 + threadIdx.x;
+  if (e < (size_t)S.L * S.p * S.q && !isfinite(slot<const float>(S, z_s)[e])) flag[0] = 1;
+}
+
+__global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
 
 // ------------------------------------------------------------------------------- conv
 // out(i) = sum_m b(m) in(i - m)      (B, circular convolution)        TR = false
 // out(i) = sum_m b(m) in(i + m)      (B^T, circular correlation)      TR = true
 // then out += add1 + add2 + halo fold (each optional).  The halo fold adds the part of the
-// regulariser term that the sweep kernel scattered above its tile: halo row h of tile t
-// (rows t*tile_rows .. ) belongs to image row (t*tile_rows - hrows + h) mod p.
+// regulariser term that the sweep scattered above its tile: halo row h of tile t belongs
+// to image row (t * rows - halo + h) mod p.  Bit 0 / bit 1 of reg_mask mark add1 / add2 as
+// regulariser terms; they and the halo are skipped for scenes without a search window,
+// whose sweep never runs.  Local block = (band, tile row, tile col), tile
+// 16 x 64; each thread produces 4 consecutive outputs of one row, reusing the LDS row it
+// reads for all 4.
 constexpr int CV_Y = 16, CV_X = 64;
 template <bool TR>
 __global__ void __launch_bounds__(256)
-conv_kernel(const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ taps,
-            int r, int p, int q, const float* __restrict__ add1, const float* __restrict__ add2,
-            const float* __restrict__ halo, int hrows, int tile_rows, int ntiles) {
+conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int in_s, int out_s,
+            int add1_s, int add2_s, int halo_s, int reg_mask) {
   extern __shared__ float csh[];
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, r = S.r;
+  const int gx = ceil_div(q, CV_X), gy = ceil_div(p, CV_Y);
+  const int c = it.y / (gx * gy);
+  const int rem = it.y - c * gx * gy;
+  const int y0 = (rem / gx) * CV_Y, x0 = (rem % gx) * CV_X;
   const int w = 2 * r + 1;
   const int TY = CV_Y + 2 * r, TX = CV_X + 2 * r;
   float* tile = csh;
   float* tp = csh + TY * TX;
-  const int x0 = blockIdx.x * CV_X, y0 = blockIdx.y * CV_Y, c = blockIdx.z;
   const size_t plane = (size_t)p * q;
-  const float* inc = in + (size_t)c * plane;
-  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) tp[idx] = taps[idx];
+  const float* inc = slot<const float>(S, in_s) + (size_t)c * plane;
+  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) tp[idx] = S.blur[idx];
   for (int idx = threadIdx.x; idx < TY * TX; idx += blockDim.x) {
     const int yy = idx / TX, xx = idx % TX;
     tile[idx] = inc[(size_t)wrapi(y0 - r + yy, p) * q + wrapi(x0 - r + xx, q)];
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < CV_Y * CV_X; idx += blockDim.x) {
-    const int y = idx / CV_X, x = idx % CV_X;
-    const int gy = y0 + y, gx = x0 + x;
-    if (gy >= p || gx >= q) continue;
-    float acc = 0.f;
-    for (int m1 = -r; m1 <= r; ++m1) {
-      const int ty = TR ? (y + r + m1) : (y + r - m1);
-      for (int m2 = -r; m2 <= r; ++m2) {
-        const int tx = TR ? (x + r + m2) : (x + r - m2);
-        acc += tp[(m1 + r) * w + (m2 + r)] * tile[ty * TX + tx];
+  const int y = threadIdx.x >> 4;            // 16 rows
+  const int xb = (threadIdx.x & 15) * 4;     // 4 outputs per thread
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int m1 = -r; m1 <= r; ++m1) {
+    const float* trow = tile + (TR ? (y + r + m1) : (y + r - m1)) * TX + xb;
+    const float* tap = tp + (m1 + r) * w;
+    for (int m2 = -r; m2 <= r; ++m2) {
+      const float b = tap[m2 + r];
+      const int o = TR ? (r + m2) : (r - m2);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += b * trow[o + e];
+    }
+  }
+  const int gy2 = y0 + y;
+  if (gy2 >= p) return;
+  const bool reg = S.npairs > 0;
+  const float* a1 = (reg || !(reg_mask & 1)) ? slot<const float>(S, add1_s) : nullptr;
+  const float* a2 = (reg || !(reg_mask & 2)) ? slot<const float>(S, add2_s) : nullptr;
+  const float* hb = reg ? slot<const float>(S, halo_s) : nullptr;
+  float* out = slot<float>(S, out_s);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int gx2 = x0 + xb + e;
+    if (gx2 >= q) continue;
+    const size_t o = (size_t)c * plane + (size_t)gy2 * q + gx2;
+    float v = acc[e];
+    if (a1) v += a1[o];
+    if (a2) v += a2[o];
+    if (hb) {
+      const int H = S.halo, R = S.rows;
+      for (int h = 0; h < H; ++h) {
+        const int r0 = wrapi(gy2 + H - h, p);
+        if (r0 % R == 0) v += hb[(((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx2];
       }
     }
-    const size_t o = (size_t)c * plane + (size_t)gy * q + gx;
-    if (add1) acc += add1[o];
-    if (add2) acc += add2[o];
-    if (halo) {
-      for (int h = 0; h < hrows; ++h) {
-        const int r0 = wrapi(gy + hrows - h, p);
-        if (r0 % tile_rows == 0) {
-          const int t = r0 / tile_rows;
-          acc += halo[(((size_t)c * ntiles + t) * hrows + h) * q + gx];
-        }
-      }
-    }
-    out[o] = acc;
+    out[o] = v;
   }
 }
 
@@ -237,14 +295,25 @@ conv_kernel(const float* __restrict__ in, float* __restrict__ out, const float* 
 //   Lambda1 -= BX - P1,  Lambda2 -= X - P2;  W1 = P1 + Lambda1,  W2 = P2 + Lambda2
 template <int LHM>
 __global__ void __launch_bounds__(256)
-pupdate_kernel(const float* __restrict__ X, const float* __restrict__ BX,
-               const float* __restrict__ Yl, const float* __restrict__ Yh,
-               float* __restrict__ L1, float* __restrict__ L2, float* __restrict__ W1,
-               float* __restrict__ W2, const float* __restrict__ R, const float* __restrict__ G,
-               int p, int q, int L, int Lh, int d, float rho, float inv_1prho) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
+               int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1_s, int w2_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, L = S.L, Lh = S.Lh, d = S.d;
+  const int j = it.y * 256 + threadIdx.x;
   const size_t plane = (size_t)p * q;
   if (j >= (int)plane) return;
+  const float* X = slot<const float>(S, x_s);
+  const float* BX = slot<const float>(S, bx_s);
+  const float* Yl = slot<const float>(S, yl_s);
+  const float* Yh = slot<const float>(S, yh_s);
+  float* L1 = slot<float>(S, l1_s);
+  float* L2 = slot<float>(S, l2_s);
+  float* W1 = slot<float>(S, w1_s);
+  float* W2 = slot<float>(S, w2_s);
+  const float* R = S.R;
+  const float* G = S.G;
+  const float rho = S.rho, inv_1prho = S.inv_1prho;
   const int i1 = j / q, i2 = j - i1 * q;
   const bool sampled = (i1 % d == 0) && (i2 % d == 0);
   const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
@@ -252,15 +321,13 @@ pupdate_kernel(const float* __restrict__ X, const float* __restrict__ BX,
   float res[LHM];
 #pragma unroll
   for (int h = 0; h < LHM; ++h) res[h] = (h < Lh) ? Yh[h * plane + j] : 0.f;
-  // res = Y_h - A0 R
-  for (int c = 0; c < L; ++c) {
+  for (int c = 0; c < L; ++c) {           // res = Y_h - A0 R
     const float a0 = X[c * plane + j] - L2[c * plane + j];
 #pragma unroll
     for (int h = 0; h < LHM; ++h)
       if (h < Lh) res[h] -= a0 * R[c * Lh + h];
   }
-  // u = res G
-  float u[LHM];
+  float u[LHM];                        // u = res G
 #pragma unroll
   for (int h2 = 0; h2 < LHM; ++h2) {
     float s = 0.f;
@@ -288,97 +355,102 @@ pupdate_kernel(const float* __restrict__ X, const float* __restrict__ BX,
   }
 }
 
-__global__ void finite_kernel(const float* __restrict__ Z, size_t n, int* flag) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (size_t)gridDim.x * blockDim.x) {
-    if (!isfinite(Z[e])) {
-      flag[0] = 1;
-      return;
-    }
+template <typename Kern, typename... Args>
+int launch_groups(const Batch& B, Kind kind, const char* name, Kern kern, hipStream_t s,
+                  Args... args) {
+  for (const Group& g : B.groups[kind]) {
+    if (g.nitems == 0) continue;
+    hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(g.block), g.lds, s, B.d_desc, g.d_items,
+                       args...);
+    NLPR_LAUNCH_CHECK(name);
   }
+  return NLPR_OK;
 }
 
 }  // namespace
 
-int launch_precompute(Plan& P, hipStream_t s) {
+// --------------------------------------------------------------------- work-item counts
+int weights_blocks(const Plan& P) {
+  return ceil_div(P.prm.q, WT_X) * ceil_div(P.prm.p, WT_Y) * P.npairs;
+}
+size_t weights_lds(const Plan& P) {
+  const int K = P.prm.K;
+  return (size_t)((WT_Y + 2 * K) * (WT_X + 2 * K) + (WT_Y + 2 * K) * WT_X) * sizeof(float);
+}
+int plane_blocks(const Plan& P) {
+  return (int)(((size_t)P.prm.L * P.prm.p * P.prm.q + 255) / 256);
+}
+int conv_blocks(const Plan& P) {
+  return ceil_div(P.prm.q, CV_X) * ceil_div(P.prm.p, CV_Y) * P.prm.L;
+}
+size_t conv_lds(const Plan& P) {
+  const int r = P.prm.blur_radius;
+  return (size_t)((CV_Y + 2 * r) * (CV_X + 2 * r) + (2 * r + 1) * (2 * r + 1)) * sizeof(float);
+}
+int pixel_blocks(const Plan& P) { return ceil_div(P.prm.p * P.prm.q, 256); }
+
+// ---------------------------------------------------------------------------- launches
+int launch_precompute(Plan& P) {
   const int p = P.prm.p, q = P.prm.q;
-  hipLaunchKernelGGL(twiddle_kernel, dim3(ceil_div(p, 256)), dim3(256), 0, s, P.d_tw_p, p);
+  hipLaunchKernelGGL(twiddle_kernel, dim3(ceil_div(p, 256)), dim3(256), 0, nullptr, P.d_tw_p, p);
   NLPR_LAUNCH_CHECK("twiddle_kernel");
-  hipLaunchKernelGGL(twiddle_kernel, dim3(ceil_div(q, 256)), dim3(256), 0, s, P.d_tw_q, q);
+  hipLaunchKernelGGL(twiddle_kernel, dim3(ceil_div(q, 256)), dim3(256), 0, nullptr, P.d_tw_q, q);
   NLPR_LAUNCH_CHECK("twiddle_kernel");
-  hipLaunchKernelGGL(den_kernel, dim3(ceil_div(q, 128), p), dim3(128), 0, s, P.d_invden, p, q,
-                     P.d_blur, P.prm.blur_radius, P.d_taus, P.npairs, P.npatch);
+  hipLaunchKernelGGL(den_kernel, dim3(ceil_div(q, 128), p), dim3(128), 0, nullptr, P.d_invden, p,
+                     q, P.d_blur, P.prm.blur_radius, P.d_taus, P.npairs, P.npatch);
   NLPR_LAUNCH_CHECK("den_kernel");
-  hipLaunchKernelGGL(g_kernel, dim3(1), dim3(1), 0, s, P.d_R, P.prm.L, P.prm.Lh,
+  hipLaunchKernelGGL(g_kernel, dim3(1), dim3(1), 0, nullptr, P.d_R, P.prm.L, P.prm.Lh,
                      P.prm.rho / P.prm.lambda1, P.d_G);
   NLPR_LAUNCH_CHECK("g_kernel");
   return NLPR_OK;
 }
 
-int launch_weights(const Plan& P, const float* Yh, float* mu, hipStream_t s) {
-  if (P.npairs == 0) return NLPR_OK;
-  const int p = P.prm.p, q = P.prm.q, K = P.prm.K;
-  const size_t lds = (size_t)((WT_Y + 2 * K) * (WT_X + 2 * K) + (WT_Y + 2 * K) * WT_X) * sizeof(float);
-  const float scale = (float)(P.prm.lambda / P.prm.rho);
-  const float inv_h2 = (P.prm.flags & NLPR_UNWEIGHTED) ? 0.f : (float)(1.0 / (P.prm.h * P.prm.h));
-  dim3 grid(ceil_div(q, WT_X), ceil_div(p, WT_Y), P.npairs);
-  hipLaunchKernelGGL(weights_kernel, grid, dim3(256), lds, s, Yh, mu, p, q, P.prm.Lh, K, P.d_taus,
-                     scale, inv_h2, (P.prm.flags & NLPR_UNWEIGHTED) ? 1 : 0);
-  NLPR_LAUNCH_CHECK("weights_kernel");
-  return NLPR_OK;
+int launch_weights(const Batch& B, int yh, int mu, hipStream_t s) {
+  return launch_groups(B, KD_WEIGHTS, "weights_kernel", weights_kernel, s, yh, mu);
 }
 
-int launch_init(const Plan& P, const float* Yl, float* X0, float* Lam1, float* Lam2, float* W2,
-                hipStream_t s) {
-  const size_t total = (size_t)P.prm.L * P.prm.p * P.prm.q;
-  const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, Yl, X0, Lam1, Lam2, W2, P.prm.p,
-                     P.prm.q, P.prm.L, P.prm.d, (P.prm.flags & NLPR_INIT_ZERO) ? 1 : 0);
-  NLPR_LAUNCH_CHECK("init_kernel");
-  return NLPR_OK;
+int launch_init(const Batch& B, int yl, int x0, int l1, int l2, int w2, hipStream_t s) {
+  return launch_groups(B, KD_PLANE, "init_kernel", init_kernel, s, yl, x0, l1, l2, w2);
 }
 
-int launch_conv(const Plan& P, const float* in, float* out, bool transpose, const float* add1,
-                const float* add2, const float* halo, hipStream_t s) {
-  const int p = P.prm.p, q = P.prm.q, r = P.prm.blur_radius;
-  const size_t lds = (size_t)((CV_Y + 2 * r) * (CV_X + 2 * r) + (2 * r + 1) * (2 * r + 1)) * sizeof(float);
-  dim3 grid(ceil_div(q, CV_X), ceil_div(p, CV_Y), P.prm.L);
-  const int hrows = halo ? P.sweep.halo : 0;
+int launch_fill(const Batch& B, int slot_, hipStream_t s) {
+  return launch_groups(B, KD_PLANE, "fill_kernel", fill_kernel, s, slot_);
+}
+
+int launch_finite(const Batch& B, int z, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+  NLPR_LAUNCH_CHECK("clear_flag_kernel");
+  return launch_groups(B, KD_PLANE, "finite_kernel", finite_kernel, s, z, flag);
+}
+
+int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int add2, int halo,
+                int reg_mask, hipStream_t s) {
   if (transpose)
-    hipLaunchKernelGGL(conv_kernel<true>, grid, dim3(256), lds, s, in, out, P.d_blur, r, p, q, add1,
-                       add2, halo, hrows, P.sweep.rows, P.sweep.ntiles);
-  else
-    hipLaunchKernelGGL(conv_kernel<false>, grid, dim3(256), lds, s, in, out, P.d_blur, r, p, q,
-                       add1, add2, halo, hrows, P.sweep.rows, P.sweep.ntiles);
-  NLPR_LAUNCH_CHECK("conv_kernel");
-  return NLPR_OK;
+    return launch_groups(B, KD_CONV, "conv_kernel<T>", conv_kernel<true>, s, in, out, add1, add2,
+                         halo, reg_mask);
+  return launch_groups(B, KD_CONV, "conv_kernel", conv_kernel<false>, s, in, out, add1, add2, halo,
+                       reg_mask);
 }
 
-int launch_pupdate(const Plan& P, const float* X, const float* BX, const float* Yl,
-                   const float* Yh, float* Lam1, float* Lam2, float* W1, float* W2,
+int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,
                    hipStream_t s) {
-  const int p = P.prm.p, q = P.prm.q;
-  const int n = p * q;
-  const float rho = (float)P.prm.rho;
-  const float inv = (float)(1.0 / (1.0 + P.prm.rho));
-  dim3 grid(ceil_div(n, 256));
-#define NLPR_PU(LHM)                                                                         \
-  hipLaunchKernelGGL(pupdate_kernel<LHM>, grid, dim3(256), 0, s, X, BX, Yl, Yh, Lam1, Lam2, W1, \
-                     W2, P.d_R, P.d_G, p, q, P.prm.L, P.prm.Lh, P.prm.d, rho, inv)
-  if (P.prm.Lh == 1) NLPR_PU(1);
-  else if (P.prm.Lh <= 4) NLPR_PU(4);
-  else NLPR_PU(16);
-#undef NLPR_PU
-  NLPR_LAUNCH_CHECK("pupdate_kernel");
+  // one launch per guide-band class (key0 = 1, 4 or 16 register slots)
+  for (const Group& g : B.groups[KD_PIXEL]) {
+    if (!g.nitems) continue;
+    if (g.key0 == 1)
+      hipLaunchKernelGGL(pupdate_kernel<1>, dim3(g.nitems), dim3(g.block), 0, s, B.d_desc,
+                         g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
+    else if (g.key0 == 4)
+      hipLaunchKernelGGL(pupdate_kernel<4>, dim3(g.nitems), dim3(g.block), 0, s, B.d_desc,
+                         g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
+    else
+      hipLaunchKernelGGL(pupdate_kernel<kMaxLh>, dim3(g.nitems), dim3(g.block), 0, s, B.d_desc,
+                         g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
+    NLPR_LAUNCH_CHECK("pupdate_kernel");
+  }
   return NLPR_OK;
 }
 
-int launch_check_finite(const Plan& P, const float* Z, int* flag, hipStream_t s) {
-  const size_t n = (size_t)P.prm.L * P.prm.p * P.prm.q;
-  NLPR_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
-  hipLaunchKernelGGL(finite_kernel, dim3(1024), dim3(256), 0, s, Z, n, flag);
-  NLPR_LAUNCH_CHECK("finite_kernel");
-  return NLPR_OK;
-}
+int lh_class(int Lh) { return Lh == 1 ? 1 : (Lh <= 4 ? 4 : kMaxLh); }
 
 }  // namespace nlpr

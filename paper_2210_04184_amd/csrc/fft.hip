@@ -11,10 +11,17 @@
 //   cols_solve : forward DFT along columns, multiply by 1/(den p q), inverse DFT along
 //                columns (the column data stays in LDS between the two transforms)
 //   rows_inv   : inverse DFT along rows, unpack the two bands
+// Every pass runs over a batch of scenes (see nlpr_internal.h); lines per block and columns
+// per block are picked per image size by timing candidates when a plan is created.
 // Each 1-D transform is a Stockham autosort FFT (mixed radix 2/3/4/8) staged in LDS:
 // every stage reads R values strided by n/R, twiddles them, does an R-point DFT and writes
 // them to their natural-order position, so no bit reversal is needed.  Twiddles come from
 // a table computed in FP64.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "nlpr_internal.h"
 
 namespace nlpr {
@@ -140,15 +147,19 @@ __device__ void fft_line(float2* buf, const LineFFT& f, int t, int tpl) {
   }
 }
 
-// Pack bands (2m, 2m+1) of C, forward DFT along rows.  grid (ceil(p / lpb), pairs).
-__global__ void fft_rows_fwd(const float* __restrict__ C, float2* __restrict__ F, int p, int q,
-                             int L, LineFFT fq, int tpl, int lpb) {
+// Pack bands (2m, 2m+1) of C, forward DFT along rows.  Local block = (pair, row block).
+__global__ void fft_rows_fwd(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
+                             int c_s, int f_s) {
   extern __shared__ float2 sh[];
-  const int m = blockIdx.y;
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, L = S.L, lpb = S.fq_lpb, tpl = S.fq_tpl;
+  const int nrb = ceil_div(p, lpb);
+  const int m = it.y / nrb, row0 = (it.y - m * nrb) * lpb;
   const size_t plane = (size_t)p * q;
+  const float* C = static_cast<const float*>(S.buf[c_s]);
   const float* Ca = C + (size_t)(2 * m) * plane;
   const float* Cb = (2 * m + 1 < L) ? C + (size_t)(2 * m + 1) * plane : nullptr;
-  const int row0 = blockIdx.x * lpb;
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
     float2 v = make_float2(0.f, 0.f);
@@ -161,8 +172,8 @@ __global__ void fft_rows_fwd(const float* __restrict__ C, float2* __restrict__ F
   __syncthreads();
   const int g = threadIdx.x / tpl;
   const int t = (g < lpb) ? threadIdx.x - g * tpl : tpl;
-  fft_line<false>(sh + (g < lpb ? g : 0) * q, fq, t, tpl);
-  float2* Fm = F + (size_t)m * plane;
+  fft_line<false>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl);
+  float2* Fm = static_cast<float2*>(S.buf[f_s]) + (size_t)m * plane;
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
     if (r < p) Fm[(size_t)r * q + i] = sh[e];
@@ -170,14 +181,18 @@ __global__ void fft_rows_fwd(const float* __restrict__ C, float2* __restrict__ F
 }
 
 // Forward DFT along columns, multiply by invden, inverse DFT along columns.
-// grid (ceil(q / cb), pairs); LDS holds cb columns of p points.
-__global__ void fft_cols_solve(float2* __restrict__ F, const float* __restrict__ invden, int p,
-                               int q, LineFFT fp, int tpl, int cb) {
+// Local block = (pair, column block); LDS holds cb columns of p points.
+__global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
+                               int f_s) {
   extern __shared__ float2 sh[];
-  const int m = blockIdx.y;
-  const int c0 = blockIdx.x * cb;
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, cb = S.fp_cb, tpl = S.fp_tpl;
+  const int ncb = ceil_div(q, cb);
+  const int m = it.y / ncb, c0 = (it.y - m * ncb) * cb;
   const size_t plane = (size_t)p * q;
-  float2* Fm = F + (size_t)m * plane;
+  float2* Fm = static_cast<float2*>(S.buf[f_s]) + (size_t)m * plane;
+  const float* invden = S.invden;
   for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
     const int i = e / cb, l = e - i * cb, col = c0 + l;
     sh[l * p + i] = (col < q) ? Fm[(size_t)i * q + col] : make_float2(0.f, 0.f);
@@ -191,7 +206,7 @@ __global__ void fft_cols_solve(float2* __restrict__ F, const float* __restrict__
     const bool act = (g < G) && (l < cb);
     const int t = act ? tl : tpl;
     float2* line = sh + (act ? l : 0) * p;
-    fft_line<false>(line, fp, t, tpl);
+    fft_line<false>(line, S.fp, t, tpl);
     if (act && c0 + l < q) {
       for (int i = tl; i < p; i += tpl) {
         const float s = invden[(size_t)i * q + c0 + l];
@@ -199,7 +214,7 @@ __global__ void fft_cols_solve(float2* __restrict__ F, const float* __restrict__
       }
     }
     __syncthreads();
-    fft_line<true>(line, fp, t, tpl);
+    fft_line<true>(line, S.fp, t, tpl);
   }
   for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
     const int i = e / cb, l = e - i * cb, col = c0 + l;
@@ -208,13 +223,16 @@ __global__ void fft_cols_solve(float2* __restrict__ F, const float* __restrict__
 }
 
 // Inverse DFT along rows, unpack bands (2m, 2m+1) into X.
-__global__ void fft_rows_inv(const float2* __restrict__ F, float* __restrict__ X, int p, int q,
-                             int L, LineFFT fq, int tpl, int lpb) {
+__global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
+                             int f_s, int x_s) {
   extern __shared__ float2 sh[];
-  const int m = blockIdx.y;
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, L = S.L, lpb = S.fq_lpb, tpl = S.fq_tpl;
+  const int nrb = ceil_div(p, lpb);
+  const int m = it.y / nrb, row0 = (it.y - m * nrb) * lpb;
   const size_t plane = (size_t)p * q;
-  const float2* Fm = F + (size_t)m * plane;
-  const int row0 = blockIdx.x * lpb;
+  const float2* Fm = static_cast<const float2*>(S.buf[f_s]) + (size_t)m * plane;
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
     sh[e] = (r < p) ? Fm[(size_t)r * q + i] : make_float2(0.f, 0.f);
@@ -222,7 +240,8 @@ __global__ void fft_rows_inv(const float2* __restrict__ F, float* __restrict__ X
   __syncthreads();
   const int g = threadIdx.x / tpl;
   const int t = (g < lpb) ? threadIdx.x - g * tpl : tpl;
-  fft_line<true>(sh + (g < lpb ? g : 0) * q, fq, t, tpl);
+  fft_line<true>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl);
+  float* X = static_cast<float*>(S.buf[x_s]);
   float* Xa = X + (size_t)(2 * m) * plane;
   float* Xb = (2 * m + 1 < L) ? X + (size_t)(2 * m + 1) * plane : nullptr;
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
@@ -235,47 +254,185 @@ __global__ void fft_rows_inv(const float2* __restrict__ F, float* __restrict__ X
   }
 }
 
-int block_for(int tpl) {
+constexpr size_t kFftLds = 65536;
+
+int launch_rows(const Batch& B, bool inv, int a, int b, hipStream_t s) {
+  for (const Group& g : B.groups[KD_ROWS]) {
+    if (!g.nitems) continue;
+    if (inv)
+      hipLaunchKernelGGL(fft_rows_inv, dim3(g.nitems), dim3(g.block), g.lds, s, B.d_desc,
+                         g.d_items, a, b);
+    else
+      hipLaunchKernelGGL(fft_rows_fwd, dim3(g.nitems), dim3(g.block), g.lds, s, B.d_desc,
+                         g.d_items, a, b);
+    NLPR_LAUNCH_CHECK(inv ? "fft_rows_inv" : "fft_rows_fwd");
+  }
+  return NLPR_OK;
+}
+
+int launch_cols(const Batch& B, int f, hipStream_t s) {
+  for (const Group& g : B.groups[KD_COLS]) {
+    if (!g.nitems) continue;
+    hipLaunchKernelGGL(fft_cols_solve, dim3(g.nitems), dim3(g.block), g.lds, s, B.d_desc,
+                       g.d_items, f);
+    NLPR_LAUNCH_CHECK("fft_cols_solve");
+  }
+  return NLPR_OK;
+}
+
+}  // namespace
+
+int fft_block(int tpl) {
   int b = 256;
   while (b < tpl) b *= 2;
   return b;
 }
 
-}  // namespace
+int rows_blocks(const Plan& P) {
+  return ceil_div(P.prm.p, P.fft.q_lpb) * ((P.prm.L + 1) / 2);
+}
+int cols_blocks(const Plan& P) {
+  return ceil_div(P.prm.q, P.fft.p_cb) * ((P.prm.L + 1) / 2);
+}
+size_t rows_lds(const Plan& P) { return (size_t)P.fft.q_lpb * P.prm.q * sizeof(float2); }
+size_t cols_lds(const Plan& P) { return (size_t)P.fft.p_cb * P.prm.p * sizeof(float2); }
 
-int launch_xsolve(const Plan& P, const float* C, float* X, float2* F, hipStream_t s) {
-  const int p = P.prm.p, q = P.prm.q, L = P.prm.L;
-  const int pairs = (L + 1) / 2;
+FftShape default_fft_shape(int p, int q) {
+  FftShape f{};
+  f.q_tpl = ceil_div(q, 8);
+  f.p_tpl = ceil_div(p, 8);
+  f.q_lpb = fft_block(f.q_tpl) / f.q_tpl;
+  while (f.q_lpb > 1 && (size_t)f.q_lpb * q * sizeof(float2) > kFftLds) --f.q_lpb;
+  f.p_cb = 16;
+  while (f.p_cb > 1 && (size_t)f.p_cb * p * sizeof(float2) > kFftLds) f.p_cb /= 2;
+  return f;
+}
+
+int launch_xsolve(const Batch& B, int c, int x, int f, hipStream_t s) {
+  int rc;
+  if ((rc = launch_rows(B, false, c, f, s))) return rc;
+  if ((rc = launch_cols(B, f, s))) return rc;
+  return launch_rows(B, true, f, x, s);
+}
+
+// Autotuner: time the row and column passes of one band pair for every admissible lines-
+// per-block / columns-per-block choice and keep the fastest; results are cached per
+// (device, p, q) for the life of the process.
+int autotune_fft(Plan& P) {
+  static std::mutex mtx;
+  static std::map<std::tuple<int, int, int>, FftShape> cache;
+  const int p = P.prm.p, q = P.prm.q;
+  int dev = 0;
+  NLPR_HIP_TRY(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, p, q);
   {
-    const int tpl = ceil_div(q, 8);
-    const int bs = block_for(tpl);
-    int lpb = bs / tpl;
-    while (lpb > 1 && (size_t)lpb * q * sizeof(float2) > 65536) --lpb;
-    dim3 grid(ceil_div(p, lpb), pairs);
-    hipLaunchKernelGGL(fft_rows_fwd, grid, dim3(bs), (size_t)lpb * q * sizeof(float2), s, C, F, p,
-                       q, L, P.fq, tpl, lpb);
-    NLPR_LAUNCH_CHECK("fft_rows_fwd");
+    std::lock_guard<std::mutex> lk(mtx);
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+      P.fft = hit->second;
+      return NLPR_OK;
+    }
   }
+  FftShape best = default_fft_shape(p, q);
+  const size_t plane = (size_t)p * q;
+  // time on up to 16 band pairs so the launch fills the GPU like the real one
+  const int tp = std::max(1, std::min((P.prm.L + 1) / 2, 16));
+  float* d_real = nullptr;
+  float2* d_cplx = nullptr;
+  SceneDesc* d_sd = nullptr;
+  int2* d_items = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int maxitems = std::max(p, q) * tp;
+  int rc = NLPR_OK;
+  auto cleanup = [&]() {
+    hipFree(d_real);
+    hipFree(d_cplx);
+    hipFree(d_sd);
+    hipFree(d_items);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  if (hipMalloc(&d_real, 2 * tp * plane * sizeof(float)) != hipSuccess ||
+      hipMalloc(&d_cplx, tp * plane * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&d_sd, sizeof(SceneDesc)) != hipSuccess ||
+      hipMalloc(&d_items, maxitems * sizeof(int2)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    set_error("autotune: allocation failed");
+    return NLPR_ERR_HIP;
+  }
+  hipMemset(d_real, 0, 2 * tp * plane * sizeof(float));
+  std::vector<int2> items(maxitems);
+  for (int i = 0; i < maxitems; ++i) items[i] = make_int2(0, i);
+  hipMemcpy(d_items, items.data(), maxitems * sizeof(int2), hipMemcpyHostToDevice);
+  SceneDesc h{};
+  h.p = p;
+  h.q = q;
+  h.L = 2 * tp;
+  h.fp = P.fp;
+  h.fq = P.fq;
+  h.invden = P.d_invden;
+  h.buf[B_C] = d_real;
+  h.buf[B_Z] = d_real;
+  h.buf[B_F] = d_cplx;
+  auto time_it = [&](auto launch) -> float {
+    launch();
+    hipEventRecord(e0, nullptr);
+    for (int r = 0; r < 5; ++r) launch();
+    hipEventRecord(e1, nullptr);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+  };
+  // rows
   {
-    const int tpl = ceil_div(p, 8);
-    const int bs = block_for(tpl);
-    int cb = 16;
-    while (cb > 1 && (size_t)cb * p * sizeof(float2) > 65536) cb /= 2;
-    dim3 grid(ceil_div(q, cb), pairs);
-    hipLaunchKernelGGL(fft_cols_solve, grid, dim3(bs), (size_t)cb * p * sizeof(float2), s, F,
-                       P.d_invden, p, q, P.fp, tpl, cb);
-    NLPR_LAUNCH_CHECK("fft_cols_solve");
+    const int tpl = best.q_tpl, bs = fft_block(tpl);
+    float tbest = 1e30f;
+    for (int lpb = 1; lpb <= bs / tpl; lpb *= 2) {
+      if ((size_t)lpb * q * sizeof(float2) > kFftLds) break;
+      h.fq_tpl = tpl;
+      h.fq_lpb = lpb;
+      hipMemcpy(d_sd, &h, sizeof(SceneDesc), hipMemcpyHostToDevice);
+      const int nb = ceil_div(p, lpb) * tp;
+      const size_t lds = (size_t)lpb * q * sizeof(float2);
+      const float ms = time_it([&]() {
+        hipLaunchKernelGGL(fft_rows_fwd, dim3(nb), dim3(bs), lds, nullptr, d_sd, d_items, (int)B_C,
+                           (int)B_F);
+        hipLaunchKernelGGL(fft_rows_inv, dim3(nb), dim3(bs), lds, nullptr, d_sd, d_items, (int)B_F,
+                           (int)B_Z);
+      });
+      if (hipGetLastError() != hipSuccess) { rc = NLPR_ERR_HIP; break; }
+      if (ms < tbest) { tbest = ms; best.q_lpb = lpb; }
+    }
   }
-  {
-    const int tpl = ceil_div(q, 8);
-    const int bs = block_for(tpl);
-    int lpb = bs / tpl;
-    while (lpb > 1 && (size_t)lpb * q * sizeof(float2) > 65536) --lpb;
-    dim3 grid(ceil_div(p, lpb), pairs);
-    hipLaunchKernelGGL(fft_rows_inv, grid, dim3(bs), (size_t)lpb * q * sizeof(float2), s, F, X, p,
-                       q, L, P.fq, tpl, lpb);
-    NLPR_LAUNCH_CHECK("fft_rows_inv");
+  // columns
+  if (rc == NLPR_OK) {
+    const int tpl = best.p_tpl, bs = fft_block(tpl);
+    float tbest = 1e30f;
+    for (int cb = 1; cb <= 32; cb *= 2) {
+      if ((size_t)cb * p * sizeof(float2) > kFftLds) break;
+      h.fp_tpl = tpl;
+      h.fp_cb = cb;
+      hipMemcpy(d_sd, &h, sizeof(SceneDesc), hipMemcpyHostToDevice);
+      const int nb = ceil_div(q, cb) * tp;
+      const size_t lds = (size_t)cb * p * sizeof(float2);
+      const float ms = time_it([&]() {
+        hipLaunchKernelGGL(fft_cols_solve, dim3(nb), dim3(bs), lds, nullptr, d_sd, d_items,
+                           (int)B_F);
+      });
+      if (hipGetLastError() != hipSuccess) { rc = NLPR_ERR_HIP; break; }
+      if (ms < tbest) { tbest = ms; best.p_cb = cb; }
+    }
   }
+  cleanup();
+  if (rc != NLPR_OK) {
+    set_error("autotune: a timing launch failed");
+    return rc;
+  }
+  P.fft = best;
+  std::lock_guard<std::mutex> lk(mtx);
+  cache[key] = best;
   return NLPR_OK;
 }
 

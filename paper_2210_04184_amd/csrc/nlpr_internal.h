@@ -1,4 +1,12 @@
-// Internal declarations of libnlpr: plan structure, kernel launchers, helpers.
+// Internal declarations of libnlpr: scene plans, the batch every launch runs over, device
+// scene descriptors and kernel launchers.
+//
+// Every kernel runs over a batch of scenes.  Block b of a launch reads its work item
+// items[b] = (scene, local block), takes the scene's sizes, tables and buffers from the
+// device descriptor sd[scene] and does the work of that local block.  A single-scene plan
+// is a batch of one, so one code path serves both.  Kernels reach buffers through slots
+// (SceneDesc::buf[slot]), so the same kernel serves the solve and the per-stage entry
+// points with different buffers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,8 +28,8 @@ constexpr int kMaxFFTFactors = 24;
 constexpr int kMaxFFTLen = 4096;
 constexpr size_t kMaxSweepLds = 160 * 1024;  // LDS per workgroup on gfx950
 
-// One-dimensional FFT of length n = product of fac[] (each 2, 3, 4 or 8); passed to
-// kernels by value.  tw[m] = exp(-2 pi i m / n), m in [0, n).
+// One-dimensional FFT of length n = product of fac[] (each 2, 3, 4 or 8).
+// tw[m] = exp(-2 pi i m / n), m in [0, n).
 struct LineFFT {
   int n;
   int nfac;
@@ -29,7 +37,29 @@ struct LineFFT {
   const float2* tw;
 };
 
-// Tiling of the sweep: a workgroup owns `rows` image rows (all q columns) of one band.
+// Buffer slots of a scene descriptor.
+enum Slot {
+  B_YL = 0, B_YH, B_Z, B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO, B_TMP,
+  B_COUNT
+};
+
+// Everything a kernel needs to know about one scene.  Lives in device memory.
+struct SceneDesc {
+  int p, q, L, Lh, d, r, K, npairs, npatch;
+  int rows, ntiles, halo;          // sweep tiling
+  int fq_tpl, fq_lpb;              // row FFT: threads per line, lines per block
+  int fp_tpl, fp_cb;               // column FFT: threads per line, columns per block
+  int init_zero, unweighted;
+  float rho, inv_1prho, mu_scale, inv_h2;
+  LineFFT fp, fq;
+  const int2* taus;
+  const float* invden;
+  const float* blur;
+  const float* R;
+  const float* G;
+  void* buf[B_COUNT];
+};
+
 struct SweepShape {
   int rows;      // tile height R
   int items;     // float4 items per thread
@@ -39,26 +69,62 @@ struct SweepShape {
   size_t lds;    // dynamic LDS bytes
 };
 
+struct FftShape {
+  int q_tpl, q_lpb;   // row passes: threads per line, lines per block
+  int p_tpl, p_cb;    // column pass: threads per line, columns per block
+};
+
+// One scene: parameters, device tables and its part of the workspace.
 struct Plan {
   nlpr_params prm{};
-  int device = 0;
-  int npairs = 0;                 // |W+|
-  int npatch = 0;                 // |P|
-  std::vector<int32_t> taus;      // host copy of W+ (tau1, tau2 pairs)
+  int npairs = 0;
+  int npatch = 0;
+  std::vector<int32_t> taus;      // W+ (tau1, tau2 pairs)
   int2* d_taus = nullptr;
   float* d_invden = nullptr;      // [p][q], 1 / (den * p * q)
   float2* d_tw_p = nullptr;
   float2* d_tw_q = nullptr;
   LineFFT fp{}, fq{};
-  float* d_blur = nullptr;        // (2r+1)^2 taps
-  float* d_R = nullptr;           // [L][Lh]
-  float* d_G = nullptr;           // [Lh][Lh]
+  FftShape fft{};
+  float* d_blur = nullptr;
+  float* d_R = nullptr;
+  float* d_G = nullptr;
   SweepShape sweep{};
-  // workspace layout
-  size_t off_sigma = 0, off_mu = 0, off_C = 0, off_L1 = 0, off_L2 = 0, off_BX = 0,
-         off_W1 = 0, off_W2 = 0, off_F = 0, off_halo = 0, off_flag = 0;
-  size_t sz_sigma = 0, sz_mu = 0, sz_plane = 0, sz_F = 0, sz_halo = 0;
+  // workspace layout relative to the scene's base
+  size_t off[B_COUNT] = {};
+  size_t sz[B_COUNT] = {};
   size_t ws_bytes = 0;
+};
+
+// A launch: the work items of the scenes that share its template parameters.
+struct Group {
+  int2* d_items = nullptr;
+  int nitems = 0;
+  int block = 256;
+  size_t lds = 0;
+  int key0 = 0, key1 = 0;   // sweep: K, items per thread
+};
+
+enum Kind { KD_WEIGHTS = 0, KD_PLANE, KD_CONV, KD_PIXEL, KD_SWEEP, KD_ROWS, KD_COLS, KD_COUNT };
+
+struct Batch {
+  int device = 0;
+  uint32_t flags = 0;              // flags shared by every scene (INIT_ZERO, STATE_IN, ...)
+  int iters = 0;
+  std::vector<Plan*> scenes;       // owned
+  std::vector<size_t> base;        // workspace base of each scene
+  size_t ws_bytes = 0;
+  SceneDesc* d_desc = nullptr;     // device descriptors, one per scene
+  SceneDesc* h_desc = nullptr;     // pinned staging copy
+  std::vector<SceneDesc> uploaded; // what d_desc holds
+  bool desc_valid = false;
+  hipEvent_t upload_ev = nullptr;
+  std::vector<Group> groups[KD_COUNT];
+  int* d_flag = nullptr;           // result of the finite check
+  // graph
+  bool use_graph = false;
+  hipGraphExec_t graph = nullptr;
+  uint32_t graph_key = 0;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -88,30 +154,46 @@ void set_error(const std::string& msg);
     }                                                                               \
   } while (0)
 
-// ---- precompute (dense.hip)
-int launch_precompute(Plan& P, hipStream_t s);
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// ---- dense kernels (dense.hip)
-int launch_weights(const Plan& P, const float* Yh, float* mu, hipStream_t s);
-int launch_init(const Plan& P, const float* Yl, float* X0, float* Lam1, float* Lam2, float* W2,
-                hipStream_t s);
-// out = conv(in) (+ add1 + add2 + halo fold); transpose selects B^T.
-int launch_conv(const Plan& P, const float* in, float* out, bool transpose, const float* add1,
-                const float* add2, const float* halo, hipStream_t s);
-int launch_pupdate(const Plan& P, const float* X, const float* BX, const float* Yl,
-                   const float* Yh, float* Lam1, float* Lam2, float* W1, float* W2,
+// ---- plan precompute (dense.hip); runs once per scene on the null stream
+int launch_precompute(Plan& P);
+
+// ---- local work-item counts per scene for each kind of launch
+int weights_blocks(const Plan& P);
+int plane_blocks(const Plan& P);      // elementwise over [L][p][q], 256 elements per block
+int conv_blocks(const Plan& P);
+int pixel_blocks(const Plan& P);      // one thread per pixel
+int rows_blocks(const Plan& P);
+int cols_blocks(const Plan& P);
+int sweep_blocks(const Plan& P);
+size_t weights_lds(const Plan& P);
+size_t conv_lds(const Plan& P);
+size_t rows_lds(const Plan& P);
+size_t cols_lds(const Plan& P);
+
+// ---- batched kernels: each launches the groups of one kind with buffer slots (< 0: none)
+int launch_weights(const Batch& B, int yh, int mu, hipStream_t s);
+int launch_init(const Batch& B, int yl, int x0, int l1, int l2, int w2, hipStream_t s);
+// reg_mask: bit 0 / 1 mark add1 / add2 as regulariser terms (skipped, like the halo, for
+// scenes without a search window)
+int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int add2, int halo,
+                int reg_mask, hipStream_t s);
+int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,
                    hipStream_t s);
-int launch_check_finite(const Plan& P, const float* Z, int* flag, hipStream_t s);
+int lh_class(int Lh);   // pupdate template class of a guide-band count: 1, 4 or 16
+int launch_finite(const Batch& B, int z, int* flag, hipStream_t s);
+int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] slot
+int launch_xsolve(const Batch& B, int c, int x, int f, hipStream_t s);
+int launch_sweep(const Batch& B, int x, int mu, int sigma, int creg, int halo, bool first,
+                 hipStream_t s);
+int sweep_prepare(int K, int items);   // kernel attributes; call before launches or capture
 
-// ---- FFT solve (fft.hip)
-int launch_xsolve(const Plan& P, const float* C, float* X, float2* F, hipStream_t s);
-
-// ---- sweep (sweep.hip)
+// ---- shapes and tuning
 SweepShape choose_sweep_shape(int p, int q, int K, int halo);
 size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npatch);
-int launch_sweep(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
-                 float* halo, bool first, hipStream_t s);
-
-inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+int fft_block(int tpl);             // workgroup size of a line FFT with tpl threads per line
+FftShape default_fft_shape(int p, int q);
+int autotune_fft(Plan& P);          // picks P.fft by timing candidates (cached per (p, q))
 
 }  // namespace nlpr

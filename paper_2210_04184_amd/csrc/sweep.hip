@@ -59,9 +59,18 @@ __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v
 
 template <int K, int ITEMS, int NT, bool FIRST>
 __global__ void __launch_bounds__(NT)
-sweep_kernel(const float* __restrict__ X, const float* __restrict__ mu, float* __restrict__ sig,
-             float* __restrict__ creg, float* __restrict__ halo, const int2* __restrict__ taus,
-             int p, int q, int L, int npairs, int R, int ntiles, int H) {
+sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s, int mu_s,
+             int sig_s, int creg_s, int halo_s) {
+  const int2 it_ = items[blockIdx.x];
+  const SceneDesc& S = sd[it_.x];
+  const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
+            H = S.halo;
+  const float* __restrict__ X = static_cast<const float*>(S.buf[x_s]);
+  const float* __restrict__ mu = static_cast<const float*>(S.buf[mu_s]);
+  float* __restrict__ sig = static_cast<float*>(S.buf[sig_s]);
+  float* __restrict__ creg = static_cast<float*>(S.buf[creg_s]);
+  float* __restrict__ halo = static_cast<float*>(S.buf[halo_s]);
+  const int2* __restrict__ taus = S.taus;
   constexpr int KW = 2 * K + 1;
   constexpr int NP = KW * KW;
   extern __shared__ float4 lds4[];
@@ -72,8 +81,8 @@ sweep_kernel(const float* __restrict__ X, const float* __restrict__ mu, float* _
   float* Xs = Ms + (R + 2 * K) * ms;    // (R + H) x q         X rows r0-H .. r0+R-1
   float* Cs = Xs + (R + H) * q;         // (R + H) x q         adjoint accumulator
 
-  const int tile = blockIdx.x / L;
-  const int c = blockIdx.x - tile * L;
+  const int tile = it_.y / L;
+  const int c = it_.y - tile * L;
   const int r0 = tile * R;
   const int rows = min(R, p - r0);
   const size_t plane = (size_t)p * q;
@@ -234,30 +243,42 @@ constexpr int kThreads = NLPR_SWEEP_THREADS;
 constexpr int kMinItems = NLPR_SWEEP_MIN_ITEMS;
 
 template <int K, int ITEMS, bool FIRST>
-int launch_k(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
-             float* halo, hipStream_t s) {
-  const SweepShape& sh = P.sweep;
+int launch_k(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
+             hipStream_t s) {
   auto kern = sweep_kernel<K, ITEMS, kThreads, FIRST>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
-  dim3 grid(sh.ntiles * P.prm.L);
-  hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh.lds, s, X, mu, sigma, creg, halo, P.d_taus,
-                     P.prm.p, P.prm.q, P.prm.L, P.npairs, sh.rows, sh.ntiles, sh.halo);
+  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(kThreads), g.lds, s, B.d_desc, g.d_items, x, mu,
+                     sig, creg, halo);
   NLPR_LAUNCH_CHECK("sweep_kernel");
   return NLPR_OK;
 }
 
+// Allow the sweep's dynamic LDS beyond the default limit (done when a batch is built, not
+// during graph capture).
+template <int K, int ITEMS>
+int set_lds_limit() {
+  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
+  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
+  return NLPR_OK;
+}
+
+template <int K>
+int set_lds_limit_items(int items) {
+  switch (items) {
+    case 1: return set_lds_limit<K, (kMinItems > 1 ? kMinItems : 1)>();
+    case 2: return set_lds_limit<K, (kMinItems > 2 ? kMinItems : 2)>();
+    default: return set_lds_limit<K, 4>();
+  }
+}
+
 template <int K, bool FIRST>
-int launch_items(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
-                 float* halo, hipStream_t s) {
-  switch (P.sweep.items) {
-    case 1: return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST>(P, X, mu, sigma, creg, halo, s);
-    case 2: return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST>(P, X, mu, sigma, creg, halo, s);
-    default: return launch_k<K, 4, FIRST>(P, X, mu, sigma, creg, halo, s);
+int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
+                 hipStream_t s) {
+  switch (g.key1) {
+    case 1: return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST>(B, g, x, mu, sig, creg, halo, s);
+    case 2: return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST>(B, g, x, mu, sig, creg, halo, s);
+    default: return launch_k<K, 4, FIRST>(B, g, x, mu, sig, creg, halo, s);
   }
 }
 
@@ -281,23 +302,43 @@ size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npa
   return (size_t)L * sh.ntiles * npairs * npatch * sh.rows * q * sizeof(float);
 }
 
-int launch_sweep(const Plan& P, const float* X, const float* mu, float* sigma, float* creg,
-                 float* halo, bool first, hipStream_t s) {
-  switch (P.prm.K) {
-#define NLPR_SW(KK)                                                                   \
-  case KK:                                                                            \
-    return first ? launch_items<KK, true>(P, X, mu, sigma, creg, halo, s)             \
-                 : launch_items<KK, false>(P, X, mu, sigma, creg, halo, s);
-    NLPR_SW(0)
-    NLPR_SW(1)
-    NLPR_SW(2)
-    NLPR_SW(3)
-    NLPR_SW(4)
-#undef NLPR_SW
-    default:
-      set_error("sweep: unsupported patch radius");
-      return NLPR_ERR_UNSUPPORTED_SHAPE;
+int sweep_blocks(const Plan& P) { return P.sweep.ntiles * P.prm.L; }
+
+int sweep_prepare(int K, int items) {
+  switch (K) {
+    case 0: return set_lds_limit_items<0>(items);
+    case 1: return set_lds_limit_items<1>(items);
+    case 2: return set_lds_limit_items<2>(items);
+    case 3: return set_lds_limit_items<3>(items);
+    case 4: return set_lds_limit_items<4>(items);
+    default: set_error("sweep: unsupported patch radius"); return NLPR_ERR_UNSUPPORTED_SHAPE;
   }
+}
+
+int launch_sweep(const Batch& B, int x, int mu, int sig, int creg, int halo, bool first,
+                 hipStream_t s) {
+  for (const Group& g : B.groups[KD_SWEEP]) {
+    if (!g.nitems) continue;
+    int rc;
+    switch (g.key0) {
+#define NLPR_SW(KK)                                                                            \
+  case KK:                                                                                     \
+    rc = first ? launch_items<KK, true>(B, g, x, mu, sig, creg, halo, s)                       \
+               : launch_items<KK, false>(B, g, x, mu, sig, creg, halo, s);                     \
+    break;
+      NLPR_SW(0)
+      NLPR_SW(1)
+      NLPR_SW(2)
+      NLPR_SW(3)
+      NLPR_SW(4)
+#undef NLPR_SW
+      default:
+        set_error("sweep: unsupported patch radius");
+        return NLPR_ERR_UNSUPPORTED_SHAPE;
+    }
+    if (rc) return rc;
+  }
+  return NLPR_OK;
 }
 
 }  // namespace nlpr

@@ -30,6 +30,7 @@ UNWEIGHTED = 1 << 2
 LOCAL_WINDOW = 1 << 3
 CHECK_FINITE = 1 << 4
 TIMING = 1 << 5
+GRAPH = 1 << 6
 
 STAGE_WEIGHTS = 1
 STAGE_XSOLVE = 2
@@ -53,7 +54,9 @@ REGION_LAMBDA2 = 4
 EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlpr_plan_destroy",
                    "nlpr_status_string", "nlpr_last_error", "nlpr_half_window",
                    "nlpr_workspace_region", "nlpr_debug_stage", "nlpr_stage_time",
-                   "nlpr_plan_get_info"])
+                   "nlpr_plan_get_info", "nlpr_batch_create", "nlpr_batch_workspace_size",
+                   "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
+                   "nlpr_batch_destroy"])
 
 
 class NlprError(RuntimeError):
@@ -103,6 +106,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_debug_stage.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), i32, vp]
     lib.nlpr_stage_time.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.nlpr_batch_create.argtypes = [i32, ctypes.POINTER(Params), pp, pp, ctypes.POINTER(vp)]
+    lib.nlpr_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.nlpr_batch_region.argtypes = [vp, i32, ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.nlpr_batch_solve.argtypes = [vp, pp, pp, pp, vp, sz, vp]
+    lib.nlpr_batch_stage_time.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.nlpr_batch_destroy.argtypes = [vp]
     for name in EXPORTED:
         if name not in ("nlpr_status_string", "nlpr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -156,12 +167,7 @@ class Plan:
 
     @classmethod
     def from_scene(cls, scene, flags: int = 0, **over) -> "Plan":
-        s = scene.spec
-        kw = dict(p=s.p, q=s.q, L=s.L, Lh=scene.R.shape[1], d=s.d, blur=scene.blur, R=scene.R,
-                  K=s.K, Sw=s.Sw, iters=s.iters, lam=s.lam, rho=s.rho, h=scene.h, lam1=s.lam1,
-                  flags=flags)
-        kw.update(over)
-        return cls(**kw)
+        return cls(**_scene_kwargs(scene, flags, **over))
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -237,6 +243,91 @@ class Plan:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(load().nlpr_stage_time(self.handle, stage, ctypes.byref(ms), ctypes.byref(n),
                                       1 if reset else 0))
+        return ms.value, n.value
+
+
+def _scene_kwargs(scene, flags: int = 0, **over):
+    s = scene.spec
+    kw = dict(p=s.p, q=s.q, L=s.L, Lh=scene.R.shape[1], d=s.d, blur=scene.blur, R=scene.R,
+              K=s.K, Sw=s.Sw, iters=s.iters, lam=s.lam, rho=s.rho, h=scene.h, lam1=s.lam1,
+              flags=flags)
+    kw.update(over)
+    return kw
+
+
+class Batch:
+    """Many independent scenes solved together: one launch per stage over all scenes."""
+
+    def __init__(self, scenes_kwargs):
+        lib = load()
+        n = len(scenes_kwargs)
+        self.params = (Params * n)()
+        self.shapes = []
+        self._keep = []
+        blurs = (ctypes.c_void_p * n)()
+        Rs = (ctypes.c_void_p * n)()
+        for i, kw in enumerate(scenes_kwargs):
+            blur = np.ascontiguousarray(kw["blur"], dtype=np.float32)
+            R = np.ascontiguousarray(kw["R"], dtype=np.float32).reshape(kw["L"], kw["Lh"])
+            r = blur.shape[0] // 2
+            self.params[i] = Params(kw["p"], kw["q"], kw["L"], kw["Lh"], kw["d"], r, kw["K"],
+                                    kw["Sw"], kw["iters"], kw.get("flags", 0), kw["lam"],
+                                    kw.get("lam1", 1.0), kw["rho"], kw["h"])
+            self._keep += [blur, R]
+            blurs[i] = blur.ctypes.data
+            Rs[i] = R.ctypes.data
+            self.shapes.append((kw["L"], kw["p"], kw["q"]))
+        handle = ctypes.c_void_p()
+        _check(lib.nlpr_batch_create(n, self.params, blurs, Rs, ctypes.byref(handle)))
+        self.handle = handle
+
+    @classmethod
+    def from_scenes(cls, scenes, flags: int = 0, **over) -> "Batch":
+        return cls([_scene_kwargs(sc, flags, **over) for sc in scenes])
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().nlpr_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(load().nlpr_batch_workspace_size(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def alloc_workspace(self):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+
+    def region(self, scene: int, which: int) -> Tuple[int, int]:
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().nlpr_batch_region(self.handle, scene, which, ctypes.byref(off),
+                                        ctypes.byref(nb)))
+        return off.value, nb.value
+
+    def solve(self, Yls, Yhs, Zs=None, ws=None, stream=None):
+        import torch
+        n = len(self.shapes)
+        if Zs is None:
+            Zs = [torch.empty(sh, dtype=torch.float32, device="cuda") for sh in self.shapes]
+        if ws is None:
+            ws = self.alloc_workspace()
+        arr = lambda ts: (ctypes.c_void_p * n)(*[_ptr(t) for t in ts])
+        _check(load().nlpr_batch_solve(self.handle, arr(Yls), arr(Yhs), arr(Zs), _ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream_handle(stream)))
+        return Zs, ws
+
+    def stage_time(self, stage: int, reset: bool = False) -> Tuple[float, int]:
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(load().nlpr_batch_stage_time(self.handle, stage, ctypes.byref(ms),
+                                            ctypes.byref(n), 1 if reset else 0))
         return ms.value, n.value
 
 

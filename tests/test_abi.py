@@ -111,3 +111,17 @@ def test_subspace_basis_is_reported_unsupported():
                               R.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p),
                               ctypes.byref(h))
     assert rc == nlpr.ERR_UNSUPPORTED_SHAPE
+
+
+def test_batch_rejects_scenes_with_different_iteration_counts():
+    lib = nlpr.load()
+    prm = (nlpr.Params * 2)(nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 3, 0, 1e-3, 1.0, 1e-2, 0.1),
+                            nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 4, 0, 1e-3, 1.0, 1e-2, 0.1))
+    blur = np.ones((3, 3), np.float32)
+    R = np.ones((8, 1), np.float32)
+    ptrs = (ctypes.c_void_p * 2)(blur.ctypes.data, blur.ctypes.data)
+    rs = (ctypes.c_void_p * 2)(R.ctypes.data, R.ctypes.data)
+    h = ctypes.c_void_p()
+    assert lib.nlpr_batch_create(2, prm, ptrs, rs, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
+    assert lib.nlpr_batch_create(0, prm, ptrs, rs, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
+    assert lib.nlpr_batch_destroy(None) == nlpr.OK
