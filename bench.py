@@ -47,6 +47,16 @@ def sweep_bytes_per_launch(spec, npairs: int) -> int:
     return (8 * npairs * npatch + 8) * n * spec.L + 4 * npairs * n
 
 
+def sweep_kernel_sha() -> str:
+    """sha256 of the sweep kernel's source text (between its begin / end markers)."""
+    import hashlib
+    with open(SWEEP_SRC) as f:
+        src = f.read()
+    a = src.index("// ---- sweep kernel begin")
+    b = src.index("// ---- sweep kernel end")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def measured_traffic(config: str):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it was
     taken on the current sweep source and workload; else None."""
@@ -54,8 +64,7 @@ def measured_traffic(config: str):
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(SWEEP_SRC, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = sweep_kernel_sha()
     except (OSError, ValueError):
         return None
     if rec.get("sweep_source_sha256") != sha or rec.get("config") != config:
@@ -197,6 +206,9 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--iters", type=int, default=None, help="override the iteration count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--subspace", type=int, default=0,
+                    help="Ls > 0: solve for Z = X E with E the Ls leading right singular "
+                         "vectors of Y_l")
     ap.add_argument("--calib-gib", type=float, default=4.0,
                     help="size of the reference copy (0 = skip)")
     args = ap.parse_args()
@@ -226,7 +238,12 @@ def main():
     dev = torch.device("cuda:0")
     Yl = torch.from_numpy(sc.Yl).to(dev)
     Yh = torch.from_numpy(sc.Yh).to(dev)
-    plan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING)
+    E = None
+    if args.subspace:
+        M = sc.Yl.reshape(spec.L, -1).T.astype(np.float64)
+        E = np.ascontiguousarray(np.linalg.svd(M, full_matrices=False)[2][:args.subspace],
+                                 dtype=np.float32)
+    plan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING, E=E)
     npairs = len(plan.half_window())
     ws = plan.alloc_workspace()
     Z = torch.empty((spec.L, spec.p, spec.q), dtype=torch.float32, device=dev)
@@ -257,11 +274,12 @@ def main():
     sw = stages.get("sweep")
     roof = None
     if sw:
-        bytes_launch = sweep_bytes_per_launch(spec, npairs)
+        bytes_launch = sweep_bytes_per_launch(spec.replace(L=args.subspace or spec.L), npairs)
         achieved = bytes_launch / (sw["ms_avg"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": "sweep_kernel", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.config), "bytes_per_launch": bytes_launch,
+                "traffic": None if args.subspace else measured_traffic(args.config),
+                "bytes_per_launch": bytes_launch,
                 "ms_per_launch": sw["ms_avg"]}
     loop_ms = sum(v["ms_total"] for k, v in stages.items() if k not in ("weights", "init"))
     out = {
@@ -270,7 +288,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload_name(spec), "p": spec.p, "q": spec.q, "L": spec.L,
+        "config": {"workload": workload_name(spec) + (f", subspace Ls={args.subspace}"
+                                                      if args.subspace else ""),
+                   "p": spec.p, "q": spec.q, "L": spec.L, "Ls": args.subspace or spec.L,
                    "Lh": spec.Lh, "d": spec.d, "blur": 2 * spec.blur_radius + 1,
                    "patch": 2 * spec.K + 1, "window": 2 * spec.Sw + 1, "iters": spec.iters,
                    "lambda": spec.lam, "rho": spec.rho, "seed": spec.seed},

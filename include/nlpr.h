@@ -88,6 +88,10 @@ enum {
  *   4 * ((R + 2K)(q + 8) + 2 (R + Sw) q) must not exceed 160 KiB (e.g. q <= 2048 for
  *   K = 2, Sw = 5).
  *   iters      : ADMM iterations, >= 0.
+ *   Ls         : 0 = no subspace (Z is the ADMM variable X).  1 <= Ls <= min(L, 32): Z = X E
+ *                with the fixed basis E (Ls x L) passed to nlpr_plan_create; X has Ls bands
+ *                and the dual state shrinks by L / Ls (Sec. "Variational models").
+ *   reserved   : must be 0.
  *   lambda     : regulariser weight lambda_2 >= 0.  The soft-threshold of eq. (Qj_main) is
  *                lambda * omega / rho.
  *   lambda1    : weight of the Y_h term, > 0.
@@ -102,6 +106,8 @@ typedef struct nlpr_params {
   int32_t K, Sw;
   int32_t iters;
   uint32_t flags;
+  int32_t Ls;
+  int32_t reserved;
   double lambda;
   double lambda1;
   double rho;
@@ -120,7 +126,11 @@ typedef struct nlpr_plan nlpr_plan;
  *   blur_host : host, (2r+1)^2 floats, row-major, tap b(m1, m2) at [(m1 + r)(2r+1) + m2 + r];
  *               B X (i) = sum_m b(m) X(i - m), circular.
  *   R_host    : host, L x Lh floats, row-major (R[c][h] at [c * Lh + h]).
- *   E_host    : must be NULL (E = I); a subspace basis is not supported yet.
+ *   E_host    : host, Ls x L floats, row-major (E[s][c] at [s * L + c]), the subspace basis
+ *               (rows need not be orthonormal, E E^T must be invertible); NULL iff Ls == 0.
+ *               With a basis the plan also holds, computed in FP64: (E E^T + rho I)^{-1} for
+ *               the P1-update (eq. (Qh_update)), E^+ = E^T (E E^T)^{-1} for the default start
+ *               X0 = up(Y_l) E^+, and E R, with which the P2-update runs as without a basis.
  *   out       : receives the plan.  The plan owns its small device tables only.
  * Allocates device memory for the tables (a few MB at 512 x 512).
  */
@@ -211,6 +221,8 @@ int nlpr_workspace_region(const nlpr_plan* plan, int region, size_t* offset, siz
  *   NLPR_STAGE_SWEEP_FIRST same, with Sigma' taken as 0 on input (only written).
  *   NLPR_STAGE_ASSEMBLE    {W1, W2, Creg, C}          C = B^T W1 + W2 + Creg
  *   NLPR_STAGE_INIT        {Yl, X0, W1, W2, Lambda1, Lambda2, C}   the initial values and C^(0)
+ * All stages act on X-space buffers (Ls bands with a basis); INIT and PUPDATE are for plans
+ * without a basis (else NLPR_ERR_UNSUPPORTED_SHAPE).
  */
 enum {
   NLPR_STAGE_WEIGHTS = 1,
@@ -244,7 +256,8 @@ int nlpr_stage_time(nlpr_plan* plan, int stage, double* ms_total, int64_t* launc
  *              parameter, but must share iters and the flags NLPR_INIT_ZERO,
  *              NLPR_STATE_IN, NLPR_CHECK_FINITE, NLPR_TIMING and NLPR_GRAPH
  *              (else NLPR_ERR_INVALID_ARG).
- *   blur_host, R_host : host arrays of n host pointers, as for nlpr_plan_create.
+ *   blur_host, R_host, E_host : host arrays of n host pointers, as for nlpr_plan_create
+ *              (E_host may be NULL when no scene has a basis).
  * The workspace of a batch is the concatenation of the scenes' workspaces;
  * nlpr_batch_region gives a region of one scene (offset from the start of ws).
  * nlpr_batch_solve takes host arrays of n device pointers Yl[s], Yh[s], Z[s] laid out as
@@ -252,7 +265,7 @@ int nlpr_stage_time(nlpr_plan* plan, int stage, double* ms_total, int64_t* launc
  */
 typedef struct nlpr_batch nlpr_batch;
 int nlpr_batch_create(int32_t n, const nlpr_params* params, const float* const* blur_host,
-                      const float* const* R_host, nlpr_batch** out);
+                      const float* const* R_host, const float* const* E_host, nlpr_batch** out);
 int nlpr_batch_workspace_size(const nlpr_batch* batch, size_t* bytes);
 int nlpr_batch_region(const nlpr_batch* batch, int32_t scene, int region, size_t* offset,
                       size_t* bytes);

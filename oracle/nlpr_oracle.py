@@ -27,7 +27,9 @@ X in R^{n_h x L} (one row per pixel).  Here images are stored planar,
 ``to_mat`` whenever a formula multiplies on the band axis.
 
 Readings of points the paper leaves open (each one is listed in the design doc):
-  * E = I (no subspace), so X and Z coincide.
+  * The subspace basis E (L_s x L, Z = X E) is optional; without it E = I and X is Z.
+  * With a basis, the default start is the least-squares coefficient image of the
+    upsampled Y_l: X0 = up(Y_l) E^T (E E^T)^{-1}.
   * The one "lambda" of a workload is lambda_2; lambda_1 defaults to 1.
   * The Q-update threshold is lambda_2 * omega / rho, as printed in eq. (Qj_main);
     the objective is ell(X) + lambda_2 * phi(X) as in eq. (mainoptim).
@@ -206,6 +208,16 @@ class Problem:
     lam1: float = 1.0       # lambda_1
     unweighted: bool = False
     local: bool = False
+    E: Optional[np.ndarray] = None   # subspace basis [Ls][L] (Z = X E); None means E = I
+
+    @property
+    def Ebasis(self) -> np.ndarray:
+        return np.eye(self.L) if self.E is None else self.E
+
+    @property
+    def Ls(self) -> int:
+        """Bands of X (rows of E)."""
+        return self.L if self.E is None else self.E.shape[0]
 
     @classmethod
     def from_scene(cls, scene, **kw) -> "Problem":
@@ -231,11 +243,11 @@ def upsample_nn(Yl: np.ndarray, d: int) -> np.ndarray:
 
 
 def p1_update(BX: np.ndarray, Lam1: np.ndarray, Yl: np.ndarray, pr: Problem) -> np.ndarray:
-    """eq. (Qh_update) with E = I:
-    P1 = S^T S (rho B X + S^T Y_l - rho Lambda1)(E E^T + rho I)^{-1} + (I - S^T S)(B X - Lambda1)."""
+    """eq. (Qh_update):
+    P1 = S^T S (rho B X + S^T Y_l E^T - rho Lambda1)(E E^T + rho I)^{-1} + (I - S^T S)(B X - Lambda1)."""
     M = to_mat(sampling_mask(pr.p, pr.q, pr.d)[None])            # n_h x 1 diagonal of S^T S
-    E = np.eye(pr.L)
-    inv = np.linalg.inv(E @ E.T + pr.rho * np.eye(pr.L))
+    E = pr.Ebasis
+    inv = np.linalg.inv(E @ E.T + pr.rho * np.eye(pr.Ls))
     StYl = decimate_T(Yl, pr.d, pr.p, pr.q)
     sampled = (pr.rho * to_mat(BX) + to_mat(StYl) @ E.T - pr.rho * to_mat(Lam1)) @ inv
     rest = to_mat(BX) - to_mat(Lam1)
@@ -243,17 +255,17 @@ def p1_update(BX: np.ndarray, Lam1: np.ndarray, Yl: np.ndarray, pr: Problem) -> 
 
 
 def p2_matrix(pr: Problem) -> np.ndarray:
-    """F = (I + lambda1/rho E R R^T E^T)^{-1}, L x L (after eq. (Qm_update)), E = I."""
-    E = np.eye(pr.L)
-    return np.linalg.inv(np.eye(pr.L) + (pr.lam1 / pr.rho) * (E @ pr.R @ pr.R.T @ E.T))
+    """F = (I + lambda1/rho E R R^T E^T)^{-1}, L_s x L_s (after eq. (Qm_update))."""
+    E = pr.Ebasis
+    return np.linalg.inv(np.eye(pr.Ls) + (pr.lam1 / pr.rho) * (E @ pr.R @ pr.R.T @ E.T))
 
 
 def p2_update(X: np.ndarray, Lam2: np.ndarray, Yh: np.ndarray, pr: Problem,
               F: Optional[np.ndarray] = None) -> np.ndarray:
-    """eq. (Qm_update): P2 = (-Lambda2 + X + lambda1/rho Y_h R^T E^T) F, E = I."""
+    """eq. (Qm_update): P2 = (-Lambda2 + X + lambda1/rho Y_h R^T E^T) F."""
     if F is None:
         F = p2_matrix(pr)
-    A = -to_mat(Lam2) + to_mat(X) + (pr.lam1 / pr.rho) * (to_mat(Yh) @ pr.R.T)
+    A = -to_mat(Lam2) + to_mat(X) + (pr.lam1 / pr.rho) * (to_mat(Yh) @ pr.R.T @ pr.Ebasis.T)
     return from_mat(A @ F, pr.p, pr.q)
 
 
@@ -271,11 +283,12 @@ def regulariser(X: np.ndarray, omega: np.ndarray, window: Sequence[Offset],
 
 def objective(X: np.ndarray, Yl: np.ndarray, Yh: np.ndarray, pr: Problem,
               omega: Optional[np.ndarray] = None) -> float:
-    """ell(X) + lambda2 phi(X), eq. (mainoptim) with E = I."""
+    """ell(X) + lambda2 phi(X), eq. (mainoptim): the data terms act on Z = X E."""
     if omega is None:
         omega = weights(Yh, pr.window, pr.K, pr.h, pr.unweighted)
-    r1 = Yl - decimate(blur(X, pr.b), pr.d)
-    r2 = Yh - spectral(X, pr.R)
+    Z = compose(X, pr)
+    r1 = Yl - decimate(blur(Z, pr.b), pr.d)
+    r2 = Yh - spectral(Z, pr.R)
     return (0.5 * float(np.sum(r1 * r1)) + 0.5 * pr.lam1 * float(np.sum(r2 * r2))
             + pr.lam * regulariser(X, omega, pr.window, pr.K))
 
@@ -294,11 +307,21 @@ class State:
     Sig: np.ndarray
 
 
+def compose(X: np.ndarray, pr: Problem) -> np.ndarray:
+    """Z = X E (the low-rank representation); X itself when E = I."""
+    if pr.E is None:
+        return X
+    return from_mat(to_mat(X) @ pr.E, pr.p, pr.q)
+
+
 def initial_state(Yl: np.ndarray, pr: Problem, init: str = "upsample") -> Tuple[np.ndarray, State]:
-    shape = (pr.L, pr.p, pr.q)
+    shape = (pr.Ls, pr.p, pr.q)
     nw, npch = len(pr.window), len(pr.patch)
     if init == "upsample":
         X0 = upsample_nn(Yl.astype(np.float64), pr.d)
+        if pr.E is not None:
+            E = pr.E
+            X0 = from_mat(to_mat(X0) @ E.T @ np.linalg.inv(E @ E.T), pr.p, pr.q)
         P1, P2 = blur(X0, pr.b), X0.copy()
     elif init == "zero":
         X0 = np.zeros(shape)
@@ -352,15 +375,16 @@ def fixed_point_residual(a: State, b: State, rho: float) -> float:
 
 @dataclasses.dataclass
 class Result:
-    X: np.ndarray
+    X: np.ndarray            # the iterate X^{(T)} (L_s bands)
     state: State
     objective: List[float]
     residual: List[float]
+    Z: Optional[np.ndarray] = None   # Z = X E (L bands)
 
 
 def solve(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, init: str = "upsample",
           track: bool = False, state: Optional[Tuple[np.ndarray, State]] = None) -> Result:
-    """Run ``iters`` ADMM iterations and return X^{(iters)} (= Z, since E = I)."""
+    """Run ``iters`` ADMM iterations; X^{(iters)} and Z = X E."""
     Yl = Yl.astype(np.float64)
     Yh = Yh.astype(np.float64)
     den = denominator(pr.p, pr.q, pr.b, pr.window, pr.K)
@@ -376,7 +400,7 @@ def solve(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, init: str = "
             objs.append(objective(X, Yl, Yh, pr, omega))
             res.append(fixed_point_residual(nst, st, pr.rho))
         st = nst
-    return Result(X=X, state=st, objective=objs, residual=res)
+    return Result(X=X, state=st, objective=objs, residual=res, Z=compose(X, pr))
 
 
 # --------------------------------------------------- first two iterations, few bands
@@ -388,7 +412,8 @@ def two_iterations_bands(Yl: np.ndarray, Yh: np.ndarray, pr: Problem,
     It is the same arithmetic as two calls of ``admm_step``: with Q^{(0)} = Sigma^{(0)} = 0
     the first X-update needs no regulariser term, and X^{(2)}_c needs the regulariser
     term of C^{(1)} only for band c.  The bands are coupled by the P2-update alone,
-    which is computed for all bands."""
+    which is computed for all bands.  Without a subspace basis only."""
+    assert pr.E is None
     Yl = Yl.astype(np.float64)
     Yh = Yh.astype(np.float64)
     den = denominator(pr.p, pr.q, pr.b, pr.window, pr.K)

@@ -68,6 +68,8 @@ struct DeviceGuard {
 
 int validate(const nlpr_params& q) {
   auto bad = [](const std::string& m) { return fail(NLPR_ERR_UNSUPPORTED_SHAPE, m); };
+  if (q.reserved != 0) return fail(NLPR_ERR_INVALID_ARG, "reserved must be 0");
+  if (q.Ls < 0 || q.Ls > std::min(q.L, kMaxLs)) return bad("Ls must lie in [0, min(L, 32)]");
   LineFFT tmp{};
   if (q.p < 8 || q.q < 8 || q.p > kMaxFFTLen || q.q > kMaxFFTLen)
     return bad("p and q must lie in [8, 4096]");
@@ -100,6 +102,10 @@ int validate(const nlpr_params& q) {
 // ---------------------------------------------------------------------------- scenes
 void scene_free(Plan* P) {
   if (!P) return;
+  hipFree(P->d_E);
+  hipFree(P->d_Ep);
+  hipFree(P->d_M);
+  hipFree(P->d_Rt);
   hipFree(P->d_taus);
   hipFree(P->d_invden);
   hipFree(P->d_tw_p);
@@ -112,14 +118,18 @@ void scene_free(Plan* P) {
 
 // Validate, upload the blur taps and R, precompute the tables, tune the FFT shapes and lay
 // out the scene's part of the workspace.
-int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_host, Plan** out) {
+int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_host,
+                 const float* E_host, Plan** out) {
   *out = nullptr;
   int rc = validate(prm);
   if (rc) return rc;
+  if ((prm.Ls > 0) != (E_host != nullptr))
+    return fail(NLPR_ERR_INVALID_ARG, "a basis E must be given exactly when Ls > 0");
   Plan* P = new (std::nothrow) Plan();
   if (!P) return fail(NLPR_ERR_INVALID_ARG, "out of host memory");
   P->prm = prm;
-  const int p = prm.p, q = prm.q, L = prm.L, Lh = prm.Lh, r = prm.blur_radius;
+  P->Lx = prm.Ls > 0 ? prm.Ls : prm.L;
+  const int p = prm.p, q = prm.q, L = prm.L, Lh = prm.Lh, r = prm.blur_radius, Lx = P->Lx;
   // W+ in storage order: (0, 1..S), then tau1 = 1..S with tau2 = -S..S
   if (prm.flags & NLPR_LOCAL_WINDOW) {
     P->taus = {0, 1, 1, 0};
@@ -161,6 +171,16 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
     set_error("upload of the plan tables failed");
     return cleanup(NLPR_ERR_HIP);
   }
+  if (E_host) {
+    if (hipMalloc(&P->d_E, (size_t)Lx * L * sizeof(float)) != hipSuccess ||
+        hipMalloc(&P->d_Ep, (size_t)L * Lx * sizeof(float)) != hipSuccess ||
+        hipMalloc(&P->d_M, (size_t)Lx * Lx * sizeof(float)) != hipSuccess ||
+        hipMalloc(&P->d_Rt, (size_t)Lx * Lh * sizeof(float)) != hipSuccess ||
+        hipMemcpy(P->d_E, E_host, (size_t)Lx * L * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("allocation or upload of the subspace tables failed");
+      return cleanup(NLPR_ERR_HIP);
+    }
+  }
   if ((rc = launch_precompute(*P))) return cleanup(rc);
   if (hipDeviceSynchronize() != hipSuccess) {
     set_error("plan precompute failed");
@@ -174,8 +194,8 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
     P->sz[slot] = bytes;
     off = align256(off + std::max<size_t>(bytes, 4));
   };
-  const size_t pl = plane * L * sizeof(float);
-  take(B_SIGMA, sweep_sigma_bytes(P->sweep, q, L, P->npairs, P->npatch));
+  const size_t pl = plane * Lx * sizeof(float);
+  take(B_SIGMA, sweep_sigma_bytes(P->sweep, q, Lx, P->npairs, P->npatch));
   take(B_MU, (size_t)P->npairs * plane * sizeof(float));
   take(B_C, pl);
   take(B_L1, pl);
@@ -183,8 +203,14 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
   take(B_BX, pl);
   take(B_W1, pl);
   take(B_W2, pl);
-  take(B_F, (size_t)((L + 1) / 2) * plane * sizeof(float2));
-  take(B_HALO, (size_t)L * P->sweep.ntiles * P->sweep.halo * q * sizeof(float));
+  take(B_F, (size_t)((Lx + 1) / 2) * plane * sizeof(float2));
+  take(B_HALO, (size_t)Lx * P->sweep.ntiles * P->sweep.halo * q * sizeof(float));
+  if (E_host) {                            // the X iterate and the projected Y_l
+    const size_t lowres = (size_t)(p / prm.d) * (q / prm.d) * Lx * sizeof(float);
+    take(B_Z, pl);
+    take(B_YLE, lowres);
+    take(B_YLP, lowres);
+  }
   P->ws_bytes = off;
   *out = P;
   return NLPR_OK;
@@ -196,7 +222,12 @@ SceneDesc static_desc(const Plan& P) {
   const nlpr_params& q = P.prm;
   d.p = q.p;
   d.q = q.q;
-  d.L = q.L;
+  d.L = P.Lx;
+  d.Lz = q.L;
+  d.subspace = P.d_E ? 1 : 0;
+  d.E = P.d_E;
+  d.Ep = P.d_Ep;
+  d.M = P.d_M;
   d.Lh = q.Lh;
   d.d = q.d;
   d.r = q.blur_radius;
@@ -221,7 +252,7 @@ SceneDesc static_desc(const Plan& P) {
   d.taus = P.d_taus;
   d.invden = P.d_invden;
   d.blur = P.d_blur;
-  d.R = P.d_R;
+  d.R = P.d_E ? P.d_Rt : P.d_R;
   d.G = P.d_G;
   return d;
 }
@@ -310,6 +341,17 @@ int batch_build(Batch& B) {
     }
     if (!it.empty() && (rc = add_group(B, KD_PIXEL, it, 256, 0, cls, 0))) return rc;
   }
+  // scenes with a subspace basis: low-resolution projections / P1, and Z = X E
+  for (Kind kind : {KD_LOWRES, KD_COMPOSE}) {
+    std::vector<int2> it;
+    for (int s = 0; s < n; ++s) {
+      const Plan& P = *B.scenes[s];
+      if (!P.d_E) continue;
+      const int c = kind == KD_LOWRES ? lowres_blocks(P) : pixel_blocks(P);
+      for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+    }
+    if ((rc = add_group(B, kind, it, 256, 0, 0, 0))) return rc;
+  }
   if ((rc = simple(KD_ROWS, rows_blocks, rows_lds, rows_block))) return rc;
   if ((rc = simple(KD_COLS, cols_blocks, cols_lds, cols_block))) return rc;
   // the sweep: one launch per (patch radius, items per thread)
@@ -389,8 +431,15 @@ int ensure_events(Batch& B) {
 // P/Lambda update, the sweep and the right-hand-side assembly.
 int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
   int rc;
-  bool reg = false;
-  for (const Plan* P : B.scenes) reg = reg || P->npairs > 0;
+  bool reg = false, sub = false;
+  for (const Plan* P : B.scenes) {
+    reg = reg || P->npairs > 0;
+    sub = sub || P->d_E != nullptr;
+  }
+  if (sub) {
+    StageTimer tm(B, s, NLPR_STAGE_INIT);
+    if ((rc = launch_project(B, B_YL, B_YLE, B_YLP, s))) return rc;
+  }
   {
     StageTimer tm(B, s, NLPR_STAGE_WEIGHTS);
     if ((rc = launch_weights(B, B_YH, B_MU, s))) return rc;
@@ -398,7 +447,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
   if (!resume) {
     StageTimer tm(B, s, NLPR_STAGE_INIT);
     // X0 into Z, W2 = P2 + Lambda2 = X0, Lambda = 0, W1 = P1 + Lambda1 = B X0, C = B^T W1 + W2
-    if ((rc = launch_init(B, B_YL, B_Z, B_L1, B_L2, B_W2, s))) return rc;
+    if ((rc = launch_init(B, B_YL, B_YLP, B_Z, B_L1, B_L2, B_W2, s))) return rc;
     if ((rc = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return rc;
     if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s))) return rc;
   }
@@ -414,6 +463,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     {
       StageTimer tm(B, s, NLPR_STAGE_PUPDATE);
       if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
+      if (sub && (rc = launch_p1_subspace(B, B_BX, B_YLE, B_L1, B_W1, s))) return rc;
     }
     if (reg) {
       const bool first = (t == 0 && !resume);
@@ -424,6 +474,10 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
       StageTimer tm(B, s, NLPR_STAGE_ASSEMBLE);
       if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
     }
+  }
+  if (sub) {
+    StageTimer tm(B, s, NLPR_STAGE_INIT);
+    if ((rc = launch_compose(B, B_Z, B_OUT, s))) return rc;
   }
   return NLPR_OK;
 }
@@ -448,7 +502,14 @@ int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float*
       d.buf[k] = base + P.off[k];
     d.buf[B_YL] = const_cast<float*>(Yl[i]);
     d.buf[B_YH] = const_cast<float*>(Yh[i]);
-    d.buf[B_Z] = Z[i];
+    if (P.d_E) {                       // X lives in the workspace; Z = X E at the end
+      d.buf[B_Z] = base + P.off[B_Z];
+      d.buf[B_YLE] = base + P.off[B_YLE];
+      d.buf[B_YLP] = base + P.off[B_YLP];
+      d.buf[B_OUT] = Z[i];
+    } else {
+      d.buf[B_Z] = Z[i];
+    }
     d.buf[B_TMP] = base + P.off[B_BX];
     descs[i] = d;
   }
@@ -535,7 +596,7 @@ int region_of(const Plan& P, int region, size_t* offset, size_t* bytes) {
 
 // Create a batch from scene parameters (n >= 1).
 int batch_create(Batch& B, int n, const nlpr_params* params, const float* const* blur,
-                 const float* const* R) {
+                 const float* const* R, const float* const* E) {
   if (n < 1 || !params || !blur || !R) return fail(NLPR_ERR_INVALID_ARG, "NULL argument or n < 1");
   const uint32_t bf = params[0].flags & kBatchFlags;
   for (int i = 0; i < n; ++i) {
@@ -554,7 +615,7 @@ int batch_create(Batch& B, int n, const nlpr_params* params, const float* const*
   B.use_graph = (bf & NLPR_GRAPH) != 0;
   for (int i = 0; i < n; ++i) {
     Plan* P = nullptr;
-    int rc = scene_create(params[i], blur[i], R[i], &P);
+    int rc = scene_create(params[i], blur[i], R[i], E ? E[i] : nullptr, &P);
     if (rc) {
       batch_release(B);
       return rc;
@@ -593,12 +654,13 @@ int nlpr_plan_create(const nlpr_params* params, const float* blur_host, const fl
                      const float* E_host, nlpr_plan** out) {
   if (!params || !blur_host || !R_host || !out) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
-  if (E_host) return fail(NLPR_ERR_UNSUPPORTED_SHAPE, "a subspace basis E is not supported (E must be NULL)");
   int rc = validate(*params);
   if (rc) return rc;
+  if ((params->Ls > 0) != (E_host != nullptr))
+    return fail(NLPR_ERR_INVALID_ARG, "a basis E must be given exactly when Ls > 0");
   nlpr_plan* h = new (std::nothrow) nlpr_plan();
   if (!h) return fail(NLPR_ERR_INVALID_ARG, "out of host memory");
-  rc = batch_create(h->B, 1, params, &blur_host, &R_host);
+  rc = batch_create(h->B, 1, params, &blur_host, &R_host, &E_host);
   if (rc) {
     delete h;
     return rc;
@@ -666,6 +728,8 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
   int rc;
   for (int i = 0; i < need[stage]; ++i)
     if ((rc = check_device_ptr(bufs[i], "stage buffer"))) return rc;
+  if (P.d_E && (stage == NLPR_STAGE_INIT || stage == NLPR_STAGE_PUPDATE))
+    return fail(NLPR_ERR_UNSUPPORTED_SHAPE, "the INIT and PUPDATE stages take no subspace basis");
   DeviceGuard dg(B.device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   SceneDesc d = static_desc(P);
@@ -720,7 +784,7 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
       put(B_C, 6);
       return run([&] {
         int r2;
-        if ((r2 = launch_init(B, B_YL, B_Z, B_L1, B_L2, B_W2, s))) return r2;
+        if ((r2 = launch_init(B, B_YL, B_YLP, B_Z, B_L1, B_L2, B_W2, s))) return r2;
         if ((r2 = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return r2;
         return launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s);
       });
@@ -736,12 +800,12 @@ int nlpr_stage_time(nlpr_plan* plan, int stage, double* ms_total, int64_t* launc
 
 // ------------------------------------------------------------------------------ batch
 int nlpr_batch_create(int32_t n, const nlpr_params* params, const float* const* blur_host,
-                      const float* const* R_host, nlpr_batch** out) {
+                      const float* const* R_host, const float* const* E_host, nlpr_batch** out) {
   if (!out) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
   nlpr_batch* h = new (std::nothrow) nlpr_batch();
   if (!h) return fail(NLPR_ERR_INVALID_ARG, "out of host memory");
-  int rc = batch_create(h->B, n, params, blur_host, R_host);
+  int rc = batch_create(h->B, n, params, blur_host, R_host, E_host);
   if (rc) {
     delete h;
     return rc;

@@ -22,11 +22,6 @@ __device__ __forceinline__ int wrapi(int x, int n) {
   return x < 0 ? x + n : x;
 }
 
-template <typename T>
-__device__ __forceinline__ T* slot(const SceneDesc& S, int k) {
-  return k < 0 ? nullptr : static_cast<T*>(S.buf[k]);
-}
-
 // ------------------------------------------------------------------------- precompute
 // tw[m] = exp(-2 pi i m / n), in FP64, stored FP32.
 __global__ void twiddle_kernel(float2* tw, int n) {
@@ -107,6 +102,172 @@ __global__ void g_kernel(const float* R, int L, int Lh, double ratio, float* G) 
     for (int b = 0; b < Lh; ++b) G[a * Lh + b] = (float)A[a][Lh + b];
 }
 
+// With a subspace basis E (Ls x L), in FP64 (one thread; Ls <= 32):
+//   M  = (E E^T + rho I)^{-1}            Ls x Ls   (P1-update, eq. (Qh_update))
+//   Ep = E^T (E E^T)^{-1}                L x Ls    (default start X0 = up(Y_l) Ep)
+//   Rt = E R                             Ls x Lh   (P2-update with E R in place of R)
+__device__ void gauss_jordan(double (*A)[2 * kMaxLs], int n) {
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (piv != col)
+      for (int j = 0; j < 2 * n; ++j) {
+        const double t = A[col][j];
+        A[col][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    const double inv = 1.0 / A[col][col];
+    for (int j = 0; j < 2 * n; ++j) A[col][j] *= inv;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = A[r][col];
+      if (f != 0.0)
+        for (int j = 0; j < 2 * n; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+}
+
+__global__ void subspace_kernel(const float* E, const float* R, int L, int Ls, int Lh, double rho,
+                                float* M, float* Ep, float* Rt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double A[kMaxLs][2 * kMaxLs];
+  double EEt[kMaxLs][kMaxLs];
+  for (int a = 0; a < Ls; ++a)
+    for (int b = 0; b < Ls; ++b) {
+      double s = 0.0;
+      for (int c = 0; c < L; ++c) s += (double)E[a * L + c] * (double)E[b * L + c];
+      EEt[a][b] = s;
+    }
+  for (int pass = 0; pass < 2; ++pass) {      // pass 0: (E E^T + rho I)^{-1}; 1: (E E^T)^{-1}
+    for (int a = 0; a < Ls; ++a)
+      for (int b = 0; b < Ls; ++b) {
+        A[a][b] = EEt[a][b] + (pass == 0 && a == b ? rho : 0.0);
+        A[a][Ls + b] = (a == b) ? 1.0 : 0.0;
+      }
+    gauss_jordan(A, Ls);
+    if (pass == 0) {
+      for (int a = 0; a < Ls; ++a)
+        for (int b = 0; b < Ls; ++b) M[a * Ls + b] = (float)A[a][Ls + b];
+    } else {
+      for (int c = 0; c < L; ++c)
+        for (int b = 0; b < Ls; ++b) {
+          double s = 0.0;
+          for (int a = 0; a < Ls; ++a) s += (double)E[a * L + c] * A[a][Ls + b];
+          Ep[c * Ls + b] = (float)s;
+        }
+    }
+  }
+  for (int a = 0; a < Ls; ++a)
+    for (int h = 0; h < Lh; ++h) {
+      double s = 0.0;
+      for (int c = 0; c < L; ++c) s += (double)E[a * L + c] * (double)R[c * Lh + h];
+      Rt[a * Lh + h] = (float)s;
+    }
+}
+
+// Y_l E^T and Y_l E^+ at every low-resolution pixel m: [Ls][p/d][q/d] each.
+__global__ void __launch_bounds__(256)
+project_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yl_s,
+               int yle_s, int ylp_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int nl = (S.p / S.d) * (S.q / S.d);
+  const int m = it.y * 256 + threadIdx.x;
+  if (m >= nl) return;
+  const int Ls = S.L, Lz = S.Lz;
+  const gfloat* __restrict__ Yl = gslot<const gfloat>(S, yl_s);
+  const gfloat* __restrict__ E = as_global(S.E);
+  const gfloat* __restrict__ Ep = as_global(S.Ep);
+  float ye[kMaxLs], yp[kMaxLs];
+#pragma unroll
+  for (int k = 0; k < kMaxLs; ++k) ye[k] = yp[k] = 0.f;
+  for (int c = 0; c < Lz; ++c) {
+    const float y = Yl[(size_t)c * nl + m];
+#pragma unroll
+    for (int k = 0; k < kMaxLs; ++k)
+      if (k < Ls) {
+        ye[k] += y * E[k * Lz + c];
+        yp[k] += y * Ep[c * Ls + k];
+      }
+  }
+  gfloat* yle = gslot<gfloat>(S, yle_s);
+  gfloat* ylp = gslot<gfloat>(S, ylp_s);
+#pragma unroll
+  for (int k = 0; k < kMaxLs; ++k)
+    if (k < Ls) {
+      yle[(size_t)k * nl + m] = ye[k];
+      ylp[(size_t)k * nl + m] = yp[k];
+    }
+}
+
+// P1 on the sampled pixels with a basis (eq. (Qh_update)):
+//   P1 = (rho BX + Y_l E^T - rho Lambda1) (E E^T + rho I)^{-1},
+// then Lambda1 -= BX - P1 and W1 = P1 + Lambda1.  One thread per low-resolution pixel.
+__global__ void __launch_bounds__(256)
+p1_subspace_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int bx_s,
+                   int yle_s, int l1_s, int w1_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int qd = S.q / S.d;
+  const int nl = (S.p / S.d) * qd;
+  const int m = it.y * 256 + threadIdx.x;
+  if (m >= nl) return;
+  const int Ls = S.L;
+  const size_t plane = (size_t)S.p * S.q;
+  const size_t j = (size_t)(m / qd) * S.d * S.q + (size_t)(m % qd) * S.d;
+  const gfloat* __restrict__ BX = gslot<const gfloat>(S, bx_s);
+  const gfloat* __restrict__ yle = gslot<const gfloat>(S, yle_s);
+  gfloat* __restrict__ L1 = gslot<gfloat>(S, l1_s);
+  gfloat* __restrict__ W1 = gslot<gfloat>(S, w1_s);
+  const gfloat* __restrict__ M = as_global(S.M);
+  const float rho = S.rho;
+  float v[kMaxLs], bx[kMaxLs], l1[kMaxLs];
+#pragma unroll
+  for (int k = 0; k < kMaxLs; ++k)
+    if (k < Ls) {
+      bx[k] = BX[k * plane + j];
+      l1[k] = L1[k * plane + j];
+      v[k] = rho * bx[k] + yle[(size_t)k * nl + m] - rho * l1[k];
+    }
+#pragma unroll
+  for (int k2 = 0; k2 < kMaxLs; ++k2)
+    if (k2 < Ls) {
+      float p1 = 0.f;
+#pragma unroll
+      for (int k = 0; k < kMaxLs; ++k)
+        if (k < Ls) p1 += v[k] * M[k * Ls + k2];
+      const float l1n = l1[k2] - (bx[k2] - p1);
+      L1[k2 * plane + j] = l1n;
+      W1[k2 * plane + j] = p1 + l1n;
+    }
+}
+
+// Z = X E at every pixel: Z_c = sum_s X_s E[s][c].
+__global__ void __launch_bounds__(256)
+compose_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
+               int z_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const size_t plane = (size_t)S.p * S.q;
+  const int j = it.y * 256 + threadIdx.x;
+  if (j >= (int)plane) return;
+  const int Ls = S.L, Lz = S.Lz;
+  const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
+  gfloat* __restrict__ Z = gslot<gfloat>(S, z_s);
+  const gfloat* __restrict__ E = as_global(S.E);
+  float x[kMaxLs];
+#pragma unroll
+  for (int k = 0; k < kMaxLs; ++k) x[k] = (k < Ls) ? X[k * plane + j] : 0.f;
+  for (int c = 0; c < Lz; ++c) {
+    float z = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMaxLs; ++k)
+      if (k < Ls) z += x[k] * E[k * Lz + c];
+    Z[c * plane + j] = z;
+  }
+}
+
 // ---------------------------------------------------------------------------- weights
 // mu_{i tau} = scale * exp(-inv_h2 * sum_{k in P} e_tau(i - k)),
 // e_tau(j) = sum_c (Y_c(j) - Y_c(j - tau))^2.  Local block = (shift, tile row, tile col);
@@ -126,9 +287,9 @@ weights_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
   const int EY = WT_Y + 2 * K, EX = WT_X + 2 * K;
   float* e = wsh;             // EY x EX
   float* hs = wsh + EY * EX;  // EY x WT_X
-  const int2 t = S.taus[n];
-  const float* Yh = slot<const float>(S, yh_s);
-  float* mun = slot<float>(S, mu_s) + (size_t)n * p * q;
+  const int2 t = tau_at(S, n);
+  const gfloat* Yh = gslot<const gfloat>(S, yh_s);
+  gfloat* mun = gslot<gfloat>(S, mu_s) + (size_t)n * p * q;
   if (S.unweighted) {
     for (int idx = threadIdx.x; idx < WT_Y * WT_X; idx += blockDim.x) {
       const int y = y0 + idx / WT_X, x = x0 + idx % WT_X;
@@ -168,8 +329,8 @@ weights_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
 // ------------------------------------------------------------------ elementwise planes
 // One thread per element of [L][p][q]; local block lb covers elements lb*256 .. +255.
 __global__ void __launch_bounds__(256)
-init_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yl_s, int x0_s,
-            int l1_s, int l2_s, int w2_s) {
+init_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yl_s, int ylp_s,
+            int x0_s, int l1_s, int l2_s, int w2_s) {
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
   const int p = S.p, q = S.q, d = S.d;
@@ -178,12 +339,13 @@ init_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   const int c = (int)(e / ((size_t)p * q));
   const int rem = (int)(e - (size_t)c * p * q);
   const int i1 = rem / q, i2 = rem - i1 * q;
-  const float* Yl = slot<const float>(S, yl_s);
+  // with a basis the start is the upsampled coefficient image Y_l E^+ (Ls bands)
+  const gfloat* Yl = gslot<const gfloat>(S, S.subspace ? ylp_s : yl_s);
   const float x = S.init_zero ? 0.f : Yl[((size_t)c * (p / d) + i1 / d) * (q / d) + i2 / d];
-  slot<float>(S, x0_s)[e] = x;
-  slot<float>(S, w2_s)[e] = x;
-  slot<float>(S, l1_s)[e] = 0.f;
-  slot<float>(S, l2_s)[e] = 0.f;
+  gslot<gfloat>(S, x0_s)[e] = x;
+  gslot<gfloat>(S, w2_s)[e] = x;
+  gslot<gfloat>(S, l1_s)[e] = 0.f;
+  gslot<gfloat>(S, l2_s)[e] = 0.f;
 }
 
 __global__ void __launch_bounds__(256)
@@ -191,7 +353,7 @@ fill_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
   const size_t e = (size_t)it.y * 256 + threadIdx.x;
-  if (e < (size_t)S.L * S.p * S.q) slot<float>(S, s_)[e] = 0.f;
+  if (e < (size_t)S.L * S.p * S.q) gslot<gfloat>(S, s_)[e] = 0.f;
 }
 
 // flag[0] |= 1 if any element of the slot is NaN or Inf (the flag is cleared beforehand by
@@ -202,7 +364,7 @@ finite_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, 
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
   const size_t e = (size_t)it.y * 256 + threadIdx.x;
-  if (e < (size_t)S.L * S.p * S.q && !isfinite(slot<const float>(S, z_s)[e])) flag[0] = 1;
+  if (e < (size_t)S.L * S.p * S.q && !isfinite(gslot<const gfloat>(S, z_s)[e])) flag[0] = 1;
 }
 
 __global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
@@ -235,8 +397,8 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   float* tile = csh;
   float* tp = csh + TY * TX;
   const size_t plane = (size_t)p * q;
-  const float* inc = slot<const float>(S, in_s) + (size_t)c * plane;
-  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) tp[idx] = S.blur[idx];
+  const gfloat* inc = gslot<const gfloat>(S, in_s) + (size_t)c * plane;
+  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) tp[idx] = as_global(S.blur)[idx];
   for (int idx = threadIdx.x; idx < TY * TX; idx += blockDim.x) {
     const int yy = idx / TX, xx = idx % TX;
     tile[idx] = inc[(size_t)wrapi(y0 - r + yy, p) * q + wrapi(x0 - r + xx, q)];
@@ -258,10 +420,10 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   const int gy2 = y0 + y;
   if (gy2 >= p) return;
   const bool reg = S.npairs > 0;
-  const float* a1 = (reg || !(reg_mask & 1)) ? slot<const float>(S, add1_s) : nullptr;
-  const float* a2 = (reg || !(reg_mask & 2)) ? slot<const float>(S, add2_s) : nullptr;
-  const float* hb = reg ? slot<const float>(S, halo_s) : nullptr;
-  float* out = slot<float>(S, out_s);
+  const gfloat* a1 = (reg || !(reg_mask & 1)) ? gslot<const gfloat>(S, add1_s) : nullptr;
+  const gfloat* a2 = (reg || !(reg_mask & 2)) ? gslot<const gfloat>(S, add2_s) : nullptr;
+  const gfloat* hb = reg ? gslot<const gfloat>(S, halo_s) : nullptr;
+  gfloat* out = gslot<gfloat>(S, out_s);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int gx2 = x0 + xb + e;
@@ -294,26 +456,13 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
 // O(lambda1/rho |Y_h|), which avoids a large cancellation.
 //   Lambda1 -= BX - P1,  Lambda2 -= X - P2;  W1 = P1 + Lambda1,  W2 = P2 + Lambda2
 template <int LHM>
-__global__ void __launch_bounds__(256)
-pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
-               int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1_s, int w2_s) {
-  const int2 it = items[blockIdx.x];
-  const SceneDesc& S = sd[it.x];
-  const int p = S.p, q = S.q, L = S.L, Lh = S.Lh, d = S.d;
-  const int j = it.y * 256 + threadIdx.x;
+__device__ __forceinline__ void pupdate_body(
+    const gfloat* __restrict__ X, const gfloat* __restrict__ BX, const gfloat* __restrict__ Yl,
+    const gfloat* __restrict__ Yh, gfloat* __restrict__ L1, gfloat* __restrict__ L2,
+    gfloat* __restrict__ W1, gfloat* __restrict__ W2, const gfloat* __restrict__ R,
+    const gfloat* __restrict__ G, int p, int q, int L, int Lh, int d, float rho, float inv_1prho,
+    int subspace, int j) {
   const size_t plane = (size_t)p * q;
-  if (j >= (int)plane) return;
-  const float* X = slot<const float>(S, x_s);
-  const float* BX = slot<const float>(S, bx_s);
-  const float* Yl = slot<const float>(S, yl_s);
-  const float* Yh = slot<const float>(S, yh_s);
-  float* L1 = slot<float>(S, l1_s);
-  float* L2 = slot<float>(S, l2_s);
-  float* W1 = slot<float>(S, w1_s);
-  float* W2 = slot<float>(S, w2_s);
-  const float* R = S.R;
-  const float* G = S.G;
-  const float rho = S.rho, inv_1prho = S.inv_1prho;
   const int i1 = j / q, i2 = j - i1 * q;
   const bool sampled = (i1 % d == 0) && (i2 % d == 0);
   const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
@@ -327,7 +476,7 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
     for (int h = 0; h < LHM; ++h)
       if (h < Lh) res[h] -= a0 * R[c * Lh + h];
   }
-  float u[LHM];                        // u = res G
+  float u[LHM];                           // u = res G
 #pragma unroll
   for (int h2 = 0; h2 < LHM; ++h2) {
     float s = 0.f;
@@ -347,12 +496,28 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
     const float l2n = l2 - (x - p2);
     L2[o] = l2n;
     W2[o] = p2 + l2n;
+    if (sampled && subspace) continue;   // coupled across bands: p1_subspace_kernel
     const float bx = BX[o], l1 = L1[o];
     const float p1 = sampled ? (rho * bx + Yl[c * lplane + lj] - rho * l1) * inv_1prho : bx - l1;
     const float l1n = l1 - (bx - p1);
     L1[o] = l1n;
     W1[o] = p1 + l1n;
   }
+}
+
+template <int LHM>
+__global__ void __launch_bounds__(256)
+pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
+               int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1_s, int w2_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int j = it.y * 256 + threadIdx.x;
+  if (j >= S.p * S.q) return;
+  pupdate_body<LHM>(gslot<const gfloat>(S, x_s), gslot<const gfloat>(S, bx_s),
+                    gslot<const gfloat>(S, yl_s), gslot<const gfloat>(S, yh_s),
+                    gslot<gfloat>(S, l1_s), gslot<gfloat>(S, l2_s), gslot<gfloat>(S, w1_s),
+                    gslot<gfloat>(S, w2_s), as_global(S.R), as_global(S.G),
+                    S.p, S.q, S.L, S.Lh, S.d, S.rho, S.inv_1prho, S.subspace, j);
 }
 
 template <typename Kern, typename... Args>
@@ -378,10 +543,10 @@ size_t weights_lds(const Plan& P) {
   return (size_t)((WT_Y + 2 * K) * (WT_X + 2 * K) + (WT_Y + 2 * K) * WT_X) * sizeof(float);
 }
 int plane_blocks(const Plan& P) {
-  return (int)(((size_t)P.prm.L * P.prm.p * P.prm.q + 255) / 256);
+  return (int)(((size_t)P.Lx * P.prm.p * P.prm.q + 255) / 256);
 }
 int conv_blocks(const Plan& P) {
-  return ceil_div(P.prm.q, CV_X) * ceil_div(P.prm.p, CV_Y) * P.prm.L;
+  return ceil_div(P.prm.q, CV_X) * ceil_div(P.prm.p, CV_Y) * P.Lx;
 }
 size_t conv_lds(const Plan& P) {
   const int r = P.prm.blur_radius;
@@ -399,8 +564,13 @@ int launch_precompute(Plan& P) {
   hipLaunchKernelGGL(den_kernel, dim3(ceil_div(q, 128), p), dim3(128), 0, nullptr, P.d_invden, p,
                      q, P.d_blur, P.prm.blur_radius, P.d_taus, P.npairs, P.npatch);
   NLPR_LAUNCH_CHECK("den_kernel");
-  hipLaunchKernelGGL(g_kernel, dim3(1), dim3(1), 0, nullptr, P.d_R, P.prm.L, P.prm.Lh,
-                     P.prm.rho / P.prm.lambda1, P.d_G);
+  if (P.d_E) {
+    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(1), 0, nullptr, P.d_E, P.d_R, P.prm.L, P.Lx,
+                       P.prm.Lh, P.prm.rho, P.d_M, P.d_Ep, P.d_Rt);
+    NLPR_LAUNCH_CHECK("subspace_kernel");
+  }
+  hipLaunchKernelGGL(g_kernel, dim3(1), dim3(1), 0, nullptr, P.d_E ? P.d_Rt : P.d_R, P.Lx,
+                     P.prm.Lh, P.prm.rho / P.prm.lambda1, P.d_G);
   NLPR_LAUNCH_CHECK("g_kernel");
   return NLPR_OK;
 }
@@ -409,8 +579,8 @@ int launch_weights(const Batch& B, int yh, int mu, hipStream_t s) {
   return launch_groups(B, KD_WEIGHTS, "weights_kernel", weights_kernel, s, yh, mu);
 }
 
-int launch_init(const Batch& B, int yl, int x0, int l1, int l2, int w2, hipStream_t s) {
-  return launch_groups(B, KD_PLANE, "init_kernel", init_kernel, s, yl, x0, l1, l2, w2);
+int launch_init(const Batch& B, int yl, int ylp, int x0, int l1, int l2, int w2, hipStream_t s) {
+  return launch_groups(B, KD_PLANE, "init_kernel", init_kernel, s, yl, ylp, x0, l1, l2, w2);
 }
 
 int launch_fill(const Batch& B, int slot_, hipStream_t s) {
@@ -449,6 +619,22 @@ int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2
     NLPR_LAUNCH_CHECK("pupdate_kernel");
   }
   return NLPR_OK;
+}
+
+int lowres_blocks(const Plan& P) {
+  return ceil_div((P.prm.p / P.prm.d) * (P.prm.q / P.prm.d), 256);
+}
+
+int launch_project(const Batch& B, int yl, int yle, int ylp, hipStream_t s) {
+  return launch_groups(B, KD_LOWRES, "project_kernel", project_kernel, s, yl, yle, ylp);
+}
+
+int launch_p1_subspace(const Batch& B, int bx, int yle, int l1, int w1, hipStream_t s) {
+  return launch_groups(B, KD_LOWRES, "p1_subspace_kernel", p1_subspace_kernel, s, bx, yle, l1, w1);
+}
+
+int launch_compose(const Batch& B, int x, int z, hipStream_t s) {
+  return launch_groups(B, KD_COMPOSE, "compose_kernel", compose_kernel, s, x, z);
 }
 
 int lh_class(int Lh) { return Lh == 1 ? 1 : (Lh <= 4 ? 4 : kMaxLh); }

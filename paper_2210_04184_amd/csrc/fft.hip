@@ -99,7 +99,7 @@ template <bool INV> struct Dft<3, INV> {
 // radices of the earlier stages.  Threads t < tpl of the line take part; tpl >= ceil(n/8)
 // keeps every thread at <= ceil(8/R) butterflies.  All threads of the block must call it.
 template <int R, bool INV>
-__device__ void fft_stage(float2* buf, int n, int Ns, const float2* __restrict__ tw, int t,
+__device__ __forceinline__ void fft_stage(float2* buf, int n, int Ns, const gfloat* __restrict__ tw, int t,
                           int tpl) {
   constexpr int MAXB = (8 + R - 1) / R;
   const int nb = n / R;
@@ -121,7 +121,7 @@ __device__ void fft_stage(float2* buf, int n, int Ns, const float2* __restrict__
       const int k = j % Ns;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * k * step];
+        float2 w = ldg2(tw + 2 * (r * k * step));
         if (INV) w.y = -w.y;
         v[u][r] = cmul(v[u][r], w);
       }
@@ -135,14 +135,15 @@ __device__ void fft_stage(float2* buf, int n, int Ns, const float2* __restrict__
 }
 
 template <bool INV>
-__device__ void fft_line(float2* buf, const LineFFT& f, int t, int tpl) {
+__device__ __forceinline__ void fft_line(float2* buf, const LineFFT& f, int t, int tpl) {
   int Ns = 1;
   for (int s = 0; s < f.nfac; ++s) {
     const int R = f.fac[s];
-    if (R == 8) fft_stage<8, INV>(buf, f.n, Ns, f.tw, t, tpl);
-    else if (R == 4) fft_stage<4, INV>(buf, f.n, Ns, f.tw, t, tpl);
-    else if (R == 2) fft_stage<2, INV>(buf, f.n, Ns, f.tw, t, tpl);
-    else fft_stage<3, INV>(buf, f.n, Ns, f.tw, t, tpl);
+    const gfloat* tw = (const gfloat*)f.tw;
+    if (R == 8) fft_stage<8, INV>(buf, f.n, Ns, tw, t, tpl);
+    else if (R == 4) fft_stage<4, INV>(buf, f.n, Ns, tw, t, tpl);
+    else if (R == 2) fft_stage<2, INV>(buf, f.n, Ns, tw, t, tpl);
+    else fft_stage<3, INV>(buf, f.n, Ns, tw, t, tpl);
     Ns *= R;
   }
 }
@@ -157,9 +158,9 @@ __global__ void fft_rows_fwd(const SceneDesc* __restrict__ sd, const int2* __res
   const int nrb = ceil_div(p, lpb);
   const int m = it.y / nrb, row0 = (it.y - m * nrb) * lpb;
   const size_t plane = (size_t)p * q;
-  const float* C = static_cast<const float*>(S.buf[c_s]);
-  const float* Ca = C + (size_t)(2 * m) * plane;
-  const float* Cb = (2 * m + 1 < L) ? C + (size_t)(2 * m + 1) * plane : nullptr;
+  const gfloat* C = gslot<const gfloat>(S, c_s);
+  const gfloat* Ca = C + (size_t)(2 * m) * plane;
+  const gfloat* Cb = (2 * m + 1 < L) ? C + (size_t)(2 * m + 1) * plane : nullptr;
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
     float2 v = make_float2(0.f, 0.f);
@@ -173,10 +174,10 @@ __global__ void fft_rows_fwd(const SceneDesc* __restrict__ sd, const int2* __res
   const int g = threadIdx.x / tpl;
   const int t = (g < lpb) ? threadIdx.x - g * tpl : tpl;
   fft_line<false>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl);
-  float2* Fm = static_cast<float2*>(S.buf[f_s]) + (size_t)m * plane;
+  gfloat* Fm = gslot<gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex, interleaved
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
-    if (r < p) Fm[(size_t)r * q + i] = sh[e];
+    if (r < p) stg2(Fm + 2 * ((size_t)r * q + i), sh[e]);
   }
 }
 
@@ -191,11 +192,11 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
   const int ncb = ceil_div(q, cb);
   const int m = it.y / ncb, c0 = (it.y - m * ncb) * cb;
   const size_t plane = (size_t)p * q;
-  float2* Fm = static_cast<float2*>(S.buf[f_s]) + (size_t)m * plane;
-  const float* invden = S.invden;
+  gfloat* Fm = gslot<gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex, interleaved
+  const gfloat* invden = as_global(S.invden);
   for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
     const int i = e / cb, l = e - i * cb, col = c0 + l;
-    sh[l * p + i] = (col < q) ? Fm[(size_t)i * q + col] : make_float2(0.f, 0.f);
+    sh[l * p + i] = (col < q) ? ldg2(Fm + 2 * ((size_t)i * q + col)) : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const int G = blockDim.x / tpl;
@@ -218,7 +219,7 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
   }
   for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
     const int i = e / cb, l = e - i * cb, col = c0 + l;
-    if (col < q) Fm[(size_t)i * q + col] = sh[l * p + i];
+    if (col < q) stg2(Fm + 2 * ((size_t)i * q + col), sh[l * p + i]);
   }
 }
 
@@ -232,18 +233,18 @@ __global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __res
   const int nrb = ceil_div(p, lpb);
   const int m = it.y / nrb, row0 = (it.y - m * nrb) * lpb;
   const size_t plane = (size_t)p * q;
-  const float2* Fm = static_cast<const float2*>(S.buf[f_s]) + (size_t)m * plane;
+  const gfloat* Fm = gslot<const gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
-    sh[e] = (r < p) ? Fm[(size_t)r * q + i] : make_float2(0.f, 0.f);
+    sh[e] = (r < p) ? ldg2(Fm + 2 * ((size_t)r * q + i)) : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const int g = threadIdx.x / tpl;
   const int t = (g < lpb) ? threadIdx.x - g * tpl : tpl;
   fft_line<true>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl);
-  float* X = static_cast<float*>(S.buf[x_s]);
-  float* Xa = X + (size_t)(2 * m) * plane;
-  float* Xb = (2 * m + 1 < L) ? X + (size_t)(2 * m + 1) * plane : nullptr;
+  gfloat* X = gslot<gfloat>(S, x_s);
+  gfloat* Xa = X + (size_t)(2 * m) * plane;
+  gfloat* Xb = (2 * m + 1 < L) ? X + (size_t)(2 * m + 1) * plane : nullptr;
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
     if (r < p) {
@@ -289,10 +290,10 @@ int fft_block(int tpl) {
 }
 
 int rows_blocks(const Plan& P) {
-  return ceil_div(P.prm.p, P.fft.q_lpb) * ((P.prm.L + 1) / 2);
+  return ceil_div(P.prm.p, P.fft.q_lpb) * ((P.Lx + 1) / 2);
 }
 int cols_blocks(const Plan& P) {
-  return ceil_div(P.prm.q, P.fft.p_cb) * ((P.prm.L + 1) / 2);
+  return ceil_div(P.prm.q, P.fft.p_cb) * ((P.Lx + 1) / 2);
 }
 size_t rows_lds(const Plan& P) { return (size_t)P.fft.q_lpb * P.prm.q * sizeof(float2); }
 size_t cols_lds(const Plan& P) { return (size_t)P.fft.p_cb * P.prm.p * sizeof(float2); }
@@ -336,7 +337,7 @@ int autotune_fft(Plan& P) {
   FftShape best = default_fft_shape(p, q);
   const size_t plane = (size_t)p * q;
   // time on up to 16 band pairs so the launch fills the GPU like the real one
-  const int tp = std::max(1, std::min((P.prm.L + 1) / 2, 16));
+  const int tp = std::max(1, std::min((P.Lx + 1) / 2, 16));
   float* d_real = nullptr;
   float2* d_cplx = nullptr;
   SceneDesc* d_sd = nullptr;

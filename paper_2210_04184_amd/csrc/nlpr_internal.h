@@ -27,6 +27,7 @@ constexpr int kMaxBlurRadius = 16;
 constexpr int kMaxFFTFactors = 24;
 constexpr int kMaxFFTLen = 4096;
 constexpr size_t kMaxSweepLds = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kMaxLs = 32;                    // bands of X with a subspace basis
 
 // One-dimensional FFT of length n = product of fac[] (each 2, 3, 4 or 8).
 // tw[m] = exp(-2 pi i m / n), m in [0, n).
@@ -40,6 +41,9 @@ struct LineFFT {
 // Buffer slots of a scene descriptor.
 enum Slot {
   B_YL = 0, B_YH, B_Z, B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO, B_TMP,
+  B_OUT,     // Z = X E when a subspace basis is used (B_Z is then the X iterate)
+  B_YLE,     // Y_l E^T, [Ls][p/d][q/d]
+  B_YLP,     // Y_l E^+, [Ls][p/d][q/d]
   B_COUNT
 };
 
@@ -50,6 +54,7 @@ struct SceneDesc {
   int fq_tpl, fq_lpb;              // row FFT: threads per line, lines per block
   int fp_tpl, fp_cb;               // column FFT: threads per line, columns per block
   int init_zero, unweighted;
+  int subspace, Lz;                // basis in use; bands of Z (L is the number of X bands)
   float rho, inv_1prho, mu_scale, inv_h2;
   LineFFT fp, fq;
   const int2* taus;
@@ -57,6 +62,9 @@ struct SceneDesc {
   const float* blur;
   const float* R;
   const float* G;
+  const float* E;                  // [Ls][Lz]
+  const float* Ep;                 // E^+ = E^T (E E^T)^{-1}, [Lz][Ls]
+  const float* M;                  // (E E^T + rho I)^{-1}, [Ls][Ls]
   void* buf[B_COUNT];
 };
 
@@ -89,6 +97,11 @@ struct Plan {
   float* d_blur = nullptr;
   float* d_R = nullptr;
   float* d_G = nullptr;
+  int Lx = 0;                     // bands of X: Ls with a basis, else L
+  float* d_E = nullptr;           // [Ls][L]
+  float* d_Ep = nullptr;          // [L][Ls]
+  float* d_M = nullptr;           // [Ls][Ls]
+  float* d_Rt = nullptr;          // E R, [Ls][Lh]
   SweepShape sweep{};
   // workspace layout relative to the scene's base
   size_t off[B_COUNT] = {};
@@ -105,7 +118,10 @@ struct Group {
   int key0 = 0, key1 = 0;   // sweep: K, items per thread
 };
 
-enum Kind { KD_WEIGHTS = 0, KD_PLANE, KD_CONV, KD_PIXEL, KD_SWEEP, KD_ROWS, KD_COLS, KD_COUNT };
+enum Kind { KD_WEIGHTS = 0, KD_PLANE, KD_CONV, KD_PIXEL, KD_SWEEP, KD_ROWS, KD_COLS,
+            KD_LOWRES,   // one thread per low-resolution pixel of scenes with a basis
+            KD_COMPOSE,  // one thread per pixel of scenes with a basis
+            KD_COUNT };
 
 struct Batch {
   int device = 0;
@@ -156,6 +172,44 @@ void set_error(const std::string& msg);
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Pointers read from a descriptor are generic (flat); kernels convert them to the global
+// address space so the compiler emits global loads, and scalar loads for uniform addresses.
+// Vector elements move through clang ext-vector types (HIP's vector structs cannot be
+// copied out of an address-space-qualified object).
+typedef __attribute__((address_space(1))) float gfloat;
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef int v2i_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) v2f_t gv2f;
+typedef __attribute__((address_space(1))) v4f_t gv4f;
+typedef __attribute__((address_space(1))) v2i_t gv2i;
+__device__ __forceinline__ const gfloat* as_global(const float* p) { return (const gfloat*)p; }
+__device__ __forceinline__ gfloat* as_global(float* p) { return (gfloat*)p; }
+template <typename G>
+__device__ __forceinline__ G* gslot(const SceneDesc& S, int k) {
+  return k < 0 ? nullptr : (G*)(S.buf[k]);
+}
+__device__ __forceinline__ float2 ldg2(const gfloat* p) {
+  const v2f_t v = *(const gv2f*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void stg2(gfloat* p, float2 a) {
+  const v2f_t v = {a.x, a.y};
+  *(gv2f*)p = v;
+}
+__device__ __forceinline__ float4 ldg4(const gfloat* p) {
+  const v4f_t v = *(const gv4f*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stg4(gfloat* p, float4 a) {
+  const v4f_t v = {a.x, a.y, a.z, a.w};
+  *(gv4f*)p = v;
+}
+__device__ __forceinline__ int2 tau_at(const SceneDesc& S, int n) {
+  const v2i_t v = ((const gv2i*)S.taus)[n];
+  return make_int2(v.x, v.y);
+}
+
 // ---- plan precompute (dense.hip); runs once per scene on the null stream
 int launch_precompute(Plan& P);
 
@@ -174,14 +228,20 @@ size_t cols_lds(const Plan& P);
 
 // ---- batched kernels: each launches the groups of one kind with buffer slots (< 0: none)
 int launch_weights(const Batch& B, int yh, int mu, hipStream_t s);
-int launch_init(const Batch& B, int yl, int x0, int l1, int l2, int w2, hipStream_t s);
+int launch_init(const Batch& B, int yl, int ylp, int x0, int l1, int l2, int w2, hipStream_t s);
 // reg_mask: bit 0 / 1 mark add1 / add2 as regulariser terms (skipped, like the halo, for
 // scenes without a search window)
 int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int add2, int halo,
                 int reg_mask, hipStream_t s);
 int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,
                    hipStream_t s);
-int lh_class(int Lh);   // pupdate template class of a guide-band count: 1, 4 or 16
+int lh_class(int Lh);                // pupdate template class of a guide-band count: 1, 4 or 16
+int lowres_blocks(const Plan& P);
+// with a subspace basis: Y_l E^T and Y_l E^+ (once per solve), the P1-update on sampled
+// pixels, and Z = X E
+int launch_project(const Batch& B, int yl, int yle, int ylp, hipStream_t s);
+int launch_p1_subspace(const Batch& B, int bx, int yle, int l1, int w1, hipStream_t s);
+int launch_compose(const Batch& B, int x, int z, hipStream_t s);
 int launch_finite(const Batch& B, int z, int* flag, hipStream_t s);
 int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] slot
 int launch_xsolve(const Batch& B, int c, int x, int f, hipStream_t s);

@@ -38,25 +38,25 @@ constexpr int PADW = 4;  // mu rows in LDS are padded by one float4 on each side
 #ifndef NLPR_SWEEP_NT
 #define NLPR_SWEEP_NT 1
 #endif
-typedef float v4f __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ld_nt(const float* p) {
+__device__ __forceinline__ float4 ld_nt(const gfloat* p) {
 #if NLPR_SWEEP_NT
-  const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+  const v4f_t v = __builtin_nontemporal_load((const gv4f*)p);
 #else
-  const v4f v = *reinterpret_cast<const v4f*>(p);
+  const v4f_t v = *(const gv4f*)p;
 #endif
   return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ void st_nt(float* p, float4 v) {
-  v4f w = {v.x, v.y, v.z, v.w};
+__device__ __forceinline__ void st_nt(gfloat* p, float4 v) {
+  v4f_t w = {v.x, v.y, v.z, v.w};
 #if NLPR_SWEEP_NT
-  __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p));
+  __builtin_nontemporal_store(w, (gv4f*)p);
 #else
-  *reinterpret_cast<v4f*>(p) = w;
+  *(gv4f*)p = w;
 #endif
 }
 __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v, -m), m); }
 
+// ---- sweep kernel begin (the traffic record of the benchmark is keyed to this text)
 template <int K, int ITEMS, int NT, bool FIRST>
 __global__ void __launch_bounds__(NT)
 sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s, int mu_s,
@@ -65,12 +65,11 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const SceneDesc& S = sd[it_.x];
   const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
             H = S.halo;
-  const float* __restrict__ X = static_cast<const float*>(S.buf[x_s]);
-  const float* __restrict__ mu = static_cast<const float*>(S.buf[mu_s]);
-  float* __restrict__ sig = static_cast<float*>(S.buf[sig_s]);
-  float* __restrict__ creg = static_cast<float*>(S.buf[creg_s]);
-  float* __restrict__ halo = static_cast<float*>(S.buf[halo_s]);
-  const int2* __restrict__ taus = S.taus;
+  const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
+  const gfloat* __restrict__ mu = gslot<const gfloat>(S, mu_s);
+  gfloat* __restrict__ sig = gslot<gfloat>(S, sig_s);
+  gfloat* __restrict__ creg = gslot<gfloat>(S, creg_s);
+  gfloat* __restrict__ halo = gslot<gfloat>(S, halo_s);
   constexpr int KW = 2 * K + 1;
   constexpr int NP = KW * KW;
   extern __shared__ float4 lds4[];
@@ -86,13 +85,13 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const int r0 = tile * R;
   const int rows = min(R, p - r0);
   const size_t plane = (size_t)p * q;
-  const float* Xc = X + (size_t)c * plane;
+  const gfloat* Xc = X + (size_t)c * plane;
 
   for (int e = threadIdx.x; e < (R + H) * q4; e += NT) {
     const int rr = e / q4, c4 = e - rr * q4;
     int gr = (r0 - H + rr) % p;
     if (gr < 0) gr += p;
-    reinterpret_cast<float4*>(Xs)[e] = reinterpret_cast<const float4*>(Xc + (size_t)gr * q)[c4];
+    reinterpret_cast<float4*>(Xs)[e] = ldg4(Xc + (size_t)gr * q + 4 * c4);
     reinterpret_cast<float4*>(Cs)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __syncthreads();
@@ -115,13 +114,13 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   // contiguous stream, each (tau, k) slab of it R*q floats.
   const size_t kstride = (size_t)R * q;             // between patch offsets
   const size_t tstride = (size_t)NP * kstride;      // between shifts
-  float* sig_tile = sig + ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
+  gfloat* sig_tile = sig + ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
 
   for (int n = 0; n < npairs; ++n) {
-    const int2 t = taus[n];
+    const int2 t = tau_at(S, n);
     __syncthreads();  // the previous shift's reads of Ms and updates of Cs are done
     {
-      const float* mun = mu + (size_t)n * plane;
+      const gfloat* mun = mu + (size_t)n * plane;
       const int ms4 = ms >> 2;
       for (int e = threadIdx.x; e < (R + 2 * K) * ms4; e += NT) {
         const int rr = e / ms4, c4 = e - rr * ms4 - 1;  // c4 in [-1, q4]
@@ -129,7 +128,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
         if (gr < 0) gr += p;
         const int gc4 = c4 < 0 ? c4 + q4 : (c4 >= q4 ? c4 - q4 : c4);
         reinterpret_cast<float4*>(Ms)[e] =
-            reinterpret_cast<const float4*>(mun + (size_t)gr * q)[gc4];
+            ldg4(mun + (size_t)gr * q + 4 * gc4);
       }
     }
     __syncthreads();
@@ -149,7 +148,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       A[m] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 
-    float* sig_n = sig_tile + (size_t)n * tstride;
+    gfloat* sig_n = sig_tile + (size_t)n * tstride;
 #pragma unroll
     for (int k1 = -K; k1 <= K; ++k1) {
       // thresholds mu(j + k, tau) for k2 in [-K, K]: columns col-4 .. col+7 of row + k1
@@ -166,7 +165,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       if (!FIRST) {
 #pragma unroll
         for (int k2 = 0; k2 < KW; ++k2) {
-          const float* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
+          const gfloat* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
 #pragma unroll
           for (int m = 0; m < ITEMS; ++m)
             s[k2][m] = ok[m] ? ld_nt(base + (size_t)row[m] * q + col[m])
@@ -175,7 +174,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       }
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
-        float* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
+        gfloat* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
 #pragma unroll
         for (int m = 0; m < ITEMS; ++m) {
           if (!ok[m]) continue;
@@ -211,23 +210,25 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   }
   __syncthreads();
 
-  float* cregc = creg + (size_t)c * plane + (size_t)r0 * q;
+  gfloat* cregc = creg + (size_t)c * plane + (size_t)r0 * q;
 #pragma unroll
   for (int m = 0; m < ITEMS; ++m) {
     if (!ok[m]) continue;
     const float4 acc = *reinterpret_cast<const float4*>(Cs + (row[m] + H) * q + col[m]);
-    *reinterpret_cast<float4*>(cregc + (size_t)row[m] * q + col[m]) =
-        make_float4(2.f * (cp[m].x + acc.x), 2.f * (cp[m].y + acc.y), 2.f * (cp[m].z + acc.z),
-                    2.f * (cp[m].w + acc.w));
+    stg4(cregc + (size_t)row[m] * q + col[m],
+         make_float4(2.f * (cp[m].x + acc.x), 2.f * (cp[m].y + acc.y), 2.f * (cp[m].z + acc.z),
+                     2.f * (cp[m].w + acc.w)));
   }
   if (H > 0) {
-    float* hb = halo + ((size_t)c * ntiles + tile) * H * q;
+    gfloat* hb = halo + ((size_t)c * ntiles + tile) * H * q;
     for (int e = threadIdx.x; e < H * q4; e += NT) {
       const float4 v = reinterpret_cast<const float4*>(Cs)[e];
-      reinterpret_cast<float4*>(hb)[e] = make_float4(2.f * v.x, 2.f * v.y, 2.f * v.z, 2.f * v.w);
+      stg4(hb + 4 * e, make_float4(2.f * v.x, 2.f * v.y, 2.f * v.z, 2.f * v.w));
     }
   }
 }
+
+// ---- sweep kernel end
 
 #ifndef NLPR_SWEEP_THREADS
 #define NLPR_SWEEP_THREADS 256
@@ -302,7 +303,7 @@ size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npa
   return (size_t)L * sh.ntiles * npairs * npatch * sh.rows * q * sizeof(float);
 }
 
-int sweep_blocks(const Plan& P) { return P.sweep.ntiles * P.prm.L; }
+int sweep_blocks(const Plan& P) { return P.sweep.ntiles * P.Lx; }
 
 int sweep_prepare(int K, int items) {
   switch (K) {

@@ -69,7 +69,8 @@ class Params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("Lh", ctypes.c_int32), ("d", ctypes.c_int32), ("blur_radius", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("Sw", ctypes.c_int32), ("iters", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("lam", ctypes.c_double), ("lam1", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("Ls", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("lam1", ctypes.c_double),
                 ("rho", ctypes.c_double), ("h", ctypes.c_double)]
 
 
@@ -107,7 +108,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_stage_time.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     pp = ctypes.POINTER(ctypes.c_void_p)
-    lib.nlpr_batch_create.argtypes = [i32, ctypes.POINTER(Params), pp, pp, ctypes.POINTER(vp)]
+    lib.nlpr_batch_create.argtypes = [i32, ctypes.POINTER(Params), pp, pp, pp, ctypes.POINTER(vp)]
     lib.nlpr_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.nlpr_batch_region.argtypes = [vp, i32, ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.nlpr_batch_solve.argtypes = [vp, pp, pp, pp, vp, sz, vp]
@@ -150,19 +151,28 @@ class Plan:
 
     def __init__(self, p: int, q: int, L: int, Lh: int, d: int, blur: np.ndarray,
                  R: np.ndarray, K: int, Sw: int, iters: int, lam: float, rho: float, h: float,
-                 lam1: float = 1.0, flags: int = 0):
+                 lam1: float = 1.0, flags: int = 0, E: Optional[np.ndarray] = None):
         lib = load()
         blur = np.ascontiguousarray(blur, dtype=np.float32)
         R = np.ascontiguousarray(R, dtype=np.float32).reshape(L, Lh)
         r = blur.shape[0] // 2
         if blur.shape != (2 * r + 1, 2 * r + 1):
             raise ValueError("blur must be (2r+1) x (2r+1)")
-        self.params = Params(p, q, L, Lh, d, r, K, Sw, iters, flags, lam, lam1, rho, h)
+        Ls = 0
+        if E is not None:
+            E = np.ascontiguousarray(E, dtype=np.float32)
+            Ls = E.shape[0]
+            if E.shape != (Ls, L):
+                raise ValueError("E must be Ls x L")
+        self.params = Params(p, q, L, Lh, d, r, K, Sw, iters, flags, Ls, 0, lam, lam1, rho, h)
         self.shape = (L, p, q)
-        self._blur, self._R = blur, R
+        self.xbands = Ls if Ls else L
+        self._blur, self._R, self._E = blur, R, E
         handle = ctypes.c_void_p()
         _check(lib.nlpr_plan_create(ctypes.byref(self.params), blur.ctypes.data_as(ctypes.c_void_p),
-                                    R.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(handle)))
+                                    R.ctypes.data_as(ctypes.c_void_p),
+                                    None if E is None else E.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.byref(handle)))
         self.handle = handle
 
     @classmethod
@@ -206,7 +216,8 @@ class Plan:
     def sigma_logical(self, sig):
         """Sigma' (tile-major, as stored) rearranged to [Npairs][|P|][L][p][q]."""
         inf = self.info()
-        L, p, q = self.shape
+        _, p, q = self.shape
+        L = self.xbands
         t = sig.view(L, inf.ntiles, inf.npairs, inf.npatch, inf.tile_rows, q)
         t = t.permute(2, 3, 0, 1, 4, 5).reshape(inf.npairs, inf.npatch, L, inf.ntiles * inf.tile_rows, q)
         return t[:, :, :, :p, :]
@@ -266,19 +277,27 @@ class Batch:
         self._keep = []
         blurs = (ctypes.c_void_p * n)()
         Rs = (ctypes.c_void_p * n)()
+        Es = (ctypes.c_void_p * n)()
         for i, kw in enumerate(scenes_kwargs):
             blur = np.ascontiguousarray(kw["blur"], dtype=np.float32)
             R = np.ascontiguousarray(kw["R"], dtype=np.float32).reshape(kw["L"], kw["Lh"])
             r = blur.shape[0] // 2
+            E = kw.get("E")
+            Ls = 0
+            if E is not None:
+                E = np.ascontiguousarray(E, dtype=np.float32)
+                Ls = E.shape[0]
+                self._keep.append(E)
+                Es[i] = E.ctypes.data
             self.params[i] = Params(kw["p"], kw["q"], kw["L"], kw["Lh"], kw["d"], r, kw["K"],
-                                    kw["Sw"], kw["iters"], kw.get("flags", 0), kw["lam"],
+                                    kw["Sw"], kw["iters"], kw.get("flags", 0), Ls, 0, kw["lam"],
                                     kw.get("lam1", 1.0), kw["rho"], kw["h"])
             self._keep += [blur, R]
             blurs[i] = blur.ctypes.data
             Rs[i] = R.ctypes.data
             self.shapes.append((kw["L"], kw["p"], kw["q"]))
         handle = ctypes.c_void_p()
-        _check(lib.nlpr_batch_create(n, self.params, blurs, Rs, ctypes.byref(handle)))
+        _check(lib.nlpr_batch_create(n, self.params, blurs, Rs, Es, ctypes.byref(handle)))
         self.handle = handle
 
     @classmethod

@@ -42,10 +42,10 @@ def test_status_strings():
 
 
 def test_params_struct_layout_matches_header():
-    # 10 x 32-bit fields, then 4 doubles at offset 40
-    assert ctypes.sizeof(nlpr.Params) == 72
-    assert nlpr.Params.lam.offset == 40
-    assert nlpr.Params.h.offset == 64
+    # 12 x 32-bit fields, then 4 doubles at offset 48
+    assert ctypes.sizeof(nlpr.Params) == 80
+    assert nlpr.Params.lam.offset == 48
+    assert nlpr.Params.h.offset == 72
 
 
 def _create(**over):
@@ -54,7 +54,8 @@ def _create(**over):
     kw.update(over)
     r = kw["blur_radius"]
     prm = nlpr.Params(kw["p"], kw["q"], kw["L"], kw["Lh"], kw["d"], r, kw["K"], kw["Sw"],
-                      kw["iters"], kw["flags"], kw["lam"], kw["lam1"], kw["rho"], kw["h"])
+                      kw["iters"], kw["flags"], kw.get("Ls", 0), kw.get("reserved", 0), kw["lam"],
+                      kw["lam1"], kw["rho"], kw["h"])
     blur = np.ones((2 * r + 1, 2 * r + 1), np.float32)
     R = np.ones((kw["L"], kw["Lh"]), np.float32)
     h = ctypes.c_void_p()
@@ -82,6 +83,9 @@ def _create(**over):
     (dict(d=0), nlpr.ERR_INVALID_ARG),
     (dict(rho=float("nan")), nlpr.ERR_INVALID_ARG),
     (dict(p=64, q=4096, K=4, Sw=8, d=1), nlpr.ERR_UNSUPPORTED_SHAPE),   # sweep tile exceeds LDS
+    (dict(Ls=9), nlpr.ERR_UNSUPPORTED_SHAPE),                         # more basis rows than bands
+    (dict(Ls=2), nlpr.ERR_INVALID_ARG),                               # Ls without a basis
+    (dict(reserved=1), nlpr.ERR_INVALID_ARG),
 ])
 def test_invalid_parameters_are_rejected_on_the_host(over, code):
     rc, h, msg = _create(**over)
@@ -100,9 +104,9 @@ def test_null_arguments_are_rejected():
     assert lib.nlpr_plan_destroy(None) == nlpr.OK
 
 
-def test_subspace_basis_is_reported_unsupported():
+def test_basis_without_Ls_is_rejected():
     lib = nlpr.load()
-    prm = nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 3, 0, 1e-3, 1.0, 1e-2, 0.1)
+    prm = nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 3, 0, 0, 0, 1e-3, 1.0, 1e-2, 0.1)
     blur = np.ones((3, 3), np.float32)
     R = np.ones((8, 1), np.float32)
     E = np.ones((4, 8), np.float32)
@@ -110,18 +114,18 @@ def test_subspace_basis_is_reported_unsupported():
     rc = lib.nlpr_plan_create(ctypes.byref(prm), blur.ctypes.data_as(ctypes.c_void_p),
                               R.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p),
                               ctypes.byref(h))
-    assert rc == nlpr.ERR_UNSUPPORTED_SHAPE
+    assert rc == nlpr.ERR_INVALID_ARG
 
 
 def test_batch_rejects_scenes_with_different_iteration_counts():
     lib = nlpr.load()
-    prm = (nlpr.Params * 2)(nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 3, 0, 1e-3, 1.0, 1e-2, 0.1),
-                            nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 4, 0, 1e-3, 1.0, 1e-2, 0.1))
+    prm = (nlpr.Params * 2)(nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 3, 0, 0, 0, 1e-3, 1.0, 1e-2, 0.1),
+                            nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 4, 0, 0, 0, 1e-3, 1.0, 1e-2, 0.1))
     blur = np.ones((3, 3), np.float32)
     R = np.ones((8, 1), np.float32)
     ptrs = (ctypes.c_void_p * 2)(blur.ctypes.data, blur.ctypes.data)
     rs = (ctypes.c_void_p * 2)(R.ctypes.data, R.ctypes.data)
     h = ctypes.c_void_p()
-    assert lib.nlpr_batch_create(2, prm, ptrs, rs, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
-    assert lib.nlpr_batch_create(0, prm, ptrs, rs, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
+    assert lib.nlpr_batch_create(2, prm, ptrs, rs, None, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
+    assert lib.nlpr_batch_create(0, prm, ptrs, rs, None, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
     assert lib.nlpr_batch_destroy(None) == nlpr.OK

@@ -67,11 +67,12 @@ def rand_blur(r, rng=None):
 
 
 def tiny_problem(p=6, q=8, L=3, Lh=2, d=2, r=1, K=1, S=1, lam=0.05, rho=0.7, lam1=0.8,
-                 h=0.9, unweighted=False, local=False, seed=0):
+                 h=0.9, unweighted=False, local=False, seed=0, Ls=None):
     rng = np.random.default_rng(seed)
+    E = None if Ls is None else rng.standard_normal((Ls, L))    # general (not orthonormal) basis
     pr = o.Problem(p=p, q=q, L=L, d=d, b=rand_blur(r, rng), R=rng.uniform(0.05, 1.0, size=(L, Lh)),
                    K=K, S=S, lam=lam, rho=rho, h=h, lam1=lam1, unweighted=unweighted,
-                   local=local)
+                   local=local, E=E)
     Yl = rng.uniform(0, 1, size=(L, p // d, q // d))
     Yh = rng.uniform(0, 1, size=(Lh, p, q))
     return pr, Yl, Yh
@@ -258,25 +259,29 @@ def test_soft_threshold_is_prox_of_weighted_l1():
     np.testing.assert_allclose(sig, -np.clip(V, -mu, mu), atol=1e-15)
 
 
-def test_p1_update_solves_its_normal_equation():
-    # eq. (P1grad) with E = I: S^T S P1 + rho P1 = S^T Y_l + rho (B X - Lambda1)
-    pr, Yl, Yh = tiny_problem()
-    BX = RNG.standard_normal((pr.L, pr.p, pr.q))
-    Lam1 = RNG.standard_normal((pr.L, pr.p, pr.q))
+@pytest.mark.parametrize("Ls", [None, 2])
+def test_p1_update_solves_its_normal_equation(Ls):
+    # eq. (P1grad): S^T S P1 E E^T + rho P1 = S^T Y_l E^T + rho (B X - Lambda1)
+    pr, Yl, Yh = tiny_problem(Ls=Ls)
+    E = np.eye(pr.L) if Ls is None else pr.E
+    BX = RNG.standard_normal((pr.Ls, pr.p, pr.q))
+    Lam1 = RNG.standard_normal((pr.Ls, pr.p, pr.q))
     P1 = o.p1_update(BX, Lam1, Yl, pr)
     S = dense_decimate(pr.p, pr.q, pr.d)
-    lhs = (S.T @ S) @ vec(P1) + pr.rho * vec(P1)
-    rhs = S.T @ vec(Yl) + pr.rho * (vec(BX) - vec(Lam1))
+    lhs = (S.T @ S) @ vec(P1) @ E @ E.T + pr.rho * vec(P1)
+    rhs = S.T @ vec(Yl) @ E.T + pr.rho * (vec(BX) - vec(Lam1))
     np.testing.assert_allclose(lhs, rhs, atol=1e-12)
 
 
-def test_p2_update_zeroes_its_gradient():
-    # gradient of lambda1/2 ||Y_h - P2 R||^2 + rho/2 ||P2 + Lambda2 - X||^2 vanishes
-    pr, Yl, Yh = tiny_problem()
-    X = RNG.standard_normal((pr.L, pr.p, pr.q))
-    Lam2 = RNG.standard_normal((pr.L, pr.p, pr.q))
+@pytest.mark.parametrize("Ls", [None, 2])
+def test_p2_update_zeroes_its_gradient(Ls):
+    # gradient of lambda1/2 ||Y_h - P2 E R||^2 + rho/2 ||P2 + Lambda2 - X||^2 vanishes
+    pr, Yl, Yh = tiny_problem(Ls=Ls)
+    ER = pr.R if Ls is None else pr.E @ pr.R
+    X = RNG.standard_normal((pr.Ls, pr.p, pr.q))
+    Lam2 = RNG.standard_normal((pr.Ls, pr.p, pr.q))
     P2 = vec(o.p2_update(X, Lam2, Yh, pr))
-    g = -pr.lam1 * (vec(Yh) - P2 @ pr.R) @ pr.R.T + pr.rho * (P2 + vec(Lam2) - vec(X))
+    g = -pr.lam1 * (vec(Yh) - P2 @ ER) @ ER.T + pr.rho * (P2 + vec(Lam2) - vec(X))
     np.testing.assert_allclose(g, 0.0, atol=1e-12)
 
 
@@ -289,6 +294,30 @@ def _full_step(pr, Yl, Yh, iters=3):
     for _ in range(iters):
         X, st = o.admm_step(st, Yl, Yh, pr, den, mu, F)
     return X, st, mu, den, F
+
+
+def test_subspace_admm_reaches_the_optimum_of_an_independent_solver():
+    """The low-rank form Z = X E (Sec. "Variational models"): the ADMM optimum over X equals
+    that of the primal-dual solver on the same dense problem."""
+    pr, Yl, Yh = tiny_problem(p=4, q=6, L=3, Lh=1, d=2, K=1, S=1, lam=0.02, h=0.7, Ls=2,
+                              rho=0.3)
+    H, bb, c0, G, w = _dense_problem(pr, Yl, Yh)
+    x_pd = _pdhg(H, bb, G, w, 10000)
+    f_pd = _dense_objective(x_pd, H, bb, c0, G, w)
+    res = o.solve(Yl, Yh, pr, 4000)
+    f_admm = _dense_objective(vec(res.X).T.ravel(), H, bb, c0, G, w)
+    assert o.objective(res.X, Yl, Yh, pr) == pytest.approx(f_admm, rel=1e-12)
+    assert f_admm == pytest.approx(f_pd, rel=1e-9)
+    # Z = X E
+    np.testing.assert_allclose(vec(res.Z), vec(res.X) @ pr.E, atol=1e-14)
+
+
+def test_subspace_start_is_the_least_squares_coefficient_image():
+    pr, Yl, Yh = tiny_problem(Ls=2)
+    X0, _ = o.initial_state(Yl, pr)
+    up = np.repeat(np.repeat(Yl, pr.d, axis=-2), pr.d, axis=-1)
+    coef, *_ = np.linalg.lstsq(pr.E.T, vec(up).T, rcond=None)     # min ||X E - up||
+    np.testing.assert_allclose(vec(X0), coef.T, atol=1e-12)
 
 
 def test_admm_step_subproblem_optimality():
@@ -351,12 +380,16 @@ def test_two_iteration_band_form_equals_full_iteration():
 
 
 def _dense_problem(pr, Yl, Yh):
-    """H, b, c, G, w of f(x) = 1/2 x^T H x - b^T x + c and phi = sum_j w_j |(G x)_j|."""
+    """H, b, c, G, w of f(x) = 1/2 x^T H x - b^T x + c and phi = sum_j w_j |(G x)_j|, for
+    x the band-major vector of X (Z = X E)."""
     n, L = pr.p * pr.q, pr.L
+    E = np.eye(L) if pr.E is None else pr.E
+    Ls = E.shape[0]
     Mb = dense_blur(pr.p, pr.q, pr.b)
     S = dense_decimate(pr.p, pr.q, pr.d)
-    A1 = np.kron(np.eye(L), S @ Mb)                # acts on x = vec of the n x L matrix, band-major
-    A2 = np.kron(pr.R.T, np.eye(n))                # (X R) flattened band-major
+    A1 = np.kron(E.T, S @ Mb)                      # S B (X E), band-major
+    A2 = np.kron((E @ pr.R).T, np.eye(n))          # (X E R), band-major
+    L = Ls
     y1 = vec(Yl).T.ravel()
     y2 = vec(Yh).T.ravel()
     H = A1.T @ A1 + pr.lam1 * A2.T @ A2
