@@ -281,16 +281,23 @@ def regulariser(X: np.ndarray, omega: np.ndarray, window: Sequence[Offset],
     return tot
 
 
-def objective(X: np.ndarray, Yl: np.ndarray, Yh: np.ndarray, pr: Problem,
-              omega: Optional[np.ndarray] = None) -> float:
-    """ell(X) + lambda2 phi(X), eq. (mainoptim): the data terms act on Z = X E."""
+def objective_terms(X: np.ndarray, Yl: np.ndarray, Yh: np.ndarray, pr: Problem,
+                    omega: Optional[np.ndarray] = None) -> Tuple[float, float, float]:
+    """The three terms of eq. (mainoptim): 1/2 ||Y_l - S B Z||^2, lambda1/2 ||Y_h - Z R||^2
+    and lambda2 phi(X), with Z = X E."""
     if omega is None:
         omega = weights(Yh, pr.window, pr.K, pr.h, pr.unweighted)
     Z = compose(X, pr)
     r1 = Yl - decimate(blur(Z, pr.b), pr.d)
     r2 = Yh - spectral(Z, pr.R)
-    return (0.5 * float(np.sum(r1 * r1)) + 0.5 * pr.lam1 * float(np.sum(r2 * r2))
-            + pr.lam * regulariser(X, omega, pr.window, pr.K))
+    return (0.5 * float(np.sum(r1 * r1)), 0.5 * pr.lam1 * float(np.sum(r2 * r2)),
+            pr.lam * regulariser(X, omega, pr.window, pr.K))
+
+
+def objective(X: np.ndarray, Yl: np.ndarray, Yh: np.ndarray, pr: Problem,
+              omega: Optional[np.ndarray] = None) -> float:
+    """ell(X) + lambda2 phi(X), eq. (mainoptim): the data terms act on Z = X E."""
+    return float(sum(objective_terms(X, Yl, Yh, pr, omega)))
 
 
 # ------------------------------------------------------------------------- ADMM
@@ -373,6 +380,35 @@ def fixed_point_residual(a: State, b: State, rho: float) -> float:
     return rho * s
 
 
+def primal_residuals(X: np.ndarray, st: State, pr: Problem) -> Tuple[float, float]:
+    """||B X - P1|| and ||X - P2||: how far the iterate is from the constraints P1 = B X and
+    P2 = X of the split problem eq. (fusionoptim), after the step that produced X and st."""
+    r1 = blur(X, pr.b) - st.P1
+    r2 = X - st.P2
+    return float(np.sqrt(np.sum(r1 * r1))), float(np.sqrt(np.sum(r2 * r2)))
+
+
+@dataclasses.dataclass
+class Monitor:
+    """What is recorded after an iteration: the objective of eq. (mainoptim) and its terms at
+    X^{(t)} (the quantity plotted against t in Fig. "objective_conv"), and the primal
+    residuals of the constraints of eq. (fusionoptim)."""
+    iteration: int
+    objective: float
+    data_l: float
+    data_h: float
+    reg: float
+    r1: float
+    r2: float
+
+
+def monitor(t: int, X: np.ndarray, st: State, Yl: np.ndarray, Yh: np.ndarray, pr: Problem,
+            omega: Optional[np.ndarray] = None) -> Monitor:
+    a, b, c = objective_terms(X, Yl, Yh, pr, omega)
+    r1, r2 = primal_residuals(X, st, pr)
+    return Monitor(iteration=t, objective=a + b + c, data_l=a, data_h=b, reg=c, r1=r1, r2=r2)
+
+
 @dataclasses.dataclass
 class Result:
     X: np.ndarray            # the iterate X^{(T)} (L_s bands)
@@ -380,11 +416,14 @@ class Result:
     objective: List[float]
     residual: List[float]
     Z: Optional[np.ndarray] = None   # Z = X E (L bands)
+    monitor: Optional[List[Monitor]] = None
 
 
 def solve(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, init: str = "upsample",
-          track: bool = False, state: Optional[Tuple[np.ndarray, State]] = None) -> Result:
-    """Run ``iters`` ADMM iterations; X^{(iters)} and Z = X E."""
+          track: bool = False, state: Optional[Tuple[np.ndarray, State]] = None,
+          monitor_every: int = 0) -> Result:
+    """Run ``iters`` ADMM iterations; X^{(iters)} and Z = X E.  With monitor_every = N > 0,
+    ``monitor`` holds a record after iterations N, 2N, ... and after the last one."""
     Yl = Yl.astype(np.float64)
     Yh = Yh.astype(np.float64)
     den = denominator(pr.p, pr.q, pr.b, pr.window, pr.K)
@@ -394,13 +433,17 @@ def solve(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, init: str = "
     X, st = state if state is not None else initial_state(Yl, pr, init)
     objs: List[float] = []
     res: List[float] = []
-    for _ in range(iters):
+    mons: List[Monitor] = []
+    for t in range(1, iters + 1):
         X, nst = admm_step(st, Yl, Yh, pr, den, mu, F)
         if track:
             objs.append(objective(X, Yl, Yh, pr, omega))
             res.append(fixed_point_residual(nst, st, pr.rho))
+        if monitor_every > 0 and (t % monitor_every == 0 or t == iters):
+            mons.append(monitor(t, X, nst, Yl, Yh, pr, omega))
         st = nst
-    return Result(X=X, state=st, objective=objs, residual=res, Z=compose(X, pr))
+    return Result(X=X, state=st, objective=objs, residual=res, Z=compose(X, pr),
+                  monitor=mons if monitor_every > 0 else None)
 
 
 # --------------------------------------------------- first two iterations, few bands

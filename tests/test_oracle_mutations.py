@@ -25,6 +25,8 @@ FAST_PINS = [
     pins.test_two_iteration_band_form_equals_full_iteration,
     lambda: pins.test_x_update_equals_dense_solve(6, 8, 1, 1),
     lambda: pins.test_lambda2_zero_with_square_R_gives_the_least_squares_solution(0, 0.5, 500),
+    lambda: pins.test_objective_terms_equal_dense_operator_forms(None),
+    lambda: pins.test_primal_residuals_are_the_lambda_steps(None),
 ]
 
 _orig = {name: getattr(o, name) for name in dir(o) if callable(getattr(o, name))}
@@ -98,6 +100,21 @@ def _admm_dual_sign(st, Yl, Yh, pr, den, mu, F):      # dual update with the wro
 
 
 MUTATIONS["admm_step"] = _admm_dual_sign
+
+
+def _mut_objective_terms(X, Yl, Yh, pr, omega=None):   # lambda1 dropped from the Y_h term
+    a, b, c = _orig["objective_terms"](X, Yl, Yh, pr, omega)
+    return a, b / pr.lam1, c
+
+
+def _mut_primal_residuals(X, st, pr):                  # first residual against X, not B X
+    r1 = X - st.P1
+    r2 = X - st.P2
+    return float(np.sqrt(np.sum(r1 * r1))), float(np.sqrt(np.sum(r2 * r2)))
+
+
+MUTATIONS["objective_terms"] = _mut_objective_terms
+MUTATIONS["primal_residuals"] = _mut_primal_residuals
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))

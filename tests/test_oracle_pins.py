@@ -462,3 +462,72 @@ def test_objective_stabilises():
     drop = obj[0] - obj[-1]
     assert drop > 0
     assert np.ptp(obj[200:]) <= 0.05 * drop
+
+
+# ------------------------------------------------------------------ monitor quantities
+@pytest.mark.parametrize("Ls", [None, 2])
+def test_objective_terms_equal_dense_operator_forms(Ls):
+    """Each term of eq. (mainoptim), from explicit matrices of S, B, R, E and D_{tau k}
+    (the three terms separately, so a term moved or dropped shows)."""
+    pr, Yl, Yh = tiny_problem(p=6, q=4, L=3, Lh=2, d=2, K=1, S=1, lam=0.07, lam1=0.6, Ls=Ls)
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((pr.Ls, pr.p, pr.q))
+    n = pr.p * pr.q
+    E = np.eye(pr.L) if Ls is None else pr.E
+    A1 = np.kron(E.T, dense_decimate(pr.p, pr.q, pr.d) @ dense_blur(pr.p, pr.q, pr.b))
+    A2 = np.kron((E @ pr.R).T, np.eye(n))
+    x = vec(X).T.ravel()
+    y1 = vec(Yl).T.ravel()
+    y2 = vec(Yh).T.ravel()
+    *_, G, w = _dense_problem(pr, Yl, Yh)
+    want = (0.5 * np.sum((y1 - A1 @ x) ** 2), 0.5 * pr.lam1 * np.sum((y2 - A2 @ x) ** 2),
+            float(np.sum(w * np.abs(G @ x))))
+    got = o.objective_terms(X, Yl, Yh, pr)
+    for g, v in zip(got, want):
+        assert g == pytest.approx(v, rel=1e-12)
+
+
+@pytest.mark.parametrize("Ls", [None, 2])
+def test_primal_residuals_are_the_lambda_steps(Ls):
+    """eqs. (dualvar1_main), (dualvar2_main): the step of Lambda1 is B X - P1 and that of
+    Lambda2 is X - P2, so the residual norms equal the norms of the dual steps; B X is
+    also formed with the explicit blur matrix."""
+    pr, Yl, Yh = tiny_problem(p=6, q=8, L=3, Lh=2, Ls=Ls, seed=3)
+    X0, st = o.initial_state(Yl, pr)
+    den = o.denominator(pr.p, pr.q, pr.b, pr.window, pr.K)
+    om = o.weights(Yh, pr.window, pr.K, pr.h)
+    mu = pr.lam * om / pr.rho
+    F = o.p2_matrix(pr)
+    for _ in range(2):
+        X, nst = o.admm_step(st, Yl, Yh, pr, den, mu, F)
+        r1, r2 = o.primal_residuals(X, nst, pr)
+        assert r1 == pytest.approx(np.linalg.norm(nst.Lam1 - st.Lam1), rel=1e-12)
+        assert r2 == pytest.approx(np.linalg.norm(nst.Lam2 - st.Lam2), rel=1e-12)
+        Mb = dense_blur(pr.p, pr.q, pr.b)
+        BX = (Mb @ vec(X)).T.reshape(X.shape)
+        assert r1 == pytest.approx(np.linalg.norm(BX - nst.P1), rel=1e-12)
+        st = nst
+
+
+def test_monitor_points_and_their_values():
+    # records after iterations N, 2N, ... and the last; each equals the per-iteration
+    # objective of the tracked run and the residuals of that iteration's state
+    pr, Yl, Yh = tiny_problem(p=6, q=8, L=2, Lh=1, seed=5)
+    res = o.solve(Yl, Yh, pr, 7, track=True, monitor_every=3)
+    assert [m.iteration for m in res.monitor] == [3, 6, 7]
+    for m in res.monitor:
+        assert m.objective == pytest.approx(res.objective[m.iteration - 1], rel=1e-14)
+        assert m.objective == pytest.approx(m.data_l + m.data_h + m.reg, rel=1e-14)
+    last = res.monitor[-1]
+    assert (last.r1, last.r2) == pytest.approx(o.primal_residuals(res.X, res.state, pr),
+                                               rel=1e-14)
+    assert o.solve(Yl, Yh, pr, 7).monitor is None
+
+
+def test_primal_residuals_vanish_at_the_optimum():
+    # Theorem 1: the constraint violations of eq. (fusionoptim) go to zero
+    pr, Yl, Yh = tiny_problem(p=4, q=6, L=2, Lh=1, d=2, K=1, S=1, lam=0.02, h=0.7, rho=0.3)
+    early = o.solve(Yl, Yh, pr, 20, monitor_every=20).monitor[-1]
+    late = o.solve(Yl, Yh, pr, 3000, monitor_every=3000).monitor[-1]
+    assert late.r1 < 1e-9 and late.r2 < 1e-9
+    assert early.r1 > 1e3 * late.r1 and early.r2 > 1e3 * late.r2
