@@ -209,6 +209,9 @@ def main():
     ap.add_argument("--subspace", type=int, default=0,
                     help="Ls > 0: solve for Z = X E with E the Ls leading right singular "
                          "vectors of Y_l")
+    ap.add_argument("--monitor", type=int, default=0,
+                    help="record the objective and residuals every N iterations (0 = off; "
+                         "the default run keeps it off)")
     ap.add_argument("--calib-gib", type=float, default=4.0,
                     help="size of the reference copy (0 = skip)")
     args = ap.parse_args()
@@ -243,7 +246,7 @@ def main():
         M = sc.Yl.reshape(spec.L, -1).T.astype(np.float64)
         E = np.ascontiguousarray(np.linalg.svd(M, full_matrices=False)[2][:args.subspace],
                                  dtype=np.float32)
-    plan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING, E=E)
+    plan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING, E=E, monitor_every=args.monitor)
     npairs = len(plan.half_window())
     ws = plan.alloc_workspace()
     Z = torch.empty((spec.L, spec.p, spec.q), dtype=torch.float32, device=dev)
@@ -299,6 +302,8 @@ def main():
         if loop_ms else None,
         "stages": stages, "finite": finite, "hbm_reference": ref,
     }
+    if args.monitor:
+        out["monitor"] = [dict(zip(nlpr.MON_FIELDS, map(float, r))) for r in plan.monitor()]
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a sample")
         out["cpu_baseline"] = cpu_baseline()

@@ -91,7 +91,9 @@ enum {
  *   Ls         : 0 = no subspace (Z is the ADMM variable X).  1 <= Ls <= min(L, 32): Z = X E
  *                with the fixed basis E (Ls x L) passed to nlpr_plan_create; X has Ls bands
  *                and the dual state shrinks by L / Ls (Sec. "Variational models").
- *   reserved   : must be 0.
+ *   monitor_every : 0 = no monitor.  N > 0: after iterations N, 2N, ... and after the last
+ *                iteration of each solve, record the objective of eq. (mainoptim) with its
+ *                terms and the primal residuals of eq. (fusionoptim) (read with nlpr_monitor).
  *   lambda     : regulariser weight lambda_2 >= 0.  The soft-threshold of eq. (Qj_main) is
  *                lambda * omega / rho.
  *   lambda1    : weight of the Y_h term, > 0.
@@ -107,7 +109,7 @@ typedef struct nlpr_params {
   int32_t iters;
   uint32_t flags;
   int32_t Ls;
-  int32_t reserved;
+  int32_t monitor_every;
   double lambda;
   double lambda1;
   double rho;
@@ -234,7 +236,8 @@ enum {
   NLPR_STAGE_SWEEP_FIRST = 7,
   NLPR_STAGE_ASSEMBLE = 8,
   NLPR_STAGE_INIT = 9,
-  NLPR_STAGE_COUNT = 10
+  NLPR_STAGE_MONITOR = 10,      /* timing only (no per-stage entry point)                         */
+  NLPR_STAGE_COUNT = 11
 };
 int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbufs, void* stream);
 
@@ -247,14 +250,42 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
 int nlpr_stage_time(nlpr_plan* plan, int stage, double* ms_total, int64_t* launches, int reset);
 
 /*
+ * Monitor trace of the last solve (plans created with monitor_every > 0, else
+ * NLPR_ERR_NOT_ENABLED).  One record of NLPR_MON_FIELDS doubles per monitored iteration
+ * t (t = N, 2N, ... and the last iteration of the solve, counted from 1 in each call):
+ *   [NLPR_MON_ITER]      t
+ *   [NLPR_MON_OBJECTIVE] f(X^(t)) = data_l + data_h + reg, eq. (mainoptim) (the quantity the
+ *                        paper plots against t in its convergence figure)
+ *   [NLPR_MON_DATA_L]    1/2 ||Y_l - S B X^(t) E||^2
+ *   [NLPR_MON_DATA_H]    lambda1/2 ||Y_h - X^(t) E R||^2
+ *   [NLPR_MON_REG]       lambda2 sum_{i, c} sum_{tau in W} sum_{k in P} omega_{i tau}
+ *                        |D_{tau k} X^(t)(i, c)|, eq. (regfilt1), evaluated as
+ *                        2 rho sum_{tau in W+} sum_j (sum_{k in P} mu_{j+k, tau})
+ *                        sum_c |X(j, c) - X(j - tau, c)| (mu = lambda2 omega / rho)
+ *   [NLPR_MON_R1]        ||B X^(t) - P1^(t)||,   [NLPR_MON_R2] ||X^(t) - P2^(t)||:
+ *                        the primal residuals of the constraints of eq. (fusionoptim)
+ *   [7]                  0
+ * Terms are formed in FP32 from the iterate and summed in FP64 in a fixed order (the
+ * trace is bit-for-bit repeatable).  Monitoring does not change the iterates.
+ *   trace : host, receives min(cap, n) records (cap * NLPR_MON_FIELDS doubles);
+ *   n     : receives the number of records of the last solve (0 before the first).
+ * Waits for the last solve to complete.
+ */
+enum {
+  NLPR_MON_ITER = 0, NLPR_MON_OBJECTIVE = 1, NLPR_MON_DATA_L = 2, NLPR_MON_DATA_H = 3,
+  NLPR_MON_REG = 4, NLPR_MON_R1 = 5, NLPR_MON_R2 = 6, NLPR_MON_FIELDS = 8
+};
+int nlpr_monitor(const nlpr_plan* plan, double* trace, int32_t cap, int32_t* n);
+
+/*
  * Batches: many independent scenes solved together (the multi-scene workload).  Every stage
  * of the iteration is one kernel launch over all scenes: a table of (scene, block) work
  * items maps each workgroup to a scene, whose sizes, tables and buffers a device
  * descriptor holds.  With NLPR_GRAPH the whole batched solve is one HIP graph.
  *   n        : number of scenes >= 1.
  *   params   : host array of n parameter sets.  Scenes may differ in every size and
- *              parameter, but must share iters and the flags NLPR_INIT_ZERO,
- *              NLPR_STATE_IN, NLPR_CHECK_FINITE, NLPR_TIMING and NLPR_GRAPH
+ *              parameter, but must share iters, monitor_every and the flags
+ *              NLPR_INIT_ZERO, NLPR_STATE_IN, NLPR_CHECK_FINITE, NLPR_TIMING and NLPR_GRAPH
  *              (else NLPR_ERR_INVALID_ARG).
  *   blur_host, R_host, E_host : host arrays of n host pointers, as for nlpr_plan_create
  *              (E_host may be NULL when no scene has a basis).
@@ -273,6 +304,9 @@ int nlpr_batch_solve(nlpr_batch* batch, const float* const* Yl, const float* con
                      float* const* Z, void* ws, size_t ws_bytes, void* stream);
 int nlpr_batch_stage_time(nlpr_batch* batch, int stage, double* ms_total, int64_t* launches,
                           int reset);
+/* The monitor trace of one scene of the last batched solve, as nlpr_monitor. */
+int nlpr_batch_monitor(const nlpr_batch* batch, int32_t scene, double* trace, int32_t cap,
+                       int32_t* n);
 int nlpr_batch_destroy(nlpr_batch* batch);
 
 #ifdef __cplusplus

@@ -68,7 +68,7 @@ struct DeviceGuard {
 
 int validate(const nlpr_params& q) {
   auto bad = [](const std::string& m) { return fail(NLPR_ERR_UNSUPPORTED_SHAPE, m); };
-  if (q.reserved != 0) return fail(NLPR_ERR_INVALID_ARG, "reserved must be 0");
+  if (q.monitor_every < 0) return fail(NLPR_ERR_INVALID_ARG, "monitor_every must be >= 0");
   if (q.Ls < 0 || q.Ls > std::min(q.L, kMaxLs)) return bad("Ls must lie in [0, min(L, 32)]");
   LineFFT tmp{};
   if (q.p < 8 || q.q < 8 || q.p > kMaxFFTLen || q.q > kMaxFFTLen)
@@ -106,6 +106,7 @@ void scene_free(Plan* P) {
   hipFree(P->d_Ep);
   hipFree(P->d_M);
   hipFree(P->d_Rt);
+  hipFree(P->d_mon);
   hipFree(P->d_taus);
   hipFree(P->d_invden);
   hipFree(P->d_tw_p);
@@ -178,6 +179,14 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
         hipMalloc(&P->d_Rt, (size_t)Lx * Lh * sizeof(float)) != hipSuccess ||
         hipMemcpy(P->d_E, E_host, (size_t)Lx * L * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
       set_error("allocation or upload of the subspace tables failed");
+      return cleanup(NLPR_ERR_HIP);
+    }
+  }
+  if (prm.monitor_every > 0) {
+    P->mon_points = monitor_points(prm.iters, prm.monitor_every);
+    const size_t nd = 4 * (size_t)pixel_blocks(*P) + monreg_blocks(*P) + 8 * (size_t)P->mon_points;
+    if (hipMalloc(&P->d_mon, std::max<size_t>(nd, 1) * sizeof(double)) != hipSuccess) {
+      set_error("allocation of the monitor buffer failed");
       return cleanup(NLPR_ERR_HIP);
     }
   }
@@ -254,6 +263,11 @@ SceneDesc static_desc(const Plan& P) {
   d.blur = P.d_blur;
   d.R = P.d_E ? P.d_Rt : P.d_R;
   d.G = P.d_G;
+  d.mon = P.d_mon;
+  d.mon_npix = P.d_mon ? pixel_blocks(P) : 0;
+  d.mon_nreg = P.d_mon ? monreg_blocks(P) : 0;
+  d.rho_d = q.rho;
+  d.lam1_d = q.lambda1;
   return d;
 }
 
@@ -268,6 +282,7 @@ void batch_release(Batch& B) {
   if (B.h_desc) hipHostFree(B.h_desc);
   hipFree(B.d_flag);
   if (B.upload_ev) hipEventDestroy(B.upload_ev);
+  if (B.done_ev) hipEventDestroy(B.done_ev);
   if (B.graph) hipGraphExecDestroy(B.graph);
   for (hipEvent_t e : B.ev_pool) hipEventDestroy(e);
   B.ev_pool.clear();
@@ -277,6 +292,7 @@ void batch_release(Batch& B) {
   B.h_desc = nullptr;
   B.d_flag = nullptr;
   B.upload_ev = nullptr;
+  B.done_ev = nullptr;
   B.graph = nullptr;
 }
 
@@ -352,6 +368,20 @@ int batch_build(Batch& B) {
     }
     if ((rc = add_group(B, kind, it, 256, 0, 0, 0))) return rc;
   }
+  if (B.monitor_every > 0) {
+    std::vector<int2> it, sc;
+    size_t l = 0;
+    for (int s = 0; s < n; ++s) {
+      const Plan& P = *B.scenes[s];
+      sc.push_back(make_int2(s, 0));
+      if (P.npairs == 0) continue;
+      const int c = monreg_blocks(P);
+      for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+      l = std::max(l, monreg_lds(P));
+    }
+    if ((rc = add_group(B, KD_MONREG, it, 256, l, 0, 0))) return rc;
+    if ((rc = add_group(B, KD_SCENE, sc, 256, 0, 0, 0))) return rc;
+  }
   if ((rc = simple(KD_ROWS, rows_blocks, rows_lds, rows_block))) return rc;
   if ((rc = simple(KD_COLS, cols_blocks, cols_lds, cols_block))) return rc;
   // the sweep: one launch per (patch radius, items per thread)
@@ -374,6 +404,7 @@ int batch_build(Batch& B) {
   NLPR_HIP_TRY(hipHostMalloc(&B.h_desc, n * sizeof(SceneDesc)));
   NLPR_HIP_TRY(hipMalloc(&B.d_flag, 256));
   NLPR_HIP_TRY(hipEventCreateWithFlags(&B.upload_ev, hipEventDisableTiming));
+  NLPR_HIP_TRY(hipEventCreateWithFlags(&B.done_ev, hipEventDisableTiming));
   B.uploaded.resize(n);
   B.desc_valid = false;
   return NLPR_OK;
@@ -418,7 +449,7 @@ struct StageTimer {
 
 int ensure_events(Batch& B) {
   if (!B.timing) return NLPR_OK;
-  const size_t need = 2 * (size_t)(6 * std::max(B.iters, 1) + 16);
+  const size_t need = 2 * (size_t)(7 * std::max(B.iters, 1) + 16);
   while (B.ev_pool.size() < need + B.ev_used) {
     hipEvent_t e;
     NLPR_HIP_TRY(hipEventCreate(&e));
@@ -431,6 +462,7 @@ int ensure_events(Batch& B) {
 // P/Lambda update, the sweep and the right-hand-side assembly.
 int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
   int rc;
+  int point = 0;
   bool reg = false, sub = false;
   for (const Plan* P : B.scenes) {
     reg = reg || P->npairs > 0;
@@ -464,6 +496,10 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
       StageTimer tm(B, s, NLPR_STAGE_PUPDATE);
       if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
       if (sub && (rc = launch_p1_subspace(B, B_BX, B_YLE, B_L1, B_W1, s))) return rc;
+    }
+    if (B.monitor_every > 0 && ((t + 1) % B.monitor_every == 0 || t + 1 == B.iters)) {
+      StageTimer tm(B, s, NLPR_STAGE_MONITOR);
+      if ((rc = launch_monitor(B, point++, t + 1, s))) return rc;
     }
     if (reg) {
       const bool first = (t == 0 && !resume);
@@ -553,6 +589,8 @@ int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float*
   } else {
     if ((rc = enqueue_solve(B, resume, s))) return rc;
   }
+  NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
+  B.mon_last = monitor_points(B.iters, B.monitor_every);
   if (B.flags & NLPR_CHECK_FINITE) {
     if ((rc = launch_finite(B, B_Z, B.d_flag, s))) return rc;
     int hflag = 0;
@@ -594,6 +632,23 @@ int region_of(const Plan& P, int region, size_t* offset, size_t* bytes) {
   return NLPR_OK;
 }
 
+int batch_monitor(const Batch& B, int scene, double* trace, int cap, int* n) {
+  if (!n || (cap > 0 && !trace)) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  if (cap < 0) return fail(NLPR_ERR_INVALID_ARG, "cap must be >= 0");
+  if (scene < 0 || scene >= (int)B.scenes.size()) return fail(NLPR_ERR_INVALID_ARG, "scene out of range");
+  if (B.monitor_every <= 0) return fail(NLPR_ERR_NOT_ENABLED, "created with monitor_every == 0");
+  const Plan& P = *B.scenes[scene];
+  *n = B.mon_last;
+  const int k = std::min(cap, B.mon_last);
+  if (k <= 0) return NLPR_OK;
+  DeviceGuard dg(B.device);
+  NLPR_HIP_TRY(hipEventSynchronize(B.done_ev));
+  const size_t off = 4 * (size_t)pixel_blocks(P) + (P.npairs ? monreg_blocks(P) : 0);
+  NLPR_HIP_TRY(hipMemcpy(trace, P.d_mon + off, (size_t)k * 8 * sizeof(double),
+                         hipMemcpyDeviceToHost));
+  return NLPR_OK;
+}
+
 // Create a batch from scene parameters (n >= 1).
 int batch_create(Batch& B, int n, const nlpr_params* params, const float* const* blur,
                  const float* const* R, const float* const* E) {
@@ -601,16 +656,18 @@ int batch_create(Batch& B, int n, const nlpr_params* params, const float* const*
   const uint32_t bf = params[0].flags & kBatchFlags;
   for (int i = 0; i < n; ++i) {
     if (!blur[i] || !R[i]) return fail(NLPR_ERR_INVALID_ARG, "NULL blur taps or R");
-    if ((params[i].flags & kBatchFlags) != bf || params[i].iters != params[0].iters)
+    if ((params[i].flags & kBatchFlags) != bf || params[i].iters != params[0].iters ||
+        params[i].monitor_every != params[0].monitor_every)
       return fail(NLPR_ERR_INVALID_ARG,
-                  "scenes of a batch must share iters and the flags INIT_ZERO, STATE_IN, "
-                  "CHECK_FINITE, TIMING and GRAPH");
+                  "scenes of a batch must share iters, monitor_every and the flags INIT_ZERO, "
+                  "STATE_IN, CHECK_FINITE, TIMING and GRAPH");
     int rc = validate(params[i]);
     if (rc) return rc;
   }
   if (hipGetDevice(&B.device) != hipSuccess) return fail(NLPR_ERR_HIP, "no HIP device");
   B.flags = bf;
   B.iters = params[0].iters;
+  B.monitor_every = params[0].monitor_every;
   B.timing = (bf & NLPR_TIMING) != 0;
   B.use_graph = (bf & NLPR_GRAPH) != 0;
   for (int i = 0; i < n; ++i) {
@@ -718,12 +775,19 @@ int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void
   return batch_solve(plan->B, &Yl, &Yh, &Z, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
+int nlpr_monitor(const nlpr_plan* plan, double* trace, int32_t cap, int32_t* n) {
+  if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
+  return batch_monitor(plan->B, 0, trace, cap, n);
+}
+
 int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbufs, void* stream) {
   if (!plan || !bufs) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
   Batch& B = plan->B;
   const Plan& P = *B.scenes[0];
-  static const int need[NLPR_STAGE_COUNT] = {0, 2, 3, 2, 2, 8, 5, 5, 4, 7};
+  static const int need[NLPR_STAGE_COUNT] = {0, 2, 3, 2, 2, 8, 5, 5, 4, 7, 0};
   if (stage < 1 || stage >= NLPR_STAGE_COUNT) return fail(NLPR_ERR_INVALID_ARG, "unknown stage");
+  if (stage == NLPR_STAGE_MONITOR)
+    return fail(NLPR_ERR_INVALID_ARG, "the monitor has no per-stage entry point");
   if (nbufs < need[stage]) return fail(NLPR_ERR_INVALID_ARG, "too few buffers for the stage");
   int rc;
   for (int i = 0; i < need[stage]; ++i)
@@ -812,6 +876,12 @@ int nlpr_batch_create(int32_t n, const nlpr_params* params, const float* const* 
   }
   *out = h;
   return NLPR_OK;
+}
+
+int nlpr_batch_monitor(const nlpr_batch* batch, int32_t scene, double* trace, int32_t cap,
+                       int32_t* n) {
+  if (!batch) return fail(NLPR_ERR_INVALID_ARG, "batch is NULL");
+  return batch_monitor(batch->B, scene, trace, cap, n);
 }
 
 int nlpr_batch_destroy(nlpr_batch* batch) {

@@ -65,6 +65,11 @@ struct SceneDesc {
   const float* E;                  // [Ls][Lz]
   const float* Ep;                 // E^+ = E^T (E E^T)^{-1}, [Lz][Ls]
   const float* M;                  // (E E^T + rho I)^{-1}, [Ls][Ls]
+  // monitor: partial sums [mon_npix][4] (data_l, data_h, r1^2, r2^2 per pixel block), then
+  // [mon_nreg] (regulariser per (shift, tile) block), then the trace [points][8]
+  double* mon;
+  int mon_npix, mon_nreg;
+  double rho_d, lam1_d;
   void* buf[B_COUNT];
 };
 
@@ -102,6 +107,8 @@ struct Plan {
   float* d_Ep = nullptr;          // [L][Ls]
   float* d_M = nullptr;           // [Ls][Ls]
   float* d_Rt = nullptr;          // E R, [Ls][Lh]
+  double* d_mon = nullptr;        // monitor partials and trace (monitor_every > 0)
+  int mon_points = 0;             // records per solve
   SweepShape sweep{};
   // workspace layout relative to the scene's base
   size_t off[B_COUNT] = {};
@@ -121,12 +128,17 @@ struct Group {
 enum Kind { KD_WEIGHTS = 0, KD_PLANE, KD_CONV, KD_PIXEL, KD_SWEEP, KD_ROWS, KD_COLS,
             KD_LOWRES,   // one thread per low-resolution pixel of scenes with a basis
             KD_COMPOSE,  // one thread per pixel of scenes with a basis
+            KD_MONREG,   // monitor regulariser: (shift, 32 x 64 tile) of scenes with a window
+            KD_SCENE,    // one workgroup per scene
             KD_COUNT };
 
 struct Batch {
   int device = 0;
   uint32_t flags = 0;              // flags shared by every scene (INIT_ZERO, STATE_IN, ...)
   int iters = 0;
+  int monitor_every = 0;           // shared by every scene
+  int mon_last = 0;                // monitor records written by the last solve
+  hipEvent_t done_ev = nullptr;    // recorded after each solve
   std::vector<Plan*> scenes;       // owned
   std::vector<size_t> base;        // workspace base of each scene
   size_t ws_bytes = 0;
@@ -177,6 +189,7 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // Vector elements move through clang ext-vector types (HIP's vector structs cannot be
 // copied out of an address-space-qualified object).
 typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) double gdouble;
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef int v2i_t __attribute__((ext_vector_type(2)));
@@ -242,6 +255,12 @@ int lowres_blocks(const Plan& P);
 int launch_project(const Batch& B, int yl, int yle, int ylp, hipStream_t s);
 int launch_p1_subspace(const Batch& B, int bx, int yle, int l1, int w1, hipStream_t s);
 int launch_compose(const Batch& B, int x, int z, hipStream_t s);
+// monitor (monitor.hip): objective terms and primal residuals after iteration `iter`,
+// written to record `point` of each scene's trace
+int monreg_blocks(const Plan& P);
+size_t monreg_lds(const Plan& P);
+int monitor_points(int iters, int every);
+int launch_monitor(const Batch& B, int point, int iter, hipStream_t s);
 int launch_finite(const Batch& B, int z, int* flag, hipStream_t s);
 int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] slot
 int launch_xsolve(const Batch& B, int c, int x, int f, hipStream_t s);

@@ -41,9 +41,15 @@ STAGE_SWEEP = 6
 STAGE_SWEEP_FIRST = 7
 STAGE_ASSEMBLE = 8
 STAGE_INIT = 9
+STAGE_MONITOR = 10
 STAGE_NAMES = {STAGE_WEIGHTS: "weights", STAGE_XSOLVE: "xsolve", STAGE_BLUR: "blur",
                STAGE_BLUR_T: "blur_t", STAGE_PUPDATE: "pupdate", STAGE_SWEEP: "sweep",
-               STAGE_SWEEP_FIRST: "sweep_first", STAGE_ASSEMBLE: "assemble", STAGE_INIT: "init"}
+               STAGE_SWEEP_FIRST: "sweep_first", STAGE_ASSEMBLE: "assemble", STAGE_INIT: "init",
+               STAGE_MONITOR: "monitor"}
+
+# fields of a monitor record (nlpr_monitor)
+MON_FIELDS = ("iteration", "objective", "data_l", "data_h", "reg", "r1", "r2")
+MON_RECORD = 8
 
 REGION_SIGMA = 0
 REGION_MU = 1
@@ -56,12 +62,13 @@ EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlp
                    "nlpr_workspace_region", "nlpr_debug_stage", "nlpr_stage_time",
                    "nlpr_plan_get_info", "nlpr_batch_create", "nlpr_batch_workspace_size",
                    "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
-                   "nlpr_batch_destroy"])
+                   "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor"])
 
 
 class NlprError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"nlpr status {status}: {msg}")
+        self.status = status
         self.status = status
 
 
@@ -69,7 +76,7 @@ class Params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("Lh", ctypes.c_int32), ("d", ctypes.c_int32), ("blur_radius", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("Sw", ctypes.c_int32), ("iters", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("Ls", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("Ls", ctypes.c_int32), ("monitor_every", ctypes.c_int32),
                 ("lam", ctypes.c_double), ("lam1", ctypes.c_double),
                 ("rho", ctypes.c_double), ("h", ctypes.c_double)]
 
@@ -115,6 +122,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_batch_stage_time.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.nlpr_batch_destroy.argtypes = [vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.nlpr_monitor.argtypes = [vp, dp, i32, ctypes.POINTER(i32)]
+    lib.nlpr_batch_monitor.argtypes = [vp, i32, dp, i32, ctypes.POINTER(i32)]
     for name in EXPORTED:
         if name not in ("nlpr_status_string", "nlpr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -151,7 +161,8 @@ class Plan:
 
     def __init__(self, p: int, q: int, L: int, Lh: int, d: int, blur: np.ndarray,
                  R: np.ndarray, K: int, Sw: int, iters: int, lam: float, rho: float, h: float,
-                 lam1: float = 1.0, flags: int = 0, E: Optional[np.ndarray] = None):
+                 lam1: float = 1.0, flags: int = 0, E: Optional[np.ndarray] = None,
+                 monitor_every: int = 0):
         lib = load()
         blur = np.ascontiguousarray(blur, dtype=np.float32)
         R = np.ascontiguousarray(R, dtype=np.float32).reshape(L, Lh)
@@ -164,7 +175,8 @@ class Plan:
             Ls = E.shape[0]
             if E.shape != (Ls, L):
                 raise ValueError("E must be Ls x L")
-        self.params = Params(p, q, L, Lh, d, r, K, Sw, iters, flags, Ls, 0, lam, lam1, rho, h)
+        self.params = Params(p, q, L, Lh, d, r, K, Sw, iters, flags, Ls, monitor_every, lam, lam1,
+                             rho, h)
         self.shape = (L, p, q)
         self.xbands = Ls if Ls else L
         self._blur, self._R, self._E = blur, R, E
@@ -256,6 +268,20 @@ class Plan:
                                       1 if reset else 0))
         return ms.value, n.value
 
+    def monitor(self) -> np.ndarray:
+        """Monitor records of the last solve, [n][8] float64 (fields MON_FIELDS)."""
+        return _read_monitor(lambda buf, cap, n: load().nlpr_monitor(self.handle, buf, cap, n))
+
+
+def _read_monitor(call) -> np.ndarray:
+    n = ctypes.c_int32()
+    _check(call(None, 0, ctypes.byref(n)))
+    out = np.zeros((n.value, MON_RECORD), dtype=np.float64)
+    if n.value:
+        _check(call(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
+                    ctypes.byref(n)))
+    return out
+
 
 def _scene_kwargs(scene, flags: int = 0, **over):
     s = scene.spec
@@ -290,8 +316,9 @@ class Batch:
                 self._keep.append(E)
                 Es[i] = E.ctypes.data
             self.params[i] = Params(kw["p"], kw["q"], kw["L"], kw["Lh"], kw["d"], r, kw["K"],
-                                    kw["Sw"], kw["iters"], kw.get("flags", 0), Ls, 0, kw["lam"],
-                                    kw.get("lam1", 1.0), kw["rho"], kw["h"])
+                                    kw["Sw"], kw["iters"], kw.get("flags", 0), Ls,
+                                    kw.get("monitor_every", 0), kw["lam"], kw.get("lam1", 1.0),
+                                    kw["rho"], kw["h"])
             self._keep += [blur, R]
             blurs[i] = blur.ctypes.data
             Rs[i] = R.ctypes.data
@@ -348,6 +375,11 @@ class Batch:
         _check(load().nlpr_batch_stage_time(self.handle, stage, ctypes.byref(ms),
                                             ctypes.byref(n), 1 if reset else 0))
         return ms.value, n.value
+
+    def monitor(self, scene: int) -> np.ndarray:
+        """Monitor records of one scene from the last batched solve, [n][8] float64."""
+        return _read_monitor(
+            lambda buf, cap, n: load().nlpr_batch_monitor(self.handle, scene, buf, cap, n))
 
 
 def fuse(Yl, Yh, blur, R, d: int, lam: float, K: int, Sw: int, rho: float, iters: int, h: float,

@@ -54,7 +54,7 @@ def _create(**over):
     kw.update(over)
     r = kw["blur_radius"]
     prm = nlpr.Params(kw["p"], kw["q"], kw["L"], kw["Lh"], kw["d"], r, kw["K"], kw["Sw"],
-                      kw["iters"], kw["flags"], kw.get("Ls", 0), kw.get("reserved", 0), kw["lam"],
+                      kw["iters"], kw["flags"], kw.get("Ls", 0), kw.get("monitor_every", 0), kw["lam"],
                       kw["lam1"], kw["rho"], kw["h"])
     blur = np.ones((2 * r + 1, 2 * r + 1), np.float32)
     R = np.ones((kw["L"], kw["Lh"]), np.float32)
@@ -85,7 +85,7 @@ def _create(**over):
     (dict(p=64, q=4096, K=4, Sw=8, d=1), nlpr.ERR_UNSUPPORTED_SHAPE),   # sweep tile exceeds LDS
     (dict(Ls=9), nlpr.ERR_UNSUPPORTED_SHAPE),                         # more basis rows than bands
     (dict(Ls=2), nlpr.ERR_INVALID_ARG),                               # Ls without a basis
-    (dict(reserved=1), nlpr.ERR_INVALID_ARG),
+    (dict(monitor_every=-1), nlpr.ERR_INVALID_ARG),
 ])
 def test_invalid_parameters_are_rejected_on_the_host(over, code):
     rc, h, msg = _create(**over)
@@ -129,3 +129,16 @@ def test_batch_rejects_scenes_with_different_iteration_counts():
     assert lib.nlpr_batch_create(2, prm, ptrs, rs, None, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
     assert lib.nlpr_batch_create(0, prm, ptrs, rs, None, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
     assert lib.nlpr_batch_destroy(None) == nlpr.OK
+    # scenes must also share the monitor interval
+    prm2 = (nlpr.Params * 2)(nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 3, 0, 0, 1, 1e-3, 1.0, 1e-2, 0.1),
+                             nlpr.Params(64, 64, 8, 1, 4, 1, 1, 2, 3, 0, 0, 2, 1e-3, 1.0, 1e-2, 0.1))
+    assert lib.nlpr_batch_create(2, prm2, ptrs, rs, None, ctypes.byref(h)) == nlpr.ERR_INVALID_ARG
+    assert "monitor_every" in lib.nlpr_last_error().decode()
+
+
+def test_monitor_entry_points_reject_null_handles():
+    lib = nlpr.load()
+    n = ctypes.c_int32(-1)
+    assert lib.nlpr_monitor(None, None, 0, ctypes.byref(n)) == nlpr.ERR_INVALID_ARG
+    assert lib.nlpr_batch_monitor(None, 0, None, 0, ctypes.byref(n)) == nlpr.ERR_INVALID_ARG
+    assert n.value == -1
