@@ -41,6 +41,9 @@ Readings of points the paper leaves open (each one is listed in the design doc):
     ``init="zero"`` starts every variable at 0.
   * The patch distance of eq. (wts) is the plain sum of squared differences over all
     (2K+1)^2 L_h entries of the patch, without normalisation.
+  * Besides the paper's splitting, ``Problem.fused`` selects a splitting without P1 that
+    keeps S B in the X-subproblem (the aliasing-group solve below); E = I there, and its
+    default start is that of the paper's splitting without P1 and Lambda1.
 """
 from __future__ import annotations
 
@@ -189,6 +192,53 @@ def x_update(C: np.ndarray, den: np.ndarray) -> np.ndarray:
     return np.fft.ifft2(np.fft.fft2(C) / den).real
 
 
+# ------------------------------------------ X-update with S inside the system (fused-S)
+# A variant of the splitting of eq. (fusionoptim) without P1: the data term
+# 1/2 ||Y_l - S B X||^2 stays in the X-subproblem, whose normal equation becomes
+#   (I + sum_{tau, k} D^T D + B^T S^T S B / rho) X = B^T S^T Y_l / rho + P2 + Lambda2
+#                                                   + sum_{tau, k} D^T (Q + Sigma).
+# It has the same minimiser as the paper's splitting (both are ADMM on a split of the
+# same objective) and different iterates.  The first two terms are diagonal in Fourier
+# (eqs. (xupdateoper), (inv) without the blur); S^T S is the sampling mask, which in
+# Fourier averages each frequency with its d^2 - 1 aliases w + (m1 p/d, m2 q/d).
+def fused_denominator(p: int, q: int, window: Sequence[Offset], K: int) -> np.ndarray:
+    """a(w) = 1 + |P| sum_{tau in W} |d^_{tau 0}(w)|^2: the denominator of eq. (inv)
+    without the blur term."""
+    return denominator(p, q, np.zeros((1, 1)), window, K)
+
+
+def aliasing_groups(p: int, q: int, d: int) -> np.ndarray:
+    """Index arrays [groups][d^2] (rows, cols) of the frequencies the mask S^T S couples:
+    (w1 + m1 p/d, w2 + m2 q/d) for m1, m2 in [0, d), one group per (w1, w2) in
+    [0, p/d) x [0, q/d)."""
+    pd, qd = p // d, q // d
+    w1, w2 = np.meshgrid(np.arange(pd), np.arange(qd), indexing="ij")
+    m1, m2 = np.meshgrid(np.arange(d), np.arange(d), indexing="ij")
+    rows = w1.reshape(-1, 1) + pd * m1.reshape(1, -1)
+    cols = w2.reshape(-1, 1) + qd * m2.reshape(1, -1)
+    return rows, cols
+
+
+def x_update_fused(C: np.ndarray, pr: Problem, a: np.ndarray) -> np.ndarray:
+    """Solve (I + sum D^T D + B^T S^T S B / rho) X = C band by band.  In Fourier the
+    system is a(w) x^(w) + conj(b^(w)) / (rho d^2) sum_{w' ~ w} b^(w') x^(w'), with w' over
+    the aliasing group of w: one dense d^2 x d^2 complex system per group, solved
+    directly."""
+    p, q, d = pr.p, pr.q, pr.d
+    bh = np.fft.fft2(blur_filter_grid(pr.b, p, q))
+    rows, cols = aliasing_groups(p, q, d)
+    bv = bh[rows, cols]                                             # [G][d^2]
+    A = np.zeros(bv.shape + (bv.shape[1],), dtype=complex)
+    A[:, np.arange(d * d), np.arange(d * d)] = a[rows, cols]
+    A += np.conj(bv)[:, :, None] * bv[:, None, :] / (pr.rho * d * d)
+    Ch = np.fft.fft2(C)                                             # [L][p][q]
+    rhs = np.moveaxis(Ch[:, rows, cols], 0, -1)                     # [G][d^2][L]
+    sol = np.linalg.solve(A, rhs)
+    Xh = np.empty_like(Ch)
+    Xh[:, rows, cols] = np.moveaxis(sol, -1, 0)
+    return np.fft.ifft2(Xh).real
+
+
 # ----------------------------------------------------------------------- problem
 @dataclasses.dataclass
 class Problem:
@@ -209,6 +259,7 @@ class Problem:
     unweighted: bool = False
     local: bool = False
     E: Optional[np.ndarray] = None   # subspace basis [Ls][L] (Z = X E); None means E = I
+    fused: bool = False     # keep S B inside the X-subproblem (no P1 split); E = I only
 
     @property
     def Ebasis(self) -> np.ndarray:
@@ -330,6 +381,8 @@ def initial_state(Yl: np.ndarray, pr: Problem, init: str = "upsample") -> Tuple[
             E = pr.E
             X0 = from_mat(to_mat(X0) @ E.T @ np.linalg.inv(E @ E.T), pr.p, pr.q)
         P1, P2 = blur(X0, pr.b), X0.copy()
+        if pr.fused:                   # no P1 in the fused-S splitting
+            P1 = np.zeros(shape)
     elif init == "zero":
         X0 = np.zeros(shape)
         P1, P2 = np.zeros(shape), np.zeros(shape)
@@ -370,6 +423,28 @@ def admm_step(st: State, Yl: np.ndarray, Yh: np.ndarray, pr: Problem, den: np.nd
     return X, State(P1=P1, P2=P2, Q=Q, Lam1=Lam1, Lam2=Lam2, Sig=Sig)
 
 
+def admm_step_fused(st: State, Yl: np.ndarray, Yh: np.ndarray, pr: Problem, a: np.ndarray,
+                    C0: np.ndarray, mu: np.ndarray, F: np.ndarray) -> Tuple[np.ndarray, State]:
+    """One iteration of the fused-S variant: the X-update solves the system above with
+    right-hand side C0 + P2 + Lambda2 + sum D^T (Q + Sigma), C0 = B^T S^T Y_l / rho; then
+    P2, Q, Lambda2 and Sigma as in the paper's iteration.  P1 and Lambda1 stay 0."""
+    C = C0 + st.P2 + st.Lam2
+    for n, t in enumerate(pr.window):
+        for m, k in enumerate(pr.patch):
+            C += D_T(st.Q[n, m] + st.Sig[n, m], t, k)
+    X = x_update_fused(C, pr, a)
+    P2 = p2_update(X, st.Lam2, Yh, pr, F)                            # eq. (Qm_update)
+    Q = np.empty_like(st.Q)
+    Sig = np.empty_like(st.Sig)
+    for n, t in enumerate(pr.window):
+        for m, k in enumerate(pr.patch):
+            DX = D(X, t, k)
+            Q[n, m] = soft_threshold(DX - st.Sig[n, m], mu[n][None])  # eq. (Qj_main)
+            Sig[n, m] = st.Sig[n, m] - (DX - Q[n, m])                 # eq. (dualvar3_main)
+    Lam2 = st.Lam2 - (X - P2)                                        # eq. (dualvar2_main)
+    return X, State(P1=st.P1, P2=P2, Q=Q, Lam1=st.Lam1, Lam2=Lam2, Sig=Sig)
+
+
 def fixed_point_residual(a: State, b: State, rho: float) -> float:
     """rho (||V^{t+1} - V^t||^2 + ||U^{t+1} - U^t||^2) with V = (P1, P2, Q) and
     U = (Lambda1, Lambda2, Sigma), the grouping of the Appendix (eqs. (Vdef2), (Udef))."""
@@ -383,8 +458,10 @@ def fixed_point_residual(a: State, b: State, rho: float) -> float:
 def primal_residuals(X: np.ndarray, st: State, pr: Problem) -> Tuple[float, float]:
     """||B X - P1|| and ||X - P2||: how far the iterate is from the constraints P1 = B X and
     P2 = X of the split problem eq. (fusionoptim), after the step that produced X and st."""
-    r1 = blur(X, pr.b) - st.P1
     r2 = X - st.P2
+    if pr.fused:                       # no P1 = B X constraint in the fused-S splitting
+        return 0.0, float(np.sqrt(np.sum(r2 * r2)))
+    r1 = blur(X, pr.b) - st.P1
     return float(np.sqrt(np.sum(r1 * r1))), float(np.sqrt(np.sum(r2 * r2)))
 
 
@@ -431,11 +508,18 @@ def solve(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, init: str = "
     mu = pr.lam * omega / pr.rho
     F = p2_matrix(pr)
     X, st = state if state is not None else initial_state(Yl, pr, init)
+    if pr.fused:
+        assert pr.E is None, "the fused-S variant is built for E = I"
+        a = fused_denominator(pr.p, pr.q, pr.window, pr.K)
+        C0 = blur_T(decimate_T(Yl, pr.d, pr.p, pr.q), pr.b) / pr.rho
+        step = lambda st_: admm_step_fused(st_, Yl, Yh, pr, a, C0, mu, F)
+    else:
+        step = lambda st_: admm_step(st_, Yl, Yh, pr, den, mu, F)
     objs: List[float] = []
     res: List[float] = []
     mons: List[Monitor] = []
     for t in range(1, iters + 1):
-        X, nst = admm_step(st, Yl, Yh, pr, den, mu, F)
+        X, nst = step(st)
         if track:
             objs.append(objective(X, Yl, Yh, pr, omega))
             res.append(fixed_point_residual(nst, st, pr.rho))

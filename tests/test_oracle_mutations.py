@@ -27,6 +27,7 @@ FAST_PINS = [
     lambda: pins.test_lambda2_zero_with_square_R_gives_the_least_squares_solution(0, 0.5, 500),
     lambda: pins.test_objective_terms_equal_dense_operator_forms(None),
     lambda: pins.test_primal_residuals_are_the_lambda_steps(None),
+    lambda: pins.test_fused_x_update_equals_dense_solve(8, 12, 2, 1, 1),
 ]
 
 _orig = {name: getattr(o, name) for name in dir(o) if callable(getattr(o, name))}
@@ -113,7 +114,18 @@ def _mut_primal_residuals(X, st, pr):                  # first residual against 
     return float(np.sqrt(np.sum(r1 * r1))), float(np.sqrt(np.sum(r2 * r2)))
 
 
+def _mut_fused_denominator(p, q, window, K):             # the patch factor |P| dropped
+    return _orig["fused_denominator"](p, q, window, 0)
+
+
+def _mut_aliasing_groups(p, q, d):                      # aliases along one axis only
+    rows, cols = _orig["aliasing_groups"](p, q, d)
+    return rows, np.repeat(cols[:, :1], cols.shape[1], axis=1)
+
+
 MUTATIONS["objective_terms"] = _mut_objective_terms
+MUTATIONS["fused_denominator"] = _mut_fused_denominator
+MUTATIONS["aliasing_groups"] = _mut_aliasing_groups
 MUTATIONS["primal_residuals"] = _mut_primal_residuals
 
 

@@ -531,3 +531,48 @@ def test_primal_residuals_vanish_at_the_optimum():
     late = o.solve(Yl, Yh, pr, 3000, monitor_every=3000).monitor[-1]
     assert late.r1 < 1e-9 and late.r2 < 1e-9
     assert early.r1 > 1e3 * late.r1 and early.r2 > 1e3 * late.r2
+
+
+# -------------------------------------------------------- fused-S X-update (S in the system)
+@pytest.mark.parametrize("p,q,d,K,S", [(8, 12, 2, 1, 1), (8, 8, 4, 0, 1), (12, 8, 4, 1, 2)])
+def test_fused_x_update_equals_dense_solve(p, q, d, K, S):
+    """(I + sum_{tau, k} D^T D + B^T S^T S B / rho) X = C from explicit matrices."""
+    pr, _, _ = tiny_problem(p=p, q=q, L=2, Lh=1, d=d, r=1, K=K, S=S, rho=0.37)
+    pr.fused = True
+    n = p * q
+    Mb = dense_blur(p, q, pr.b)
+    Sd = dense_decimate(p, q, d)
+    A = np.eye(n) + Mb.T @ Sd.T @ Sd @ Mb / pr.rho
+    for t in pr.window:
+        for k in pr.patch:
+            Dm = dense_shift_diff(p, q, t, k)
+            A += Dm.T @ Dm
+    C = RNG.standard_normal((2, p, q))
+    want = np.stack([np.linalg.solve(A, C[c].ravel()).reshape(p, q) for c in range(2)])
+    a = o.fused_denominator(p, q, pr.window, pr.K)
+    np.testing.assert_allclose(o.x_update_fused(C, pr, a), want, atol=1e-11)
+
+
+def test_fused_x_update_without_decimation_is_a_fourier_division():
+    # d = 1: S = I, the system is diagonal in Fourier with 1 + |b^|^2 / rho + |P| sum |d^|^2
+    pr, _, _ = tiny_problem(p=6, q=10, L=2, d=1, rho=0.6)
+    C = RNG.standard_normal((2, 6, 10))
+    bh = np.fft.fft2(o.blur_filter_grid(pr.b, 6, 10))
+    a = o.fused_denominator(6, 10, pr.window, pr.K)
+    den = a + np.abs(bh) ** 2 / pr.rho
+    want = np.fft.ifft2(np.fft.fft2(C) / den).real
+    np.testing.assert_allclose(o.x_update_fused(C, pr, a), want, atol=1e-12)
+
+
+def test_fused_admm_reaches_the_optimum_of_an_independent_solver():
+    """Same minimiser as the paper's splitting (Theorem 1 holds for this splitting too):
+    compare the optimal value with the primal-dual solver on dense matrices."""
+    pr, Yl, Yh = tiny_problem(p=4, q=6, L=2, Lh=1, d=2, K=1, S=1, lam=0.02, h=0.7)
+    H, bb, c0, G, w = _dense_problem(pr, Yl, Yh)
+    f_pd = _dense_objective(_pdhg(H, bb, G, w, 10000), H, bb, c0, G, w)
+    pr.fused = True
+    pr.rho = 0.3
+    res = o.solve(Yl, Yh, pr, 4000, monitor_every=4000)
+    f = _dense_objective(vec(res.X).T.ravel(), H, bb, c0, G, w)
+    assert f == pytest.approx(f_pd, rel=1e-10)
+    assert res.monitor[-1].r1 == 0.0 and res.monitor[-1].r2 < 1e-9
