@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--subspace", type=int, default=0,
                     help="Ls > 0: solve for Z = X E with E the Ls leading right singular "
                          "vectors of Y_l")
+    ap.add_argument("--fused", action="store_true",
+                    help="the splitting with S inside the X-update (no P1)")
     ap.add_argument("--monitor", type=int, default=0,
                     help="record the objective and residuals every N iterations (0 = off; "
                          "the default run keeps it off)")
@@ -246,7 +248,8 @@ def main():
         M = sc.Yl.reshape(spec.L, -1).T.astype(np.float64)
         E = np.ascontiguousarray(np.linalg.svd(M, full_matrices=False)[2][:args.subspace],
                                  dtype=np.float32)
-    plan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING, E=E, monitor_every=args.monitor)
+    flags = nlpr.TIMING | (nlpr.FUSED_S if args.fused else 0)
+    plan = nlpr.Plan.from_scene(sc, flags=flags, E=E, monitor_every=args.monitor)
     npairs = len(plan.half_window())
     ws = plan.alloc_workspace()
     Z = torch.empty((spec.L, spec.p, spec.q), dtype=torch.float32, device=dev)
@@ -292,7 +295,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload_name(spec) + (f", subspace Ls={args.subspace}"
-                                                      if args.subspace else ""),
+                                                      if args.subspace else "")
+                   + (", fused-S X-update" if args.fused else ""),
                    "p": spec.p, "q": spec.q, "L": spec.L, "Ls": args.subspace or spec.L,
                    "Lh": spec.Lh, "d": spec.d, "blur": 2 * spec.blur_radius + 1,
                    "patch": 2 * spec.K + 1, "window": 2 * spec.Sw + 1, "iters": spec.iters,

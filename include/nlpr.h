@@ -66,11 +66,18 @@ enum {
   NLPR_CHECK_FINITE = 1u << 4,  /* nlpr_solve checks Z for NaN/Inf at the end; this synchronises
                                    the stream and may return NLPR_ERR_NUMERICAL                      */
   NLPR_TIMING = 1u << 5,        /* record HIP events around every stage; read with nlpr_stage_time   */
-  NLPR_GRAPH = 1u << 6          /* capture the whole solve (weights, start, all iterations) in a HIP
+  NLPR_GRAPH = 1u << 6,         /* capture the whole solve (weights, start, all iterations) in a HIP
                                    graph on the first call and replay it on later calls; ignored
                                    with NLPR_TIMING.  The graph reads buffer addresses from a
                                    device descriptor written before each launch, so later calls
                                    may pass other buffers.                                          */
+  NLPR_FUSED_S = 1u << 7        /* splitting without P1: the X-update keeps S B in its system,
+                                   (I + sum D^T D + B^T S^T S B / rho) X = B^T S^T Y_l / rho + P2
+                                   + Lambda2 + sum D^T (Q + Sigma), solved in Fourier per
+                                   aliasing group of d^2 frequencies (Sherman-Morrison, tables in
+                                   FP64).  Same minimiser as the paper's splitting of eq.
+                                   (fusionoptim), different iterates.  Requires Ls == 0 and
+                                   8 * d * p <= 65536 (a column group fits one FFT workgroup).  */
 };
 
 /*
@@ -128,6 +135,9 @@ typedef struct nlpr_plan nlpr_plan;
  *   blur_host : host, (2r+1)^2 floats, row-major, tap b(m1, m2) at [(m1 + r)(2r+1) + m2 + r];
  *               B X (i) = sum_m b(m) X(i - m), circular.
  *   R_host    : host, L x Lh floats, row-major (R[c][h] at [c * Lh + h]).
+ *   With NLPR_FUSED_S the plan also holds, per frequency, the FP64-derived factors of the
+ *   aliasing-group solve (1/a, b^/a and gamma conj(b^)/a, with a the denominator of
+ *   eq. (inv) without |b^|^2 and gamma = 1/(rho d^2 + sum_group |b^|^2/a)).
  *   E_host    : host, Ls x L floats, row-major (E[s][c] at [s * L + c]), the subspace basis
  *               (rows need not be orthonormal, E E^T must be invertible); NULL iff Ls == 0.
  *               With a basis the plan also holds, computed in FP64: (E E^T + rho I)^{-1} for

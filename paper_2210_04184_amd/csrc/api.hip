@@ -23,7 +23,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 namespace {
 
 constexpr uint32_t kBatchFlags = NLPR_INIT_ZERO | NLPR_STATE_IN | NLPR_CHECK_FINITE |
-                                 NLPR_TIMING | NLPR_GRAPH;
+                                 NLPR_TIMING | NLPR_GRAPH | NLPR_FUSED_S;
 
 bool factor_23(int n, LineFFT& f) {
   f.n = n;
@@ -84,6 +84,10 @@ int validate(const nlpr_params& q) {
   if (q.Sw < 0 || q.Sw > kMaxSw) return bad("Sw must lie in [0, 8]");
   if (q.Sw >= q.p || q.Sw >= q.q) return bad("Sw must be smaller than p and q");
   if ((q.flags & NLPR_LOCAL_WINDOW) && q.Sw != 1) return bad("NLPR_LOCAL_WINDOW needs Sw == 1");
+  if (q.flags & NLPR_FUSED_S) {
+    if (q.Ls != 0) return bad("NLPR_FUSED_S takes no subspace basis (Ls must be 0)");
+    if ((size_t)8 * q.d * q.p > 65536) return bad("NLPR_FUSED_S needs 8 * d * p <= 65536");
+  }
   if (q.iters < 0) return fail(NLPR_ERR_INVALID_ARG, "iters must be >= 0");
   if (!(q.lambda >= 0.0) || !std::isfinite(q.lambda)) return fail(NLPR_ERR_INVALID_ARG, "lambda must be >= 0");
   if (!(q.lambda1 > 0.0) || !std::isfinite(q.lambda1)) return fail(NLPR_ERR_INVALID_ARG, "lambda1 must be > 0");
@@ -107,6 +111,9 @@ void scene_free(Plan* P) {
   hipFree(P->d_M);
   hipFree(P->d_Rt);
   hipFree(P->d_mon);
+  hipFree(P->d_fia);
+  hipFree(P->d_fu);
+  hipFree(P->d_fv);
   hipFree(P->d_taus);
   hipFree(P->d_invden);
   hipFree(P->d_tw_p);
@@ -179,6 +186,14 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
         hipMalloc(&P->d_Rt, (size_t)Lx * Lh * sizeof(float)) != hipSuccess ||
         hipMemcpy(P->d_E, E_host, (size_t)Lx * L * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
       set_error("allocation or upload of the subspace tables failed");
+      return cleanup(NLPR_ERR_HIP);
+    }
+  }
+  if (prm.flags & NLPR_FUSED_S) {
+    if (hipMalloc(&P->d_fia, plane * sizeof(float)) != hipSuccess ||
+        hipMalloc(&P->d_fu, plane * sizeof(float2)) != hipSuccess ||
+        hipMalloc(&P->d_fv, plane * sizeof(float2)) != hipSuccess) {
+      set_error("allocation of the fused-S tables failed");
       return cleanup(NLPR_ERR_HIP);
     }
   }
@@ -263,6 +278,10 @@ SceneDesc static_desc(const Plan& P) {
   d.blur = P.d_blur;
   d.R = P.d_E ? P.d_Rt : P.d_R;
   d.G = P.d_G;
+  d.fused = P.d_fia ? 1 : 0;
+  d.fia = P.d_fia;
+  d.fu = P.d_fu;
+  d.fv = P.d_fv;
   d.mon = P.d_mon;
   d.mon_npix = P.d_mon ? pixel_blocks(P) : 0;
   d.mon_nreg = P.d_mon ? monreg_blocks(P) : 0;
@@ -468,6 +487,11 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     reg = reg || P->npairs > 0;
     sub = sub || P->d_E != nullptr;
   }
+  // fused-S (shared by every scene of a batch): no P1 / Lambda1.  The constant part of
+  // every X-update, Xc0 = A^{-1} B^T S^T Y_l / rho, is solved once and added after each
+  // solve, so the per-iteration right-hand side W2 + C_reg stays of the size of X.  W1
+  // holds Xc0 and L1 serves as scratch.
+  const bool fused = (B.flags & NLPR_FUSED_S) != 0;
   if (sub) {
     StageTimer tm(B, s, NLPR_STAGE_INIT);
     if ((rc = launch_project(B, B_YL, B_YLE, B_YLP, s))) return rc;
@@ -476,19 +500,31 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     StageTimer tm(B, s, NLPR_STAGE_WEIGHTS);
     if ((rc = launch_weights(B, B_YH, B_MU, s))) return rc;
   }
+  if (fused) {
+    StageTimer tm(B, s, NLPR_STAGE_INIT);
+    if ((rc = launch_upsample_zero(B, B_YL, B_L1, s))) return rc;
+    if ((rc = launch_conv(B, B_L1, B_W1, true, -1, -1, -1, 0, s))) return rc;
+    if ((rc = launch_xsolve(B, B_W1, B_W1, B_F, -1, s))) return rc;
+  }
   if (!resume) {
     StageTimer tm(B, s, NLPR_STAGE_INIT);
     // X0 into Z, W2 = P2 + Lambda2 = X0, Lambda = 0, W1 = P1 + Lambda1 = B X0, C = B^T W1 + W2
+    // (fused-S: C = W2)
     if ((rc = launch_init(B, B_YL, B_YLP, B_Z, B_L1, B_L2, B_W2, s))) return rc;
-    if ((rc = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return rc;
-    if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s))) return rc;
+    if (fused) {
+      if ((rc = launch_conv(B, -1, B_C, false, B_W2, -1, -1, 0, s))) return rc;
+    } else {
+      if ((rc = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return rc;
+      if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s))) return rc;
+    }
   }
   for (int t = 0; t < B.iters; ++t) {
+    const bool mon = B.monitor_every > 0 && ((t + 1) % B.monitor_every == 0 || t + 1 == B.iters);
     {
       StageTimer tm(B, s, NLPR_STAGE_XSOLVE);
-      if ((rc = launch_xsolve(B, B_C, B_Z, B_F, s))) return rc;
+      if ((rc = launch_xsolve(B, B_C, B_Z, B_F, fused ? B_W1 : -1, s))) return rc;
     }
-    {
+    if (!fused || mon) {           // fused-S needs B X only for the monitor's data term
       StageTimer tm(B, s, NLPR_STAGE_BLUR);
       if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
     }
@@ -497,7 +533,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
       if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
       if (sub && (rc = launch_p1_subspace(B, B_BX, B_YLE, B_L1, B_W1, s))) return rc;
     }
-    if (B.monitor_every > 0 && ((t + 1) % B.monitor_every == 0 || t + 1 == B.iters)) {
+    if (mon) {
       StageTimer tm(B, s, NLPR_STAGE_MONITOR);
       if ((rc = launch_monitor(B, point++, t + 1, s))) return rc;
     }
@@ -508,7 +544,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     }
     {
       StageTimer tm(B, s, NLPR_STAGE_ASSEMBLE);
-      if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
+      if ((rc = launch_conv(B, fused ? -1 : B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
     }
   }
   if (sub) {
@@ -794,6 +830,8 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
     if ((rc = check_device_ptr(bufs[i], "stage buffer"))) return rc;
   if (P.d_E && (stage == NLPR_STAGE_INIT || stage == NLPR_STAGE_PUPDATE))
     return fail(NLPR_ERR_UNSUPPORTED_SHAPE, "the INIT and PUPDATE stages take no subspace basis");
+  if (P.d_fia && stage == NLPR_STAGE_INIT)
+    return fail(NLPR_ERR_UNSUPPORTED_SHAPE, "the INIT stage is for the paper's splitting");
   DeviceGuard dg(B.device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   SceneDesc d = static_desc(P);
@@ -814,7 +852,7 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
       return run([&] { return launch_weights(B, B_YH, B_MU, s); });
     case NLPR_STAGE_XSOLVE:
       put(B_C, 0); put(B_Z, 1); scratch(B_F, 2, B_F);
-      return run([&] { return launch_xsolve(B, B_C, B_Z, B_F, s); });
+      return run([&] { return launch_xsolve(B, B_C, B_Z, B_F, -1, s); });
     case NLPR_STAGE_BLUR:
     case NLPR_STAGE_BLUR_T:
       put(B_Z, 0); put(B_BX, 1);

@@ -66,6 +66,71 @@ __global__ void den_kernel(float* invden, int p, int q, const float* blur, int r
   invden[(size_t)u * q + v] = (float)(1.0 / (den * (double)p * (double)q));
 }
 
+// Tables of the X-update with S inside the system (fused-S).  Per band the system is
+//   a(w) x^(w) + conj(b^(w)) / (rho d^2) sum_{w' ~ w} b^(w') x^(w') = c^(w),
+// a = 1 + |P| sum_{tau in W} |d^_{tau 0}|^2, w' over the aliasing group of w (the d^2
+// frequencies (w1 + m1 p/d, w2 + m2 q/d) the sampling mask S^T S couples).  Each group's
+// matrix is diag(a) plus a rank-one term, so Sherman-Morrison gives
+//   x_j = c_j / a_j - (conj(b^_j) / a_j) gamma sum_k (b^_k / a_k) c_k,
+//   gamma = 1 / (rho d^2 + sum_k |b^_k|^2 / a_k).
+// One thread per group, all in FP64; stored FP32 in column-major [q][p] order with the
+// 1/(p q) of the unnormalised inverse DFT folded into ia and v:
+//   ia = 1 / (a p q),  u = b^ / a,  v = gamma conj(b^) / (a p q).
+__device__ void freq_terms(int u, int v, int p, int q, const float* blur, int r, const int2* taus,
+                           int npairs, int npatch, double* br, double* bi, double* a) {
+  double sr = 0.0, si = 0.0;
+  const int w = 2 * r + 1;
+  for (int m1 = -r; m1 <= r; ++m1) {
+    const long ka = (((long)u * m1) % p + p) % p;
+    for (int m2 = -r; m2 <= r; ++m2) {
+      const long kb = (((long)v * m2) % q + q) % q;
+      double sn, cs;
+      sincospi(-2.0 * ((double)ka / p + (double)kb / q), &sn, &cs);
+      const double tap = (double)blur[(m1 + r) * w + (m2 + r)];
+      sr += tap * cs;
+      si += tap * sn;
+    }
+  }
+  double dsum = 0.0;
+  for (int n = 0; n < npairs; ++n) {
+    const int2 t = taus[n];
+    const long ka = (((long)u * t.x) % p + p) % p;
+    const long kb = (((long)v * t.y) % q + q) % q;
+    dsum += 2.0 - 2.0 * cospi(2.0 * ((double)ka / p + (double)kb / q));
+  }
+  *br = sr;
+  *bi = si;
+  *a = 1.0 + (double)npatch * 2.0 * dsum;
+}
+
+__global__ void fused_tables_kernel(int p, int q, int d, const float* blur, int r,
+                                    const int2* taus, int npairs, int npatch, double rho,
+                                    float* ia, float2* fu, float2* fv) {
+  const int pd = p / d, qd = q / d;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= pd * qd) return;
+  const int w1 = g / qd, w2 = g - (g / qd) * qd;
+  double s = 0.0;
+  for (int m1 = 0; m1 < d; ++m1)
+    for (int m2 = 0; m2 < d; ++m2) {
+      double br, bi, a;
+      freq_terms(w1 + m1 * pd, w2 + m2 * qd, p, q, blur, r, taus, npairs, npatch, &br, &bi, &a);
+      s += (br * br + bi * bi) / a;
+    }
+  const double gamma = 1.0 / (rho * d * d + s);
+  const double pq = (double)p * (double)q;
+  for (int m1 = 0; m1 < d; ++m1)
+    for (int m2 = 0; m2 < d; ++m2) {
+      const int u = w1 + m1 * pd, v = w2 + m2 * qd;
+      double br, bi, a;
+      freq_terms(u, v, p, q, blur, r, taus, npairs, npatch, &br, &bi, &a);
+      const size_t o = (size_t)v * p + u;
+      ia[o] = (float)(1.0 / (a * pq));
+      fu[o] = make_float2((float)(br / a), (float)(bi / a));
+      fv[o] = make_float2((float)(gamma * br / (a * pq)), (float)(-gamma * bi / (a * pq)));
+    }
+}
+
 // G = (ratio I + R^T R)^{-1}, L_h x L_h, ratio = rho / lambda1, by Gauss-Jordan elimination
 // with partial pivoting in FP64 (one thread; L_h <= 16).
 __global__ void g_kernel(const float* R, int L, int Lh, double ratio, float* G) {
@@ -348,6 +413,24 @@ init_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   gslot<gfloat>(S, l2_s)[e] = 0.f;
 }
 
+// T = S^T Y_l / rho: the low-resolution pixels at (d m1, d m2), zero elsewhere (fused-S).
+__global__ void __launch_bounds__(256)
+upsample_zero_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yl_s,
+                     int t_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, d = S.d;
+  const size_t e = (size_t)it.y * 256 + threadIdx.x;
+  if (e >= (size_t)S.L * p * q) return;
+  const int c = (int)(e / ((size_t)p * q));
+  const int rem = (int)(e - (size_t)c * p * q);
+  const int i1 = rem / q, i2 = rem - i1 * q;
+  float v = 0.f;
+  if (i1 % d == 0 && i2 % d == 0)
+    v = gslot<const gfloat>(S, yl_s)[((size_t)c * (p / d) + i1 / d) * (q / d) + i2 / d] / S.rho;
+  gslot<gfloat>(S, t_s)[e] = v;
+}
+
 __global__ void __launch_bounds__(256)
 fill_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int s_) {
   const int2 it = items[blockIdx.x];
@@ -397,17 +480,21 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   float* tile = csh;
   float* tp = csh + TY * TX;
   const size_t plane = (size_t)p * q;
-  const gfloat* inc = gslot<const gfloat>(S, in_s) + (size_t)c * plane;
-  for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) tp[idx] = as_global(S.blur)[idx];
-  for (int idx = threadIdx.x; idx < TY * TX; idx += blockDim.x) {
-    const int yy = idx / TX, xx = idx % TX;
-    tile[idx] = inc[(size_t)wrapi(y0 - r + yy, p) * q + wrapi(x0 - r + xx, q)];
-  }
-  __syncthreads();
   const int y = threadIdx.x >> 4;            // 16 rows
   const int xb = (threadIdx.x & 15) * 4;     // 4 outputs per thread
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int m1 = -r; m1 <= r; ++m1) {
+  // in_s < 0: no convolution, out = add1 + add2 + halo fold (uniform over the launch)
+  const int rr = in_s < 0 ? -1 : r;
+  if (in_s >= 0) {
+    const gfloat* inc = gslot<const gfloat>(S, in_s) + (size_t)c * plane;
+    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) tp[idx] = as_global(S.blur)[idx];
+    for (int idx = threadIdx.x; idx < TY * TX; idx += blockDim.x) {
+      const int yy = idx / TX, xx = idx % TX;
+      tile[idx] = inc[(size_t)wrapi(y0 - r + yy, p) * q + wrapi(x0 - r + xx, q)];
+    }
+    __syncthreads();
+  }
+  for (int m1 = -rr; m1 <= rr; ++m1) {
     const float* trow = tile + (TR ? (y + r + m1) : (y + r - m1)) * TX + xb;
     const float* tap = tp + (m1 + r) * w;
     for (int m2 = -r; m2 <= r; ++m2) {
@@ -461,7 +548,7 @@ __device__ __forceinline__ void pupdate_body(
     const gfloat* __restrict__ Yh, gfloat* __restrict__ L1, gfloat* __restrict__ L2,
     gfloat* __restrict__ W1, gfloat* __restrict__ W2, const gfloat* __restrict__ R,
     const gfloat* __restrict__ G, int p, int q, int L, int Lh, int d, float rho, float inv_1prho,
-    int subspace, int j) {
+    int p1mode, int j) {
   const size_t plane = (size_t)p * q;
   const int i1 = j / q, i2 = j - i1 * q;
   const bool sampled = (i1 % d == 0) && (i2 % d == 0);
@@ -496,7 +583,9 @@ __device__ __forceinline__ void pupdate_body(
     const float l2n = l2 - (x - p2);
     L2[o] = l2n;
     W2[o] = p2 + l2n;
-    if (sampled && subspace) continue;   // coupled across bands: p1_subspace_kernel
+    // p1mode 1: a basis couples the sampled pixels across bands (p1_subspace_kernel);
+    // p1mode 2: fused-S splitting, no P1
+    if (p1mode == 2 || (sampled && p1mode == 1)) continue;
     const float bx = BX[o], l1 = L1[o];
     const float p1 = sampled ? (rho * bx + Yl[c * lplane + lj] - rho * l1) * inv_1prho : bx - l1;
     const float l1n = l1 - (bx - p1);
@@ -517,7 +606,8 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
                     gslot<const gfloat>(S, yl_s), gslot<const gfloat>(S, yh_s),
                     gslot<gfloat>(S, l1_s), gslot<gfloat>(S, l2_s), gslot<gfloat>(S, w1_s),
                     gslot<gfloat>(S, w2_s), as_global(S.R), as_global(S.G),
-                    S.p, S.q, S.L, S.Lh, S.d, S.rho, S.inv_1prho, S.subspace, j);
+                    S.p, S.q, S.L, S.Lh, S.d, S.rho, S.inv_1prho,
+                    S.fused ? 2 : (S.subspace ? 1 : 0), j);
 }
 
 template <typename Kern, typename... Args>
@@ -569,6 +659,13 @@ int launch_precompute(Plan& P) {
                        P.prm.Lh, P.prm.rho, P.d_M, P.d_Ep, P.d_Rt);
     NLPR_LAUNCH_CHECK("subspace_kernel");
   }
+  if (P.d_fia) {
+    const int groups = (p / P.prm.d) * (q / P.prm.d);
+    hipLaunchKernelGGL(fused_tables_kernel, dim3(ceil_div(groups, 64)), dim3(64), 0, nullptr, p, q,
+                       P.prm.d, P.d_blur, P.prm.blur_radius, P.d_taus, P.npairs, P.npatch,
+                       P.prm.rho, P.d_fia, P.d_fu, P.d_fv);
+    NLPR_LAUNCH_CHECK("fused_tables_kernel");
+  }
   hipLaunchKernelGGL(g_kernel, dim3(1), dim3(1), 0, nullptr, P.d_E ? P.d_Rt : P.d_R, P.Lx,
                      P.prm.Lh, P.prm.rho / P.prm.lambda1, P.d_G);
   NLPR_LAUNCH_CHECK("g_kernel");
@@ -581,6 +678,10 @@ int launch_weights(const Batch& B, int yh, int mu, hipStream_t s) {
 
 int launch_init(const Batch& B, int yl, int ylp, int x0, int l1, int l2, int w2, hipStream_t s) {
   return launch_groups(B, KD_PLANE, "init_kernel", init_kernel, s, yl, ylp, x0, l1, l2, w2);
+}
+
+int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s) {
+  return launch_groups(B, KD_PLANE, "upsample_zero_kernel", upsample_zero_kernel, s, yl, t);
 }
 
 int launch_fill(const Batch& B, int slot_, hipStream_t s) {

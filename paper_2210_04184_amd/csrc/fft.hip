@@ -183,6 +183,12 @@ __global__ void fft_rows_fwd(const SceneDesc* __restrict__ sd, const int2* __res
 
 // Forward DFT along columns, multiply by invden, inverse DFT along columns.
 // Local block = (pair, column block); LDS holds cb columns of p points.
+//
+// Fused-S scenes solve, per aliasing group of d^2 frequencies, the system of
+// fused_tables_kernel instead of the division: line l of the block holds column
+// b0 + (l % cbb) + (l / cbb) q/d (cbb = cb / d base columns and their d - 1 column aliases),
+// so each group's d^2 entries (rows i1 + m1 p/d of those d columns) are in LDS.  All lines
+// are transformed forward, the group solves run, then all lines are transformed back.
 __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
                                int f_s) {
   extern __shared__ float2 sh[];
@@ -190,42 +196,98 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
   const SceneDesc& S = sd[it.x];
   const int p = S.p, q = S.q, cb = S.fp_cb, tpl = S.fp_tpl;
   const int ncb = ceil_div(q, cb);
-  const int m = it.y / ncb, c0 = (it.y - m * ncb) * cb;
+  const int m = it.y / ncb, cblk = it.y - m * ncb;
   const size_t plane = (size_t)p * q;
   gfloat* Fm = gslot<gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex, interleaved
-  const gfloat* invden = as_global(S.invden);
+  const int d = S.d, cbb = S.fused ? cb / d : cb, qd = q / d;
+  // column of LDS line l (-1: past the image)
+  auto column = [&](int l) -> int {
+    if (!S.fused) {
+      const int col = cblk * cb + l;
+      return col < q ? col : -1;
+    }
+    const int bc = cblk * cbb + l % cbb;
+    return bc < qd ? bc + (l / cbb) * qd : -1;
+  };
   for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
-    const int i = e / cb, l = e - i * cb, col = c0 + l;
-    sh[l * p + i] = (col < q) ? ldg2(Fm + 2 * ((size_t)i * q + col)) : make_float2(0.f, 0.f);
+    const int i = e / cb, l = e - i * cb, col = column(l);
+    sh[l * p + i] = (col >= 0) ? ldg2(Fm + 2 * ((size_t)i * q + col)) : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const int G = blockDim.x / tpl;
   const int g = threadIdx.x / tpl;
   const int tl = threadIdx.x - g * tpl;
-  for (int base = 0; base < cb; base += G) {
-    const int l = base + g;
-    const bool act = (g < G) && (l < cb);
-    const int t = act ? tl : tpl;
-    float2* line = sh + (act ? l : 0) * p;
-    fft_line<false>(line, S.fp, t, tpl);
-    if (act && c0 + l < q) {
-      for (int i = tl; i < p; i += tpl) {
-        const float s = invden[(size_t)i * q + c0 + l];
-        line[i] = cscale(line[i], s);
+  if (!S.fused) {
+    const gfloat* invden = as_global(S.invden);
+    for (int base = 0; base < cb; base += G) {
+      const int l = base + g;
+      const bool act = (g < G) && (l < cb);
+      const int t = act ? tl : tpl;
+      float2* line = sh + (act ? l : 0) * p;
+      fft_line<false>(line, S.fp, t, tpl);
+      const int col = act ? column(l) : -1;
+      if (col >= 0) {
+        for (int i = tl; i < p; i += tpl) {
+          const float s = invden[(size_t)i * q + col];
+          line[i] = cscale(line[i], s);
+        }
+      }
+      __syncthreads();
+      fft_line<true>(line, S.fp, t, tpl);
+    }
+  } else {
+    for (int base = 0; base < cb; base += G) {
+      const int l = base + g;
+      const bool act = (g < G) && (l < cb);
+      fft_line<false>(sh + (act ? l : 0) * p, S.fp, act ? tl : tpl, tpl);
+    }
+    // group solves: (i1, base column) pairs, i1 fastest (tables are column-major)
+    const int pd = p / d;
+    const gfloat* ia = as_global(S.fia);
+    const gfloat* fu = (const gfloat*)S.fu;
+    const gfloat* fv = (const gfloat*)S.fv;
+    for (int e = threadIdx.x; e < pd * cbb; e += blockDim.x) {
+      const int bcl = e / pd, i1 = e - bcl * pd;
+      if (cblk * cbb + bcl >= qd) continue;
+      const int col0 = cblk * cbb + bcl;
+      float tr = 0.f, ti = 0.f;          // t = sum_k u_k c_k
+      for (int m2 = 0; m2 < d; ++m2) {
+        const size_t cbase = (size_t)(col0 + m2 * qd) * p;
+        const float2* ln = sh + (m2 * cbb + bcl) * p;
+        for (int m1 = 0; m1 < d; ++m1) {
+          const int i = i1 + m1 * pd;
+          const float2 u = ldg2(fu + 2 * (cbase + i)), c = ln[i];
+          tr += u.x * c.x - u.y * c.y;
+          ti += u.x * c.y + u.y * c.x;
+        }
+      }
+      for (int m2 = 0; m2 < d; ++m2) {
+        const size_t cbase = (size_t)(col0 + m2 * qd) * p;
+        float2* ln = sh + (m2 * cbb + bcl) * p;
+        for (int m1 = 0; m1 < d; ++m1) {
+          const int i = i1 + m1 * pd;
+          const float a = ia[cbase + i];
+          const float2 v = ldg2(fv + 2 * (cbase + i)), c = ln[i];
+          ln[i] = make_float2(a * c.x - (v.x * tr - v.y * ti), a * c.y - (v.x * ti + v.y * tr));
+        }
       }
     }
     __syncthreads();
-    fft_line<true>(line, S.fp, t, tpl);
+    for (int base = 0; base < cb; base += G) {
+      const int l = base + g;
+      const bool act = (g < G) && (l < cb);
+      fft_line<true>(sh + (act ? l : 0) * p, S.fp, act ? tl : tpl, tpl);
+    }
   }
   for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
-    const int i = e / cb, l = e - i * cb, col = c0 + l;
-    if (col < q) stg2(Fm + 2 * ((size_t)i * q + col), sh[l * p + i]);
+    const int i = e / cb, l = e - i * cb, col = column(l);
+    if (col >= 0) stg2(Fm + 2 * ((size_t)i * q + col), sh[l * p + i]);
   }
 }
 
 // Inverse DFT along rows, unpack bands (2m, 2m+1) into X.
 __global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
-                             int f_s, int x_s) {
+                             int f_s, int x_s, int add_s) {
   extern __shared__ float2 sh[];
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
@@ -245,24 +307,28 @@ __global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __res
   gfloat* X = gslot<gfloat>(S, x_s);
   gfloat* Xa = X + (size_t)(2 * m) * plane;
   gfloat* Xb = (2 * m + 1 < L) ? X + (size_t)(2 * m + 1) * plane : nullptr;
+  const gfloat* Ad = add_s < 0 ? nullptr : gslot<const gfloat>(S, add_s);
+  const gfloat* Aa = Ad ? Ad + (size_t)(2 * m) * plane : nullptr;
+  const gfloat* Ab = (Ad && Xb) ? Ad + (size_t)(2 * m + 1) * plane : nullptr;
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
     if (r < p) {
       const float2 v = sh[e];
-      Xa[(size_t)r * q + i] = v.x;
-      if (Xb) Xb[(size_t)r * q + i] = v.y;
+      const size_t o = (size_t)r * q + i;
+      Xa[o] = Aa ? v.x + Aa[o] : v.x;
+      if (Xb) Xb[o] = Ab ? v.y + Ab[o] : v.y;
     }
   }
 }
 
 constexpr size_t kFftLds = 65536;
 
-int launch_rows(const Batch& B, bool inv, int a, int b, hipStream_t s) {
+int launch_rows(const Batch& B, bool inv, int a, int b, int add, hipStream_t s) {
   for (const Group& g : B.groups[KD_ROWS]) {
     if (!g.nitems) continue;
     if (inv)
       hipLaunchKernelGGL(fft_rows_inv, dim3(g.nitems), dim3(g.block), g.lds, s, B.d_desc,
-                         g.d_items, a, b);
+                         g.d_items, a, b, add);
     else
       hipLaunchKernelGGL(fft_rows_fwd, dim3(g.nitems), dim3(g.block), g.lds, s, B.d_desc,
                          g.d_items, a, b);
@@ -298,22 +364,25 @@ int cols_blocks(const Plan& P) {
 size_t rows_lds(const Plan& P) { return (size_t)P.fft.q_lpb * P.prm.q * sizeof(float2); }
 size_t cols_lds(const Plan& P) { return (size_t)P.fft.p_cb * P.prm.p * sizeof(float2); }
 
-FftShape default_fft_shape(int p, int q) {
+// d_fused > 0: the columns per block must be a multiple of d (a base column and its aliases)
+FftShape default_fft_shape(int p, int q, int d_fused) {
   FftShape f{};
   f.q_tpl = ceil_div(q, 8);
   f.p_tpl = ceil_div(p, 8);
   f.q_lpb = fft_block(f.q_tpl) / f.q_tpl;
   while (f.q_lpb > 1 && (size_t)f.q_lpb * q * sizeof(float2) > kFftLds) --f.q_lpb;
-  f.p_cb = 16;
-  while (f.p_cb > 1 && (size_t)f.p_cb * p * sizeof(float2) > kFftLds) f.p_cb /= 2;
+  const int unit = d_fused > 0 ? d_fused : 1;
+  f.p_cb = unit;
+  while (f.p_cb * 2 <= std::max(16, unit) && (size_t)f.p_cb * 2 * p * sizeof(float2) <= kFftLds)
+    f.p_cb *= 2;
   return f;
 }
 
-int launch_xsolve(const Batch& B, int c, int x, int f, hipStream_t s) {
+int launch_xsolve(const Batch& B, int c, int x, int f, int add, hipStream_t s) {
   int rc;
-  if ((rc = launch_rows(B, false, c, f, s))) return rc;
+  if ((rc = launch_rows(B, false, c, f, -1, s))) return rc;
   if ((rc = launch_cols(B, f, s))) return rc;
-  return launch_rows(B, true, f, x, s);
+  return launch_rows(B, true, f, x, add, s);
 }
 
 // Autotuner: time the row and column passes of one band pair for every admissible lines-
@@ -321,11 +390,12 @@ int launch_xsolve(const Batch& B, int c, int x, int f, hipStream_t s) {
 // (device, p, q) for the life of the process.
 int autotune_fft(Plan& P) {
   static std::mutex mtx;
-  static std::map<std::tuple<int, int, int>, FftShape> cache;
+  static std::map<std::tuple<int, int, int, int>, FftShape> cache;
   const int p = P.prm.p, q = P.prm.q;
+  const int dfu = P.d_fia ? P.prm.d : 0;
   int dev = 0;
   NLPR_HIP_TRY(hipGetDevice(&dev));
-  const auto key = std::make_tuple(dev, p, q);
+  const auto key = std::make_tuple(dev, p, q, dfu);
   {
     std::lock_guard<std::mutex> lk(mtx);
     auto hit = cache.find(key);
@@ -334,7 +404,7 @@ int autotune_fft(Plan& P) {
       return NLPR_OK;
     }
   }
-  FftShape best = default_fft_shape(p, q);
+  FftShape best = default_fft_shape(p, q, dfu);
   const size_t plane = (size_t)p * q;
   // time on up to 16 band pairs so the launch fills the GPU like the real one
   const int tp = std::max(1, std::min((P.Lx + 1) / 2, 16));
@@ -373,6 +443,11 @@ int autotune_fft(Plan& P) {
   h.fp = P.fp;
   h.fq = P.fq;
   h.invden = P.d_invden;
+  h.d = P.prm.d;
+  h.fused = dfu > 0 ? 1 : 0;
+  h.fia = P.d_fia;
+  h.fu = P.d_fu;
+  h.fv = P.d_fv;
   h.buf[B_C] = d_real;
   h.buf[B_Z] = d_real;
   h.buf[B_F] = d_cplx;
@@ -401,7 +476,7 @@ int autotune_fft(Plan& P) {
         hipLaunchKernelGGL(fft_rows_fwd, dim3(nb), dim3(bs), lds, nullptr, d_sd, d_items, (int)B_C,
                            (int)B_F);
         hipLaunchKernelGGL(fft_rows_inv, dim3(nb), dim3(bs), lds, nullptr, d_sd, d_items, (int)B_F,
-                           (int)B_Z);
+                           (int)B_Z, -1);
       });
       if (hipGetLastError() != hipSuccess) { rc = NLPR_ERR_HIP; break; }
       if (ms < tbest) { tbest = ms; best.q_lpb = lpb; }
@@ -411,7 +486,7 @@ int autotune_fft(Plan& P) {
   if (rc == NLPR_OK) {
     const int tpl = best.p_tpl, bs = fft_block(tpl);
     float tbest = 1e30f;
-    for (int cb = 1; cb <= 32; cb *= 2) {
+    for (int cb = std::max(dfu, 1); cb <= std::max(32, dfu); cb *= 2) {
       if ((size_t)cb * p * sizeof(float2) > kFftLds) break;
       h.fp_tpl = tpl;
       h.fp_cb = cb;

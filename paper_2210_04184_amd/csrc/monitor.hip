@@ -68,9 +68,11 @@ monitor_pixel_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ 
     for (int c = 0; c < L; ++c) {
       const size_t o = (size_t)c * plane + j;
       const double x = X[o], bx = BX[o];
-      const double e1 = bx - ((double)W1[o] - (double)L1[o]);
       const double e2 = x - ((double)W2[o] - (double)L2[o]);
-      acc[2] += e1 * e1;
+      if (!S.fused) {                     // the fused-S splitting has no P1 = B X constraint
+        const double e1 = bx - ((double)W1[o] - (double)L1[o]);
+        acc[2] += e1 * e1;
+      }
       acc[3] += e2 * e2;
 #pragma unroll
       for (int h = 0; h < kMaxLh; ++h)

@@ -55,6 +55,7 @@ struct SceneDesc {
   int fp_tpl, fp_cb;               // column FFT: threads per line, columns per block
   int init_zero, unweighted;
   int subspace, Lz;                // basis in use; bands of Z (L is the number of X bands)
+  int fused;                       // S inside the X-system (no P1)
   float rho, inv_1prho, mu_scale, inv_h2;
   LineFFT fp, fq;
   const int2* taus;
@@ -65,6 +66,10 @@ struct SceneDesc {
   const float* E;                  // [Ls][Lz]
   const float* Ep;                 // E^+ = E^T (E E^T)^{-1}, [Lz][Ls]
   const float* M;                  // (E E^T + rho I)^{-1}, [Ls][Ls]
+  // fused-S X-update tables, column-major [q][p]: 1/(a p q), b^/a, gamma conj(b^)/(a p q)
+  const float* fia;
+  const float2* fu;
+  const float2* fv;
   // monitor: partial sums [mon_npix][4] (data_l, data_h, r1^2, r2^2 per pixel block), then
   // [mon_nreg] (regulariser per (shift, tile) block), then the trace [points][8]
   double* mon;
@@ -108,6 +113,9 @@ struct Plan {
   float* d_M = nullptr;           // [Ls][Ls]
   float* d_Rt = nullptr;          // E R, [Ls][Lh]
   double* d_mon = nullptr;        // monitor partials and trace (monitor_every > 0)
+  float* d_fia = nullptr;         // fused-S tables (NLPR_FUSED_S)
+  float2* d_fu = nullptr;
+  float2* d_fv = nullptr;
   int mon_points = 0;             // records per solve
   SweepShape sweep{};
   // workspace layout relative to the scene's base
@@ -263,7 +271,9 @@ int monitor_points(int iters, int every);
 int launch_monitor(const Batch& B, int point, int iter, hipStream_t s);
 int launch_finite(const Batch& B, int z, int* flag, hipStream_t s);
 int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] slot
-int launch_xsolve(const Batch& B, int c, int x, int f, hipStream_t s);
+int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s);   // S^T Y_l / rho
+// X = solve(C) (+ add, a [L][p][q] slot, when add >= 0); the fused-S system for fused scenes
+int launch_xsolve(const Batch& B, int c, int x, int f, int add, hipStream_t s);
 int launch_sweep(const Batch& B, int x, int mu, int sigma, int creg, int halo, bool first,
                  hipStream_t s);
 int sweep_prepare(int K, int items);   // kernel attributes; call before launches or capture
@@ -272,7 +282,7 @@ int sweep_prepare(int K, int items);   // kernel attributes; call before launche
 SweepShape choose_sweep_shape(int p, int q, int K, int halo);
 size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npatch);
 int fft_block(int tpl);             // workgroup size of a line FFT with tpl threads per line
-FftShape default_fft_shape(int p, int q);
-int autotune_fft(Plan& P);          // picks P.fft by timing candidates (cached per (p, q))
+int autotune_fft(Plan& P);          // picks P.fft by timing candidates (cached per (p, q, d if fused))
+FftShape default_fft_shape(int p, int q, int d_fused);
 
 }  // namespace nlpr

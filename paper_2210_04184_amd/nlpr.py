@@ -31,6 +31,7 @@ LOCAL_WINDOW = 1 << 3
 CHECK_FINITE = 1 << 4
 TIMING = 1 << 5
 GRAPH = 1 << 6
+FUSED_S = 1 << 7
 
 STAGE_WEIGHTS = 1
 STAGE_XSOLVE = 2
