@@ -288,6 +288,37 @@ enum {
 int nlpr_monitor(const nlpr_plan* plan, double* trace, int32_t cap, int32_t* n);
 
 /*
+ * Reverse mode (the differentiated form): the gradient of a loss of Z = X^(iters) with
+ * respect to Y_l, Y_h, lambda_2 and rho, through every unrolled iteration of the paper's
+ * splitting (Sec. "Optimization": eqs. (inv), (Qh_update), (Qm_update), (Qj_main),
+ * (dualvar1_main) - (dualvar3_main)), the default start and the guide weights of eq. (wts)
+ * (Y_h reaches Z both through Y_h R^T and through the weights).  The derivative of the
+ * soft threshold is taken as 1 where |V| > mu and 0 elsewhere (its value at |V| = mu is
+ * immaterial for almost every input).  Plans with E = I, the paper's splitting (no
+ * NLPR_FUSED_S), without NLPR_STATE_IN, iters >= 1, and (with a search window) q <= 1024
+ * with the sweep adjoint's LDS tile within 160 KiB; else NLPR_ERR_UNSUPPORTED_SHAPE or
+ * NLPR_ERR_INVALID_ARG.
+ *
+ * nlpr_grad_sizes: bytes of the checkpoint buffer (for t = 0 .. iters-1 the state entering
+ *   iteration t+1: C, Lambda1, Lambda2 and, for t >= 1, Sigma') and of the gradient
+ *   workspace.  Checkpoints take about iters * (3 + 2 Npairs |P|) * 4 * L * p * q bytes.
+ * nlpr_forward: like nlpr_solve (Z equal bit for bit) and also writes the checkpoints to ck
+ *   (device, 256-byte aligned).  ws as for nlpr_solve.
+ * nlpr_backward: given dZ = dloss/dZ (device, [L][p][q]), recomputes each iteration's X and
+ *   B X from its checkpoint and carries the adjoints back; writes dYl ([L][p/d][q/d]),
+ *   dYh ([Lh][p][q]) and dscal (device, 2 doubles: dloss/dlambda_2, dloss/drho).  ws, ck
+ *   from the matching nlpr_forward (same Yl, Yh); gws: gradient workspace (device,
+ *   256-byte aligned).  Never allocates; asynchronous on `stream`; sums run in a fixed
+ *   order, so gradients repeat bit for bit.
+ */
+int nlpr_grad_sizes(const nlpr_plan* plan, size_t* ck_bytes, size_t* gws_bytes);
+int nlpr_forward(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void* ws,
+                 size_t ws_bytes, void* ck, size_t ck_bytes, void* stream);
+int nlpr_backward(nlpr_plan* plan, const float* Yl, const float* Yh, const float* dZ, void* ws,
+                  size_t ws_bytes, void* ck, size_t ck_bytes, void* gws, size_t gws_bytes,
+                  float* dYl, float* dYh, double* dscal, void* stream);
+
+/*
  * Batches: many independent scenes solved together (the multi-scene workload).  Every stage
  * of the iteration is one kernel launch over all scenes: a table of (scene, block) work
  * items maps each workgroup to a scene, whose sizes, tables and buffers a device

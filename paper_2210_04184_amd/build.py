@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnlpr.so")
-SOURCES = ["api.hip", "dense.hip", "fft.hip", "monitor.hip", "sweep.hip"]
+SOURCES = ["adjoint.hip", "api.hip", "dense.hip", "fft.hip", "monitor.hip", "sweep.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions stay off: only ordinary scalar float code is emitted.

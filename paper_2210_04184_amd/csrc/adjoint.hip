@@ -1,0 +1,675 @@
+// Reverse mode of the unrolled ADMM: kernels that carry adjoints (written v') back through
+// one iteration of Sec. "Optimization" (paper's splitting, E = I), and through the guide
+// weights and the start.  The iteration, in the form the forward kernels compute it:
+//   X   = solve(C)                                        (self-adjoint: C' = solve(X'))
+//   BX  = B X
+//   P1  = M (rho BX + S^T Y_l - rho L1) / (1 + rho) + (1 - M)(BX - L1)   eq. (Qh_update)
+//   P2  = A0 + (Y_h - A0 R) G R^T,  A0 = X - L2,  G = (rho/lambda1 I + R^T R)^{-1}
+//   L1+ = L1 - (BX - P1),  L2+ = L2 - (X - P2),  W1 = P1 + L1+,  W2 = P2 + L2+
+//   per tau in W+, k in P (reduced sweep):  V = g_tau(j) - Sigma'(j),  c = clip(V, +-mu(j+k)),
+//     Sigma'+ = -c,  A_tau(j) += V - 2c,  g_tau = X - X(. - tau)
+//   C+  = B^T W1 + W2 + 2 sum_tau [A_tau(j) - A_tau(j + tau)]
+// The derivative of clip is 1 inside (|V| < mu) and 0 outside, where clip = +-mu moves with
+// mu instead.  All sums run in a fixed order (no atomics): gradients repeat bit for bit.
+#include "nlpr_internal.h"
+
+namespace nlpr {
+namespace {
+
+constexpr int PADW = 4;   // LDS column padding of the mu tiles (K <= 4), as in the sweep
+
+__device__ __forceinline__ int wrapg(int a, int m) {
+  a %= m;
+  return a < 0 ? a + m : a;
+}
+__device__ __forceinline__ float4 ld4_nt(const gfloat* p) {
+  const v4f_t v = __builtin_nontemporal_load((const gv4f*)p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4_nt(gfloat* p, float4 v) {
+  v4f_t w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, (gv4f*)p);
+}
+
+template <int N>
+__device__ __forceinline__ void block_sum256(double (&v)[N]) {
+  __shared__ double red[N][4];
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[k][w] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------ sweep adjoint
+// Per workgroup (tile, band) as the forward sweep, one float4 item per thread.  Inputs: X,
+// mu, Sigma' before the forward sweep (sig_in, tile-major; absent for the first sweep,
+// where it is 0), C' (adjoint of the right-hand side the sweep fed), Sigma'' (adjoint of
+// the sweep's Sigma' output, updated in place to the adjoint of its input).  Outputs: X'
+// of the sweep (xr, plus the rows above the tile in the halo buffer, folded like the
+// forward's), and mu' accumulated into per-(band, tile) partial tiles covering the rows
+// r0 - K .. r0 + R + K - 1 (mup), reduced over bands and tiles by mubar_reduce_kernel.
+//   A'(j) = 2 (C'(j) - C'(j - tau));  per k: c' = -Sigma''(j) - 2 A'(j);
+//   V' = A'(j) + [|V| < mu] c';  mu'(j + k) += [|V| >= mu] sign(V) c';  Sigma''(j) := -V';
+//   g'(j) = sum_k V';  X'(j) += g'(j),  X'(j - tau) -= g'(j).
+template <int K, bool FIRST>
+__global__ void __launch_bounds__(256)
+sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
+                 int mu_s, int cb_s, const float* sig_in, int sb_s, int xr_s, int halo_s,
+                 int mup_s) {
+  constexpr int NT = 256;
+  constexpr int KW = 2 * K + 1;
+  constexpr int NP = KW * KW;
+  const int2 it_ = items[blockIdx.x];
+  const SceneDesc& S = sd[it_.x];
+  const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
+            H = S.halo;
+  const gfloat* X = gslot<const gfloat>(S, x_s);
+  const gfloat* mu = gslot<const gfloat>(S, mu_s);
+  const gfloat* Cb = gslot<const gfloat>(S, cb_s);
+  const gfloat* sgin = FIRST ? nullptr : as_global(sig_in);
+  gfloat* sb = gslot<gfloat>(S, sb_s);
+  gfloat* mup = gslot<gfloat>(S, mup_s);
+  extern __shared__ float4 lds4[];
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int q4 = q >> 2;
+  const int ms = q + 2 * PADW;
+  const int ER = R + 2 * K;               // extended rows of the mu tiles
+  float* Ms = lds;                        // ER x ms   mu(., tau)
+  float* Mb = Ms + ER * ms;               // ER x ms   mu' accumulator
+  float* Xs = Mb + ER * ms;               // (R + H) x q
+  float* Cs = Xs + (R + H) * q;           // (R + H) x q   C'
+  float* As = Cs + (R + H) * q;           // (R + H) x q   X' accumulator
+
+  const int tile = it_.y / L;
+  const int c = it_.y - tile * L;
+  const int r0 = tile * R;
+  const int rows = min(R, p - r0);
+  const size_t plane = (size_t)p * q;
+  const gfloat* Xc = X + (size_t)c * plane;
+  const gfloat* Cc = Cb + (size_t)c * plane;
+  for (int e = threadIdx.x; e < (R + H) * q4; e += NT) {
+    const int rr = e / q4, c4 = e - rr * q4;
+    const int gr = wrapg(r0 - H + rr, p);
+    reinterpret_cast<float4*>(Xs)[e] = ldg4(Xc + (size_t)gr * q + 4 * c4);
+    reinterpret_cast<float4*>(Cs)[e] = ldg4(Cc + (size_t)gr * q + 4 * c4);
+    reinterpret_cast<float4*>(As)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+
+  const int row = threadIdx.x / q4;
+  const int col = (threadIdx.x - row * q4) * 4;
+  const bool ok = row < rows;
+  const float4 xv = ok ? *reinterpret_cast<const float4*>(Xs + (row + H) * q + col)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 cv = ok ? *reinterpret_cast<const float4*>(Cs + (row + H) * q + col)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 cp = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  const size_t kstride = (size_t)R * q;
+  const size_t tstride = (size_t)NP * kstride;
+  const size_t tile_off = ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
+  gfloat* mup_tile = mup + ((size_t)c * ntiles + tile) * (size_t)npairs * ER * q;
+
+  for (int n = 0; n < npairs; ++n) {
+    const int2 t = tau_at(S, n);
+    __syncthreads();
+    {
+      const gfloat* mun = mu + (size_t)n * plane;
+      const int ms4 = ms >> 2;
+      for (int e = threadIdx.x; e < ER * ms4; e += NT) {
+        const int rr = e / ms4, c4 = e - rr * ms4 - 1;
+        const int gr = wrapg(r0 - K + rr, p);
+        const int gc4 = c4 < 0 ? c4 + q4 : (c4 >= q4 ? c4 - q4 : c4);
+        reinterpret_cast<float4*>(Ms)[e] = ldg4(mun + (size_t)gr * q + 4 * gc4);
+        reinterpret_cast<float4*>(Mb)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    // g and A' at the item's four pixels
+    float gg[4], ab[4], gb[4] = {0.f, 0.f, 0.f, 0.f};
+    {
+      const float* xr = Xs + (row + H - t.x) * q;
+      const float* cr = Cs + (row + H - t.x) * q;
+      const float xa[4] = {xv.x, xv.y, xv.z, xv.w};
+      const float ca[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int cc = col + e - t.y;
+        cc = cc < 0 ? cc + q : (cc >= q ? cc - q : cc);
+        gg[e] = ok ? xa[e] - xr[cc] : 0.f;
+        ab[e] = ok ? 2.f * (ca[e] - cr[cc]) : 0.f;
+      }
+    }
+    const size_t n_off = tile_off + (size_t)n * tstride;
+#pragma unroll
+    for (int k1 = -K; k1 <= K; ++k1) {
+      float mw[12];
+      {
+        const float4* mr = reinterpret_cast<const float4*>(Ms + (row + K + k1) * ms + col);
+        const float4 a = mr[0], b = mr[1], d = mr[2];
+        mw[0] = a.x; mw[1] = a.y; mw[2] = a.z; mw[3] = a.w;
+        mw[4] = b.x; mw[5] = b.y; mw[6] = b.z; mw[7] = b.w;
+        mw[8] = d.x; mw[9] = d.y; mw[10] = d.z; mw[11] = d.w;
+      }
+      float4 sv[KW], sbv[KW];
+#pragma unroll
+      for (int k2 = 0; k2 < KW; ++k2) {
+        const size_t off = n_off + (size_t)((k1 + K) * KW + k2) * kstride + (size_t)row * q + col;
+        sv[k2] = (FIRST || !ok) ? make_float4(0.f, 0.f, 0.f, 0.f) : ld4_nt(sgin + off);
+        sbv[k2] = ok ? ld4_nt(sb + off) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < KW; ++k2) {
+        const int o = 4 + (k2 - K);
+        const float s4[4] = {sv[k2].x, sv[k2].y, sv[k2].z, sv[k2].w};
+        const float b4[4] = {sbv[k2].x, sbv[k2].y, sbv[k2].z, sbv[k2].w};
+        float vb[4], mb[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float V = gg[e] - s4[e];
+          const float m = mw[o + e];
+          const float cbar = -b4[e] - 2.f * ab[e];
+          const bool inside = fabsf(V) < m;
+          vb[e] = ab[e] + (inside ? cbar : 0.f);
+          mb[e] = inside ? 0.f : (V > 0.f ? cbar : (V < 0.f ? -cbar : 0.f));
+          gb[e] += vb[e];
+        }
+        if (ok) {
+          const size_t off = n_off + (size_t)((k1 + K) * KW + k2) * kstride + (size_t)row * q + col;
+          st4_nt(sb + off, make_float4(-vb[0], -vb[1], -vb[2], -vb[3]));
+          float* mrow = Mb + (row + K + k1) * ms + col + o;   // mu' at (row + k1, col + k2 - K + e)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) mrow[e] += mb[e];
+        }
+        __syncthreads();   // j -> j + k is one-to-one for a fixed k; k's overlap
+      }
+    }
+    if (ok) {
+      cp.x += gb[0]; cp.y += gb[1]; cp.z += gb[2]; cp.w += gb[3];
+      float* ar = As + (row + H - t.x) * q;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int cc = col + e - t.y;
+        cc = cc < 0 ? cc + q : (cc >= q ? cc - q : cc);
+        ar[cc] -= gb[e];
+      }
+    }
+    __syncthreads();
+    // fold the padded columns into their wrapped positions and accumulate the partial tile
+    gfloat* mpn = mup_tile + (size_t)n * ER * q;
+    for (int e = threadIdx.x; e < ER * q; e += NT) {
+      const int rr = e / q, cc = e - rr * q;
+      const float* mrow = Mb + rr * ms + PADW;
+      float v = mrow[cc];
+      if (cc < PADW) v += mrow[q + cc];            // columns q .. q + PADW - 1
+      if (cc >= q - PADW) v += mrow[cc - q];       // columns -PADW .. -1
+      mpn[e] += v;
+    }
+  }
+  __syncthreads();
+  gfloat* xro = gslot<gfloat>(S, xr_s) + (size_t)c * plane + (size_t)r0 * q;
+  if (ok) {
+    const float4 acc = *reinterpret_cast<const float4*>(As + (row + H) * q + col);
+    stg4(xro + (size_t)row * q + col,
+         make_float4(cp.x + acc.x, cp.y + acc.y, cp.z + acc.z, cp.w + acc.w));
+  }
+  if (H > 0) {
+    gfloat* hb = gslot<gfloat>(S, halo_s) + ((size_t)c * ntiles + tile) * H * q;
+    for (int e = threadIdx.x; e < H * q4; e += NT)
+      stg4(hb + 4 * e, reinterpret_cast<const float4*>(As)[e]);
+  }
+}
+
+// mu'(tau, i) = sum over bands and over the tiles whose extended rows cover image row i of
+// the partial tiles.  One thread per (tau, pixel).
+__global__ void __launch_bounds__(256)
+mubar_reduce_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int mup_s,
+                    int mub_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, R = S.rows, ntiles = S.ntiles, ER = S.rows + 2 * S.K;
+  const size_t plane = (size_t)p * q;
+  const size_t e = (size_t)it.y * 256 + threadIdx.x;
+  if (e >= (size_t)S.npairs * plane) return;
+  const int n = (int)(e / plane);
+  const int rem = (int)(e - (size_t)n * plane);
+  const int i = rem / q, col = rem - (rem / q) * q;
+  const gfloat* mup = gslot<const gfloat>(S, mup_s);
+  float acc = 0.f;
+  for (int c = 0; c < S.L; ++c)
+    for (int tl = 0; tl < ntiles; ++tl) {
+      // extended row er of tile tl is image row (tl R - K + er) mod p
+      for (int er = wrapg(i - tl * R + S.K, p); er < ER; er += p)
+        acc += mup[((((size_t)c * ntiles + tl) * S.npairs + n) * ER + er) * q + col];
+    }
+  gslot<gfloat>(S, mub_s)[e] = acc;
+}
+
+// ----------------------------------------------------------------------- P-update adjoint
+// One thread per pixel.  Inputs: X, BX of the iteration, Y_l, Y_h, Lambda1 and Lambda2
+// before the update; adjoints W1' (= B C'), W2' (= C'), Lambda1'', Lambda2'' of the
+// outputs.  Outputs: BX', X' of this step, Lambda'' of the inputs (in place), Y_l' and Y_h'
+// accumulated, and per workgroup two FP64 partial sums of rho', added to the workgroup's
+// own slot (repeatable across iterations): through P1, and through G, where
+// G' = sum res s^T and dG/drho = -G G / lambda1 give -res^T G (G s) / lambda1 per pixel.
+template <int LHM>
+__global__ void __launch_bounds__(256)
+pupdate_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
+                   int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1b_s, int w2b_s,
+                   int l1b_s, int l2b_s, int bxb_s, int xp_s, int gyl_s, int gyh_s, int part_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, L = S.L, Lh = S.Lh, d = S.d;
+  const size_t plane = (size_t)p * q;
+  const int j = it.y * 256 + threadIdx.x;
+  const bool act = j < (int)plane;
+  double acc[2] = {0.0, 0.0};
+  if (act) {
+    const gfloat* X = gslot<const gfloat>(S, x_s);
+    const gfloat* BX = gslot<const gfloat>(S, bx_s);
+    const gfloat* Yl = gslot<const gfloat>(S, yl_s);
+    const gfloat* Yh = gslot<const gfloat>(S, yh_s);
+    const gfloat* L1 = gslot<const gfloat>(S, l1_s);
+    const gfloat* L2 = gslot<const gfloat>(S, l2_s);
+    const gfloat* W1b = gslot<const gfloat>(S, w1b_s);
+    const gfloat* W2b = gslot<const gfloat>(S, w2b_s);
+    gfloat* L1b = gslot<gfloat>(S, l1b_s);
+    gfloat* L2b = gslot<gfloat>(S, l2b_s);
+    gfloat* BXb = gslot<gfloat>(S, bxb_s);
+    gfloat* Xp = gslot<gfloat>(S, xp_s);
+    gfloat* GYl = gslot<gfloat>(S, gyl_s);
+    gfloat* GYh = gslot<gfloat>(S, gyh_s);
+    const gfloat* R = as_global(S.R);
+    const gfloat* G = as_global(S.G);
+    const float rho = S.rho, inv = S.inv_1prho, rr = S.rho * S.inv_1prho;
+    const int i1 = j / q, i2 = j - (j / q) * q;
+    const bool sampled = (i1 % d == 0) && (i2 % d == 0);
+    const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
+    const size_t lplane = (size_t)(p / d) * (q / d);
+    float res[LHM], sv[LHM], v[LHM];
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) {
+      res[h] = (h < Lh) ? Yh[h * plane + j] : 0.f;
+      sv[h] = 0.f;
+    }
+    for (int c = 0; c < L; ++c) {      // res = Y_h - A0 R,  s = P2' R
+      const size_t o = (size_t)c * plane + j;
+      const float a0 = X[o] - L2[o];
+      const float p2b = 2.f * W2b[o] + L2b[o];
+#pragma unroll
+      for (int h = 0; h < LHM; ++h)
+        if (h < Lh) {
+          res[h] -= a0 * R[c * Lh + h];
+          sv[h] += p2b * R[c * Lh + h];
+        }
+    }
+#pragma unroll
+    for (int h2 = 0; h2 < LHM; ++h2) {  // v = s G  (G symmetric);  Y_h' += v;  G' += res s^T
+      float t = 0.f;
+#pragma unroll
+      for (int h = 0; h < LHM; ++h)
+        if (h < Lh && h2 < Lh) t += sv[h] * G[h * Lh + h2];
+      v[h2] = t;
+      if (h2 < Lh) GYh[h2 * plane + j] += t;
+    }
+    float rg = 0.f;                     // res^T G v, v = G s
+#pragma unroll
+    for (int h2 = 0; h2 < LHM; ++h2) {
+      float w = 0.f;
+#pragma unroll
+      for (int h = 0; h < LHM; ++h)
+        if (h < Lh && h2 < Lh) w += v[h] * G[h * Lh + h2];
+      rg += res[h2] * w;
+    }
+    acc[1] = -(double)rg / S.lam1_d;
+    for (int c = 0; c < L; ++c) {
+      const size_t o = (size_t)c * plane + j;
+      float corr = 0.f;
+#pragma unroll
+      for (int h = 0; h < LHM; ++h)
+        if (h < Lh) corr += v[h] * R[c * Lh + h];
+      const float w2b = W2b[o], l2b = L2b[o];
+      const float a0b = (2.f * w2b + l2b) - corr;           // A0' = P2' - P2' R G R^T
+      Xp[o] = -w2b - l2b + a0b;
+      L2b[o] = w2b + l2b - a0b;
+      const float w1b = W1b[o], l1b = L1b[o];
+      if (sampled) {
+        const float p1b = 2.f * w1b + l1b;
+        const float y = Yl[c * lplane + lj];
+        BXb[o] = -w1b - l1b + p1b * rr;
+        L1b[o] = w1b + l1b - p1b * rr;
+        GYl[c * lplane + lj] += p1b * inv;
+        acc[0] += (double)p1b * ((double)BX[o] - (double)L1[o] - (double)y) * (double)inv *
+                  (double)inv;
+      } else {
+        BXb[o] = w1b;
+        L1b[o] = -w1b;
+      }
+    }
+    (void)rho;
+  }
+  block_sum256(acc);
+  if (threadIdx.x == 0) {
+    gdouble* part = gslot<gdouble>(S, part_s) + 2 * (size_t)it.y;
+    part[0] += acc[0];
+    part[1] += acc[1];
+  }
+}
+
+// ------------------------------------------------------------------ weights adjoint
+// mu = (lambda/rho) omega,  omega(i) = exp(-Bx(e)(i) / h^2),  Bx = box sum over P,
+// e_tau(j) = sum_c (Y_h(j) - Y_h(j - tau))^2.  Per (shift, 16 x 64 tile): recompute e on the
+// tile plus a 2K halo and omega on the tile plus a K halo, form
+// Bx(e)'(i) = -mu'(i) (lambda/rho) omega(i) / h^2 there, and box-sum it back (the box is
+// symmetric) into e'_tau on the tile.  FP64 partials of lambda' = sum mu' omega / rho and of
+// the thresholds' share of rho' = -sum mu' lambda omega / rho^2, over the tile.
+constexpr int WB_Y = 16, WB_X = 64;
+__global__ void __launch_bounds__(256)
+weights_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yh_s,
+                   int mub_s, int eb_s, int part_s, int w0) {
+  extern __shared__ float wsh[];
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, K = S.K, Lh = S.Lh;
+  const int gx = ceil_div(q, WB_X), gy = ceil_div(p, WB_Y);
+  const int n = it.y / (gx * gy);
+  const int rem = it.y - n * gx * gy;
+  const int y0 = (rem / gx) * WB_Y, x0 = (rem % gx) * WB_X;
+  const int2 t = tau_at(S, n);
+  const size_t plane = (size_t)p * q;
+  const int E2Y = WB_Y + 4 * K, E2X = WB_X + 4 * K;    // e on the tile + 2K
+  const int E1Y = WB_Y + 2 * K, E1X = WB_X + 2 * K;    // omega, Bx(e)' on the tile + K
+  float* e2 = wsh;                    // E2Y x E2X
+  float* hs = e2 + E2Y * E2X;         // E2Y x E1X   row box sums, then reused
+  float* ob = hs + E2Y * E1X;         // E1Y x E1X   Bx(e)'
+  const gfloat* Yh = gslot<const gfloat>(S, yh_s);
+  const gfloat* mub = gslot<const gfloat>(S, mub_s) + (size_t)n * plane;
+  gfloat* eb = gslot<gfloat>(S, eb_s) + (size_t)n * plane;
+  const double lam = S.lam_d, rho = S.rho_d;
+  double acc[2] = {0.0, 0.0};
+  if (S.unweighted) {
+    for (int idx = threadIdx.x; idx < WB_Y * WB_X; idx += blockDim.x) {
+      const int y = y0 + idx / WB_X, x = x0 + idx % WB_X;
+      if (y < p && x < q) {
+        const double m = mub[(size_t)y * q + x];
+        acc[0] += m / rho;
+        acc[1] -= m * lam / (rho * rho);
+        eb[(size_t)y * q + x] = 0.f;
+      }
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < E2Y * E2X; idx += blockDim.x) {
+      const int yy = idx / E2X, xx = idx % E2X;
+      const int gyy = wrapg(y0 - 2 * K + yy, p), gxx = wrapg(x0 - 2 * K + xx, q);
+      const int sy = wrapg(gyy - t.x, p), sx = wrapg(gxx - t.y, q);
+      float a = 0.f;
+      for (int c = 0; c < Lh; ++c) {
+        const float dl = Yh[c * plane + (size_t)gyy * q + gxx] - Yh[c * plane + (size_t)sy * q + sx];
+        a += dl * dl;
+      }
+      e2[idx] = a;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < E2Y * E1X; idx += blockDim.x) {
+      const int yy = idx / E1X, x = idx % E1X;
+      float a = 0.f;
+      for (int dx = 0; dx <= 2 * K; ++dx) a += e2[yy * E2X + x + dx];
+      hs[idx] = a;
+    }
+    __syncthreads();
+    const float ih2 = S.inv_h2;
+    for (int idx = threadIdx.x; idx < E1Y * E1X; idx += blockDim.x) {
+      const int yy = idx / E1X, xx = idx % E1X;
+      float bxe = 0.f;
+      for (int dy = 0; dy <= 2 * K; ++dy) bxe += hs[(yy + dy) * E1X + xx];
+      const float om = expf(-bxe * ih2);
+      const int gyy = wrapg(y0 - K + yy, p), gxx = wrapg(x0 - K + xx, q);
+      const float m = mub[(size_t)gyy * q + gxx];
+      ob[idx] = -m * S.mu_scale * om * ih2;
+      const bool inside = yy >= K && yy < K + WB_Y && xx >= K && xx < K + WB_X &&
+                          y0 - K + yy < p && x0 - K + xx < q;
+      if (inside) {
+        acc[0] += (double)m * (double)om / rho;
+        acc[1] -= (double)m * lam * (double)om / (rho * rho);
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < E1Y * WB_X; idx += blockDim.x) {   // rows of the box
+      const int yy = idx / WB_X, x = idx % WB_X;
+      float a = 0.f;
+      for (int dx = 0; dx <= 2 * K; ++dx) a += ob[yy * E1X + x + dx];
+      hs[idx] = a;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < WB_Y * WB_X; idx += blockDim.x) {
+      const int y = idx / WB_X, x = idx % WB_X;
+      float a = 0.f;
+      for (int dy = 0; dy <= 2 * K; ++dy) a += hs[(y + dy) * WB_X + x];
+      if (y0 + y < p && x0 + x < q) eb[(size_t)(y0 + y) * q + x0 + x] = a;
+    }
+  }
+  block_sum256(acc);
+  if (threadIdx.x == 0) {
+    gdouble* part = gslot<gdouble>(S, part_s) + w0 + 2 * (size_t)it.y;
+    part[0] = acc[0];
+    part[1] = acc[1];
+  }
+}
+
+// Y_h'(c, i) += sum_tau 2 [e'_tau(i) (Y(i) - Y(i - tau)) - e'_tau(i + tau) (Y(i + tau) - Y(i))].
+__global__ void __launch_bounds__(256)
+yh_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int yh_s,
+              int eb_s, int gyh_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q;
+  const size_t plane = (size_t)p * q;
+  const int j = it.y * 256 + threadIdx.x;
+  if (j >= (int)plane || S.unweighted) return;
+  const int i1 = j / q, i2 = j - (j / q) * q;
+  const gfloat* Yh = gslot<const gfloat>(S, yh_s);
+  const gfloat* eb = gslot<const gfloat>(S, eb_s);
+  gfloat* gyh = gslot<gfloat>(S, gyh_s);
+  for (int c = 0; c < S.Lh; ++c) {
+    const gfloat* Y = Yh + (size_t)c * plane;
+    const float y = Y[j];
+    float a = 0.f;
+    for (int n = 0; n < S.npairs; ++n) {
+      const int2 t = tau_at(S, n);
+      const size_t jm = (size_t)wrapg(i1 - t.x, p) * q + wrapg(i2 - t.y, q);
+      const size_t jp = (size_t)wrapg(i1 + t.x, p) * q + wrapg(i2 + t.y, q);
+      a += eb[(size_t)n * plane + j] * (y - Y[jm]) - eb[(size_t)n * plane + jp] * (Y[jp] - y);
+    }
+    gyh[(size_t)c * plane + j] += 2.f * a;
+  }
+}
+
+// Y_l'(c, m) += sum of X0' over the d x d block of m (adjoint of the nearest-neighbour start).
+__global__ void __launch_bounds__(256)
+upsample_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x0b_s,
+                    int gyl_s) {
+  const int2 it = items[blockIdx.x];
+  const SceneDesc& S = sd[it.x];
+  const int p = S.p, q = S.q, d = S.d, pd = S.p / S.d, qd = S.q / S.d;
+  const size_t e = (size_t)it.y * 256 + threadIdx.x;
+  if (e >= (size_t)S.L * pd * qd) return;
+  const int c = (int)(e / ((size_t)pd * qd));
+  const int rem = (int)(e - (size_t)c * pd * qd);
+  const int m1 = rem / qd, m2 = rem - (rem / qd) * qd;
+  const gfloat* xb = gslot<const gfloat>(S, x0b_s) + (size_t)c * p * q;
+  float a = 0.f;
+  for (int u = 0; u < d; ++u)
+    for (int v = 0; v < d; ++v) a += xb[(size_t)(m1 * d + u) * q + m2 * d + v];
+  gslot<gfloat>(S, gyl_s)[e] += a;
+}
+
+// lambda' and rho' from the partial sums (one workgroup, fixed order): the pixel blocks'
+// [rho' through P1, rho' through G] pairs, then the weight blocks' [lambda', rho' through
+// the thresholds] pairs from offset 2 npix.
+__global__ void __launch_bounds__(256)
+grad_scalars_kernel(const SceneDesc* __restrict__ sd, int part_s, int npix, int nw,
+                    double* out) {
+  const SceneDesc& S = sd[0];
+  const gdouble* part = gslot<const gdouble>(S, part_s);
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < npix; b += 256) v[1] += part[2 * (size_t)b] + part[2 * (size_t)b + 1];
+  for (int b = threadIdx.x; b < nw; b += 256) {
+    v[0] += part[2 * (size_t)npix + 2 * (size_t)b];
+    v[1] += part[2 * (size_t)npix + 2 * (size_t)b + 1];
+  }
+  block_sum256(v);
+  if (threadIdx.x == 0) {
+    out[0] = v[0];
+    out[1] = v[1];
+  }
+}
+
+template <typename Kern, typename... Args>
+int launch_kind(const Batch& B, Kind kind, const char* name, Kern kern, hipStream_t s,
+                Args... args) {
+  for (const Group& g : B.groups[kind]) {
+    if (g.nitems == 0) continue;
+    hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(256), g.lds, s, B.d_desc, g.d_items, args...);
+    NLPR_LAUNCH_CHECK(name);
+  }
+  return NLPR_OK;
+}
+
+template <int K, bool FIRST>
+int launch_sbwd(const Batch& B, const Group& g, size_t lds, int x, int mu, int cb,
+                const float* sig_in, int sb, int xr, int halo, int mup, hipStream_t s) {
+  auto kern = sweep_bwd_kernel<K, FIRST>;
+  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(256), lds, s, B.d_desc, g.d_items, x, mu, cb,
+                     sig_in, sb, xr, halo, mup);
+  NLPR_LAUNCH_CHECK("sweep_bwd_kernel");
+  return NLPR_OK;
+}
+
+template <int K>
+int sbwd_attr() {
+  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K, true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
+  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K, false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
+  return NLPR_OK;
+}
+
+}  // namespace
+
+size_t sweep_bwd_lds(const Plan& P) {
+  const int R = P.sweep.rows, H = P.sweep.halo, K = P.prm.K, q = P.prm.q;
+  return (size_t)(2 * (R + 2 * K) * (q + 2 * PADW) + 3 * (R + H) * q) * sizeof(float);
+}
+size_t weights_bwd_lds(const Plan& P) {
+  const int K = P.prm.K;
+  const size_t e2 = (size_t)(WB_Y + 4 * K) * (WB_X + 4 * K);
+  const size_t hs = (size_t)(WB_Y + 4 * K) * (WB_X + 2 * K);
+  const size_t ob = (size_t)(WB_Y + 2 * K) * (WB_X + 2 * K);
+  return (e2 + hs + ob) * sizeof(float);
+}
+int weights_bwd_blocks(const Plan& P) {
+  return ceil_div(P.prm.q, WB_X) * ceil_div(P.prm.p, WB_Y) * P.npairs;
+}
+size_t mubar_partial_elems(const Plan& P) {
+  return (size_t)P.prm.L * P.sweep.ntiles * P.npairs * (P.sweep.rows + 2 * P.prm.K) * P.prm.q;
+}
+
+int sweep_bwd_prepare(int K) {
+  switch (K) {
+    case 0: return sbwd_attr<0>();
+    case 1: return sbwd_attr<1>();
+    case 2: return sbwd_attr<2>();
+    case 3: return sbwd_attr<3>();
+    default: return sbwd_attr<4>();
+  }
+}
+
+int launch_sweep_bwd(const Batch& B, int x, int mu, int cb, const float* sig_in, int sb, int xr,
+                     int halo, int mup, bool first, hipStream_t s) {
+  const Plan& P = *B.scenes[0];
+  const size_t lds = sweep_bwd_lds(P);
+  for (const Group& g : B.groups[KD_SWEEP]) {
+    if (!g.nitems) continue;
+    int rc;
+    switch (g.key0) {
+#define NLPR_SB(KK)                                                                           \
+  case KK:                                                                                    \
+    rc = first ? launch_sbwd<KK, true>(B, g, lds, x, mu, cb, sig_in, sb, xr, halo, mup, s)   \
+               : launch_sbwd<KK, false>(B, g, lds, x, mu, cb, sig_in, sb, xr, halo, mup, s); \
+    break;
+      NLPR_SB(0)
+      NLPR_SB(1)
+      NLPR_SB(2)
+      NLPR_SB(3)
+      NLPR_SB(4)
+#undef NLPR_SB
+      default:
+        set_error("sweep adjoint: unsupported patch radius");
+        return NLPR_ERR_UNSUPPORTED_SHAPE;
+    }
+    if (rc) return rc;
+  }
+  return NLPR_OK;
+}
+
+int launch_mubar_reduce(const Batch& B, int mup, int mub, hipStream_t s) {
+  return launch_kind(B, KD_MUPLANE, "mubar_reduce_kernel", mubar_reduce_kernel, s, mup, mub);
+}
+
+int launch_pupdate_bwd(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1b,
+                       int w2b, int l1b, int l2b, int bxb, int xp, int gyl, int gyh, int part,
+                       hipStream_t s) {
+  for (const Group& g : B.groups[KD_PIXEL]) {
+    if (!g.nitems) continue;
+    if (g.key0 == 1)
+      hipLaunchKernelGGL(pupdate_bwd_kernel<1>, dim3(g.nitems), dim3(256), 0, s, B.d_desc,
+                         g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl, gyh,
+                         part);
+    else if (g.key0 == 4)
+      hipLaunchKernelGGL(pupdate_bwd_kernel<4>, dim3(g.nitems), dim3(256), 0, s, B.d_desc,
+                         g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl, gyh,
+                         part);
+    else
+      hipLaunchKernelGGL(pupdate_bwd_kernel<kMaxLh>, dim3(g.nitems), dim3(256), 0, s, B.d_desc,
+                         g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl, gyh,
+                         part);
+    NLPR_LAUNCH_CHECK("pupdate_bwd_kernel");
+  }
+  return NLPR_OK;
+}
+
+int launch_weights_bwd(const Batch& B, int yh, int mub, int eb, int part, int w0, hipStream_t s) {
+  return launch_kind(B, KD_WBWD, "weights_bwd_kernel", weights_bwd_kernel, s, yh, mub, eb, part,
+                     w0);
+}
+
+int launch_yh_bwd(const Batch& B, int yh, int eb, int gyh, hipStream_t s) {
+  for (const Group& g : B.groups[KD_PIXEL]) {
+    if (!g.nitems) continue;
+    hipLaunchKernelGGL(yh_bwd_kernel, dim3(g.nitems), dim3(256), 0, s, B.d_desc, g.d_items, yh,
+                       eb, gyh);
+    NLPR_LAUNCH_CHECK("yh_bwd_kernel");
+  }
+  return NLPR_OK;
+}
+
+int launch_upsample_bwd(const Batch& B, int x0b, int gyl, hipStream_t s) {
+  return launch_kind(B, KD_PLANE, "upsample_bwd_kernel", upsample_bwd_kernel, s, x0b, gyl);
+}
+
+int launch_grad_scalars(const Batch& B, int part, int npix, int nw, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(grad_scalars_kernel, dim3(1), dim3(256), 0, s, B.d_desc, part, npix, nw,
+                     out);
+  NLPR_LAUNCH_CHECK("grad_scalars_kernel");
+  return NLPR_OK;
+}
+
+}  // namespace nlpr

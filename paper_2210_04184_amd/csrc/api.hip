@@ -287,6 +287,7 @@ SceneDesc static_desc(const Plan& P) {
   d.mon_nreg = P.d_mon ? monreg_blocks(P) : 0;
   d.rho_d = q.rho;
   d.lam1_d = q.lambda1;
+  d.lam_d = q.lambda;
   return d;
 }
 
@@ -400,6 +401,19 @@ int batch_build(Batch& B) {
     }
     if ((rc = add_group(B, KD_MONREG, it, 256, l, 0, 0))) return rc;
     if ((rc = add_group(B, KD_SCENE, sc, 256, 0, 0, 0))) return rc;
+  }
+  if (n == 1 && B.scenes[0]->npairs > 0) {     // reverse mode of a single scene
+    const Plan& P = *B.scenes[0];
+    std::vector<int2> it;
+    const int c = (int)(((size_t)P.npairs * P.prm.p * P.prm.q + 255) / 256);
+    for (int i = 0; i < c; ++i) it.push_back(make_int2(0, i));
+    if ((rc = add_group(B, KD_MUPLANE, it, 256, 0, 0, 0))) return rc;
+    it.clear();
+    for (int i = 0; i < weights_bwd_blocks(P); ++i) it.push_back(make_int2(0, i));
+    if ((rc = add_group(B, KD_WBWD, it, 256, weights_bwd_lds(P), 0, 0))) return rc;
+    if (P.sweep.items == 1 && sweep_bwd_lds(P) <= kMaxSweepLds &&
+        (rc = sweep_bwd_prepare(P.prm.K)))
+      return rc;
   }
   if ((rc = simple(KD_ROWS, rows_blocks, rows_lds, rows_block))) return rc;
   if ((rc = simple(KD_COLS, cols_blocks, cols_lds, cols_block))) return rc;
@@ -554,6 +568,25 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
   return NLPR_OK;
 }
 
+// Descriptor of one scene for a solve: workspace regions, observations and output.
+SceneDesc solve_desc(const Plan& P, char* base, const float* Yl, const float* Yh, float* Z) {
+  SceneDesc d = static_desc(P);
+  for (int k : {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO})
+    d.buf[k] = base + P.off[k];
+  d.buf[B_YL] = const_cast<float*>(Yl);
+  d.buf[B_YH] = const_cast<float*>(Yh);
+  if (P.d_E) {                       // X lives in the workspace; Z = X E at the end
+    d.buf[B_Z] = base + P.off[B_Z];
+    d.buf[B_YLE] = base + P.off[B_YLE];
+    d.buf[B_YLP] = base + P.off[B_YLP];
+    d.buf[B_OUT] = Z;
+  } else {
+    d.buf[B_Z] = Z;
+  }
+  d.buf[B_TMP] = base + P.off[B_BX];
+  return d;
+}
+
 int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float* const* Z,
                 void* ws, size_t ws_bytes, hipStream_t s) {
   const int n = (int)B.scenes.size();
@@ -567,23 +600,7 @@ int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float*
     if ((rc = check_device_ptr(Yl[i], "Yl")) || (rc = check_device_ptr(Yh[i], "Yh")) ||
         (rc = check_device_ptr(Z[i], "Z")))
       return rc;
-    const Plan& P = *B.scenes[i];
-    SceneDesc d = static_desc(P);
-    char* base = static_cast<char*>(ws) + B.base[i];
-    for (int k : {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO})
-      d.buf[k] = base + P.off[k];
-    d.buf[B_YL] = const_cast<float*>(Yl[i]);
-    d.buf[B_YH] = const_cast<float*>(Yh[i]);
-    if (P.d_E) {                       // X lives in the workspace; Z = X E at the end
-      d.buf[B_Z] = base + P.off[B_Z];
-      d.buf[B_YLE] = base + P.off[B_YLE];
-      d.buf[B_YLP] = base + P.off[B_YLP];
-      d.buf[B_OUT] = Z[i];
-    } else {
-      d.buf[B_Z] = Z[i];
-    }
-    d.buf[B_TMP] = base + P.off[B_BX];
-    descs[i] = d;
+    descs[i] = solve_desc(*B.scenes[i], static_cast<char*>(ws) + B.base[i], Yl[i], Yh[i], Z[i]);
   }
   DeviceGuard dg(B.device);
   if ((rc = ensure_events(B))) return rc;
@@ -634,6 +651,200 @@ int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float*
     NLPR_HIP_TRY(hipStreamSynchronize(s));
     if (hflag) return fail(NLPR_ERR_NUMERICAL, "NaN or Inf in Z");
   }
+  return NLPR_OK;
+}
+
+// ---------------------------------------------------------------------- reverse mode
+// Checkpoints: for t = 0 .. T-1 the state at the start of iteration t + 1, i.e. C^t,
+// Lambda1^t, Lambda2^t (planes) and, for t >= 1, Sigma'^t.  Layout: the 3 T planes first
+// ([t][C, Lambda1, Lambda2]), then the T - 1 Sigma' blocks.
+struct GradLayout {
+  size_t off[B_COUNT] = {};
+  size_t gws_bytes = 0;
+  size_t plane_al = 0, sig_al = 0, ck_bytes = 0;
+  int npix = 0, nw = 0;
+};
+
+GradLayout grad_layout(const Plan& P) {
+  GradLayout G;
+  const size_t pl = (size_t)P.Lx * P.prm.p * P.prm.q * sizeof(float);
+  size_t off = 0;
+  auto take = [&](int slot, size_t bytes) {
+    G.off[slot] = off;
+    off = align256(off + std::max<size_t>(bytes, 4));
+  };
+  for (int k : {B_GC, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR}) take(k, pl);
+  const size_t mup = (size_t)P.npairs * P.prm.p * P.prm.q * sizeof(float);
+  G.npix = pixel_blocks(P);
+  G.nw = P.npairs ? weights_bwd_blocks(P) : 0;
+  take(B_GSIG, P.sz[B_SIGMA]);
+  take(B_GHALO, P.sz[B_HALO]);
+  take(B_GMUP, P.npairs ? mubar_partial_elems(P) * sizeof(float) : 4);
+  take(B_GMU, mup);
+  take(B_GE, mup);
+  take(B_GPART, 2 * (size_t)(G.npix + G.nw) * sizeof(double));
+  G.gws_bytes = off;
+  const int T = P.prm.iters;
+  G.plane_al = align256(pl);
+  G.sig_al = P.npairs ? align256(P.sz[B_SIGMA]) : 0;
+  G.ck_bytes = (size_t)T * 3 * G.plane_al + (size_t)std::max(T - 1, 0) * G.sig_al;
+  return G;
+}
+
+int grad_check(const Batch& B) {
+  if (B.scenes.size() != 1) return fail(NLPR_ERR_INVALID_ARG, "reverse mode takes a single scene");
+  const Plan& P = *B.scenes[0];
+  if (P.d_E) return fail(NLPR_ERR_UNSUPPORTED_SHAPE, "reverse mode is built for E = I");
+  if (P.d_fia) return fail(NLPR_ERR_UNSUPPORTED_SHAPE, "reverse mode follows the paper's splitting (no NLPR_FUSED_S)");
+  if (B.flags & NLPR_STATE_IN) return fail(NLPR_ERR_INVALID_ARG, "reverse mode starts from the default start (no NLPR_STATE_IN)");
+  if (B.iters < 1) return fail(NLPR_ERR_INVALID_ARG, "reverse mode needs iters >= 1");
+  if (P.npairs && (P.sweep.items != 1 || sweep_bwd_lds(P) > kMaxSweepLds))
+    return fail(NLPR_ERR_UNSUPPORTED_SHAPE,
+                "the sweep adjoint needs q <= 1024 and its LDS tile within 160 KiB");
+  return NLPR_OK;
+}
+
+char* ck_plane(void* ck, const GradLayout& G, int t, int k) {
+  return static_cast<char*>(ck) + ((size_t)t * 3 + k) * G.plane_al;
+}
+float* ck_sig(void* ck, const GradLayout& G, int T, int t) {
+  return reinterpret_cast<float*>(static_cast<char*>(ck) + (size_t)T * 3 * G.plane_al +
+                                  (size_t)(t - 1) * G.sig_al);
+}
+
+int save_state(const Plan& P, const GradLayout& G, char* ws, void* ck, int t, hipStream_t s) {
+  const size_t pl = (size_t)P.Lx * P.prm.p * P.prm.q * sizeof(float);
+  const int slots[3] = {B_C, B_L1, B_L2};
+  for (int k = 0; k < 3; ++k)
+    NLPR_HIP_TRY(hipMemcpyAsync(ck_plane(ck, G, t, k), ws + P.off[slots[k]], pl,
+                                hipMemcpyDeviceToDevice, s));
+  return NLPR_OK;
+}
+
+int load_state(const Plan& P, const GradLayout& G, char* ws, void* ck, int t, hipStream_t s) {
+  const size_t pl = (size_t)P.Lx * P.prm.p * P.prm.q * sizeof(float);
+  const int slots[3] = {B_C, B_L1, B_L2};
+  for (int k = 0; k < 3; ++k)
+    NLPR_HIP_TRY(hipMemcpyAsync(ws + P.off[slots[k]], ck_plane(ck, G, t, k), pl,
+                                hipMemcpyDeviceToDevice, s));
+  return NLPR_OK;
+}
+
+// Forward solve that keeps the checkpoints.  Z = X^T equals nlpr_solve's output bit for bit;
+// the last iteration stops after its X-update, the only part of it that reaches Z.
+int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws, size_t ws_bytes,
+                 void* ck, size_t ck_bytes, hipStream_t s) {
+  int rc;
+  if ((rc = grad_check(B))) return rc;
+  const Plan& P = *B.scenes[0];
+  const GradLayout G = grad_layout(P);
+  if ((rc = check_device_ptr(ws, "ws")) || (rc = check_device_ptr(ck, "ck")) ||
+      (rc = check_device_ptr(Yl, "Yl")) || (rc = check_device_ptr(Yh, "Yh")) ||
+      (rc = check_device_ptr(Z, "Z")))
+    return rc;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 || reinterpret_cast<uintptr_t>(ck) % 256)
+    return fail(NLPR_ERR_INVALID_ARG, "ws and ck must be 256-byte aligned");
+  if (ws_bytes < B.ws_bytes || ck_bytes < G.ck_bytes)
+    return fail(NLPR_ERR_WORKSPACE_TOO_SMALL, "workspace or checkpoint buffer too small");
+  char* base = static_cast<char*>(ws);
+  std::vector<SceneDesc> descs{solve_desc(P, base, Yl, Yh, Z)};
+  DeviceGuard dg(B.device);
+  if ((rc = upload_desc(B, descs, s))) return rc;
+  const int T = B.iters;
+  const bool reg = P.npairs > 0;
+  if ((rc = launch_weights(B, B_YH, B_MU, s))) return rc;
+  if ((rc = launch_init(B, B_YL, B_YLP, B_Z, B_L1, B_L2, B_W2, s))) return rc;
+  if ((rc = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return rc;
+  if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s))) return rc;
+  if ((rc = save_state(P, G, base, ck, 0, s))) return rc;
+  for (int t = 1; t <= T; ++t) {
+    if ((rc = launch_xsolve(B, B_C, B_Z, B_F, -1, s))) return rc;
+    if (t == T) break;
+    if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
+    if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
+    if (reg && (rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, t == 1, s,
+                                  t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
+                                  ck_sig(ck, G, T, t))))
+      return rc;
+    if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
+    if ((rc = save_state(P, G, base, ck, t, s))) return rc;
+  }
+  NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
+  return NLPR_OK;
+}
+
+// Reverse pass: from Z' back through the T iterations (recomputing X and B X of each from
+// its checkpoint), the start and the weights.
+int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, void* ws,
+                  size_t ws_bytes, void* ck, size_t ck_bytes, void* gws, size_t gws_bytes,
+                  float* dYl, float* dYh, double* dscal, hipStream_t s) {
+  int rc;
+  if ((rc = grad_check(B))) return rc;
+  const Plan& P = *B.scenes[0];
+  const GradLayout G = grad_layout(P);
+  for (const void* ptr : {(const void*)ws, (const void*)ck, (const void*)gws, (const void*)Yl,
+                          (const void*)Yh, (const void*)dZ, (const void*)dYl, (const void*)dYh,
+                          (const void*)dscal})
+    if ((rc = check_device_ptr(ptr, "reverse-mode buffer"))) return rc;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 || reinterpret_cast<uintptr_t>(ck) % 256 ||
+      reinterpret_cast<uintptr_t>(gws) % 256)
+    return fail(NLPR_ERR_INVALID_ARG, "ws, ck and gws must be 256-byte aligned");
+  if (ws_bytes < B.ws_bytes || ck_bytes < G.ck_bytes || gws_bytes < G.gws_bytes)
+    return fail(NLPR_ERR_WORKSPACE_TOO_SMALL, "workspace, checkpoint or gradient buffer too small");
+  char* base = static_cast<char*>(ws);
+  char* gb = static_cast<char*>(gws);
+  // X of each iteration is recomputed into the W2 region (W2 is not needed backwards)
+  SceneDesc d = solve_desc(P, base, Yl, Yh, reinterpret_cast<float*>(base + P.off[B_W2]));
+  for (int k : {B_GC, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR, B_GSIG, B_GHALO, B_GMUP,
+                B_GMU, B_GE, B_GPART})
+    d.buf[k] = gb + G.off[k];
+  d.buf[B_GZ] = const_cast<float*>(dZ);
+  d.buf[B_GYL] = dYl;
+  d.buf[B_GYH] = dYh;
+  std::vector<SceneDesc> descs{d};
+  DeviceGuard dg(B.device);
+  if ((rc = upload_desc(B, descs, s))) return rc;
+  const int T = B.iters;
+  const bool reg = P.npairs > 0;
+  const int p = P.prm.p, q = P.prm.q, d_ = P.prm.d;
+  const size_t pl = (size_t)P.Lx * p * q * sizeof(float);
+  NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GL1], 0, pl, s));
+  NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GL2], 0, pl, s));
+  NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GSIG], 0, P.sz[B_SIGMA], s));
+  if (reg)
+    NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GMUP], 0, mubar_partial_elems(P) * sizeof(float), s));
+  NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GPART], 0, 2 * (size_t)(G.npix + G.nw) * sizeof(double), s));
+  NLPR_HIP_TRY(hipMemsetAsync(dYl, 0, (size_t)P.Lx * (p / d_) * (q / d_) * sizeof(float), s));
+  NLPR_HIP_TRY(hipMemsetAsync(dYh, 0, (size_t)P.prm.Lh * p * q * sizeof(float), s));
+  if ((rc = launch_weights(B, B_YH, B_MU, s))) return rc;
+  // Z = X^T = solve(C^{T-1})
+  if ((rc = launch_xsolve(B, B_GZ, B_GC, B_F, -1, s))) return rc;
+  for (int t = T - 1; t >= 1; --t) {
+    if ((rc = load_state(P, G, base, ck, t - 1, s))) return rc;
+    if ((rc = launch_xsolve(B, B_C, B_Z, B_F, -1, s))) return rc;
+    if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
+    if ((rc = launch_conv(B, B_GC, B_GW1, false, -1, -1, -1, 0, s))) return rc;   // W1' = B C'
+    if (reg && (rc = launch_sweep_bwd(B, B_Z, B_MU, B_GC, t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
+                                      B_GSIG, B_GXR, B_GHALO, B_GMUP, t == 1, s)))
+      return rc;
+    if ((rc = launch_pupdate_bwd(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_GW1, B_GC, B_GL1, B_GL2,
+                                 B_GBX, B_GXP, B_GYL, B_GYH, B_GPART, s)))
+      return rc;
+    // X' = B^T BX' + X'(P-update) + X'(sweep) (+ halo rows)
+    if ((rc = launch_conv(B, B_GBX, B_GX, true, B_GXP, B_GXR, B_GHALO, 2, s))) return rc;
+    if ((rc = launch_xsolve(B, B_GX, B_GC, B_F, -1, s))) return rc;
+  }
+  // start: C^0 = B^T B X0 + X0, X0 = up(Y_l)
+  if ((rc = launch_conv(B, B_GC, B_GW1, false, -1, -1, -1, 0, s))) return rc;
+  if ((rc = launch_conv(B, B_GW1, B_GX, true, B_GC, -1, -1, 0, s))) return rc;
+  if (!(B.flags & NLPR_INIT_ZERO) && (rc = launch_upsample_bwd(B, B_GX, B_GYL, s))) return rc;
+  if (reg) {
+    if ((rc = launch_mubar_reduce(B, B_GMUP, B_GMU, s))) return rc;
+    if ((rc = launch_weights_bwd(B, B_YH, B_GMU, B_GE, B_GPART, 2 * G.npix, s))) return rc;
+    if ((rc = launch_yh_bwd(B, B_YH, B_GE, B_GYH, s))) return rc;
+  }
+  if ((rc = launch_grad_scalars(B, B_GPART, G.npix, G.nw, dscal, s))) return rc;
+  NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
   return NLPR_OK;
 }
 
@@ -814,6 +1025,31 @@ int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void
 int nlpr_monitor(const nlpr_plan* plan, double* trace, int32_t cap, int32_t* n) {
   if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
   return batch_monitor(plan->B, 0, trace, cap, n);
+}
+
+int nlpr_grad_sizes(const nlpr_plan* plan, size_t* ck_bytes, size_t* gws_bytes) {
+  if (!plan || !ck_bytes || !gws_bytes) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  int rc = grad_check(plan->B);
+  if (rc) return rc;
+  const GradLayout G = grad_layout(*plan->B.scenes[0]);
+  *ck_bytes = G.ck_bytes;
+  *gws_bytes = G.gws_bytes;
+  return NLPR_OK;
+}
+
+int nlpr_forward(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void* ws,
+                 size_t ws_bytes, void* ck, size_t ck_bytes, void* stream) {
+  if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
+  return grad_forward(plan->B, Yl, Yh, Z, ws, ws_bytes, ck, ck_bytes,
+                      static_cast<hipStream_t>(stream));
+}
+
+int nlpr_backward(nlpr_plan* plan, const float* Yl, const float* Yh, const float* dZ, void* ws,
+                  size_t ws_bytes, void* ck, size_t ck_bytes, void* gws, size_t gws_bytes,
+                  float* dYl, float* dYh, double* dscal, void* stream) {
+  if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
+  return grad_backward(plan->B, Yl, Yh, dZ, ws, ws_bytes, ck, ck_bytes, gws, gws_bytes, dYl, dYh,
+                       dscal, static_cast<hipStream_t>(stream));
 }
 
 int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbufs, void* stream) {

@@ -44,6 +44,22 @@ enum Slot {
   B_OUT,     // Z = X E when a subspace basis is used (B_Z is then the X iterate)
   B_YLE,     // Y_l E^T, [Ls][p/d][q/d]
   B_YLP,     // Y_l E^+, [Ls][p/d][q/d]
+  // reverse mode (single scene): adjoints of the iteration's variables and the outputs
+  B_GZ,      // Z' (input)
+  B_GC,      // C'
+  B_GL1, B_GL2,   // Lambda1'', Lambda2''
+  B_GSIG,    // Sigma''
+  B_GX,      // X'
+  B_GW1,     // W1' = B C'
+  B_GBX,     // BX'
+  B_GXP,     // X' of the P-update
+  B_GXR,     // X' of the sweep (+ halo rows in B_GHALO)
+  B_GHALO,
+  B_GMUP,    // mu' partial tiles [L][ntiles][Npairs][R + 2K][q]
+  B_GMU,     // mu' [Npairs][p][q]
+  B_GE,      // e' [Npairs][p][q]
+  B_GYL, B_GYH,   // Y_l', Y_h' (outputs)
+  B_GPART,   // FP64 partial sums
   B_COUNT
 };
 
@@ -74,7 +90,7 @@ struct SceneDesc {
   // [mon_nreg] (regulariser per (shift, tile) block), then the trace [points][8]
   double* mon;
   int mon_npix, mon_nreg;
-  double rho_d, lam1_d;
+  double rho_d, lam1_d, lam_d;
   void* buf[B_COUNT];
 };
 
@@ -138,6 +154,8 @@ enum Kind { KD_WEIGHTS = 0, KD_PLANE, KD_CONV, KD_PIXEL, KD_SWEEP, KD_ROWS, KD_C
             KD_COMPOSE,  // one thread per pixel of scenes with a basis
             KD_MONREG,   // monitor regulariser: (shift, 32 x 64 tile) of scenes with a window
             KD_SCENE,    // one workgroup per scene
+            KD_MUPLANE,  // one thread per (shift, pixel): single-scene reverse mode
+            KD_WBWD,     // weights adjoint: (shift, 16 x 64 tile), single-scene reverse mode
             KD_COUNT };
 
 struct Batch {
@@ -269,13 +287,31 @@ int monreg_blocks(const Plan& P);
 size_t monreg_lds(const Plan& P);
 int monitor_points(int iters, int every);
 int launch_monitor(const Batch& B, int point, int iter, hipStream_t s);
+// reverse mode (adjoint.hip); single-scene batches
+size_t sweep_bwd_lds(const Plan& P);
+size_t weights_bwd_lds(const Plan& P);
+int weights_bwd_blocks(const Plan& P);
+size_t mubar_partial_elems(const Plan& P);
+int sweep_bwd_prepare(int K);
+int launch_sweep_bwd(const Batch& B, int x, int mu, int cb, const float* sig_in, int sb, int xr,
+                     int halo, int mup, bool first, hipStream_t s);
+int launch_mubar_reduce(const Batch& B, int mup, int mub, hipStream_t s);
+int launch_pupdate_bwd(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1b,
+                       int w2b, int l1b, int l2b, int bxb, int xp, int gyl, int gyh, int part,
+                       hipStream_t s);
+int launch_weights_bwd(const Batch& B, int yh, int mub, int eb, int part, int w0, hipStream_t s);
+int launch_yh_bwd(const Batch& B, int yh, int eb, int gyh, hipStream_t s);
+int launch_upsample_bwd(const Batch& B, int x0b, int gyl, hipStream_t s);
+int launch_grad_scalars(const Batch& B, int part, int npix, int nw, double* out, hipStream_t s);
 int launch_finite(const Batch& B, int z, int* flag, hipStream_t s);
 int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] slot
 int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s);   // S^T Y_l / rho
 // X = solve(C) (+ add, a [L][p][q] slot, when add >= 0); the fused-S system for fused scenes
 int launch_xsolve(const Batch& B, int c, int x, int f, int add, hipStream_t s);
+// sig_in / sig_out: read Sigma' from / write it to other buffers than the slot (a single
+// scene: the checkpoints of the differentiated solve); null = in place in the slot
 int launch_sweep(const Batch& B, int x, int mu, int sigma, int creg, int halo, bool first,
-                 hipStream_t s);
+                 hipStream_t s, const float* sig_in = nullptr, float* sig_out = nullptr);
 int sweep_prepare(int K, int items);   // kernel attributes; call before launches or capture
 
 // ---- shapes and tuning

@@ -60,14 +60,16 @@ __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v
 template <int K, int ITEMS, int NT, bool FIRST>
 __global__ void __launch_bounds__(NT)
 sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s, int mu_s,
-             int sig_s, int creg_s, int halo_s) {
+             int sig_s, int creg_s, int halo_s, const float* sig_in, float* sig_out) {
   const int2 it_ = items[blockIdx.x];
   const SceneDesc& S = sd[it_.x];
   const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
             H = S.halo;
   const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
   const gfloat* __restrict__ mu = gslot<const gfloat>(S, mu_s);
-  gfloat* __restrict__ sig = gslot<gfloat>(S, sig_s);
+  // Sigma' is updated in place unless sig_in / sig_out name other buffers (checkpoints)
+  gfloat* sig_w = sig_out ? as_global(sig_out) : gslot<gfloat>(S, sig_s);
+  const gfloat* sig_r = sig_in ? as_global(sig_in) : sig_w;
   gfloat* __restrict__ creg = gslot<gfloat>(S, creg_s);
   gfloat* __restrict__ halo = gslot<gfloat>(S, halo_s);
   constexpr int KW = 2 * K + 1;
@@ -114,7 +116,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   // contiguous stream, each (tau, k) slab of it R*q floats.
   const size_t kstride = (size_t)R * q;             // between patch offsets
   const size_t tstride = (size_t)NP * kstride;      // between shifts
-  gfloat* sig_tile = sig + ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
+  const size_t tile_off = ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
 
   for (int n = 0; n < npairs; ++n) {
     const int2 t = tau_at(S, n);
@@ -148,7 +150,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       A[m] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 
-    gfloat* sig_n = sig_tile + (size_t)n * tstride;
+    const size_t n_off = tile_off + (size_t)n * tstride;
 #pragma unroll
     for (int k1 = -K; k1 <= K; ++k1) {
       // thresholds mu(j + k, tau) for k2 in [-K, K]: columns col-4 .. col+7 of row + k1
@@ -165,7 +167,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       if (!FIRST) {
 #pragma unroll
         for (int k2 = 0; k2 < KW; ++k2) {
-          const gfloat* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
+          const gfloat* base = sig_r + n_off + (size_t)((k1 + K) * KW + k2) * kstride;
 #pragma unroll
           for (int m = 0; m < ITEMS; ++m)
             s[k2][m] = ok[m] ? ld_nt(base + (size_t)row[m] * q + col[m])
@@ -174,7 +176,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       }
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
-        gfloat* base = sig_n + (size_t)((k1 + K) * KW + k2) * kstride;
+        gfloat* base = sig_w + n_off + (size_t)((k1 + K) * KW + k2) * kstride;
 #pragma unroll
         for (int m = 0; m < ITEMS; ++m) {
           if (!ok[m]) continue;
@@ -245,10 +247,10 @@ constexpr int kMinItems = NLPR_SWEEP_MIN_ITEMS;
 
 template <int K, int ITEMS, bool FIRST>
 int launch_k(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
-             hipStream_t s) {
+             const float* sig_in, float* sig_out, hipStream_t s) {
   auto kern = sweep_kernel<K, ITEMS, kThreads, FIRST>;
   hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(kThreads), g.lds, s, B.d_desc, g.d_items, x, mu,
-                     sig, creg, halo);
+                     sig, creg, halo, sig_in, sig_out);
   NLPR_LAUNCH_CHECK("sweep_kernel");
   return NLPR_OK;
 }
@@ -275,11 +277,15 @@ int set_lds_limit_items(int items) {
 
 template <int K, bool FIRST>
 int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
-                 hipStream_t s) {
+                 const float* sig_in, float* sig_out, hipStream_t s) {
   switch (g.key1) {
-    case 1: return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST>(B, g, x, mu, sig, creg, halo, s);
-    case 2: return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST>(B, g, x, mu, sig, creg, halo, s);
-    default: return launch_k<K, 4, FIRST>(B, g, x, mu, sig, creg, halo, s);
+    case 1:
+      return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST>(B, g, x, mu, sig, creg, halo,
+                                                                  sig_in, sig_out, s);
+    case 2:
+      return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST>(B, g, x, mu, sig, creg, halo,
+                                                                  sig_in, sig_out, s);
+    default: return launch_k<K, 4, FIRST>(B, g, x, mu, sig, creg, halo, sig_in, sig_out, s);
   }
 }
 
@@ -317,15 +323,15 @@ int sweep_prepare(int K, int items) {
 }
 
 int launch_sweep(const Batch& B, int x, int mu, int sig, int creg, int halo, bool first,
-                 hipStream_t s) {
+                 hipStream_t s, const float* sig_in, float* sig_out) {
   for (const Group& g : B.groups[KD_SWEEP]) {
     if (!g.nitems) continue;
     int rc;
     switch (g.key0) {
 #define NLPR_SW(KK)                                                                            \
   case KK:                                                                                     \
-    rc = first ? launch_items<KK, true>(B, g, x, mu, sig, creg, halo, s)                       \
-               : launch_items<KK, false>(B, g, x, mu, sig, creg, halo, s);                     \
+    rc = first ? launch_items<KK, true>(B, g, x, mu, sig, creg, halo, sig_in, sig_out, s)      \
+               : launch_items<KK, false>(B, g, x, mu, sig, creg, halo, sig_in, sig_out, s);    \
     break;
       NLPR_SW(0)
       NLPR_SW(1)

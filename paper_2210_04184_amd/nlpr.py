@@ -63,7 +63,8 @@ EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlp
                    "nlpr_workspace_region", "nlpr_debug_stage", "nlpr_stage_time",
                    "nlpr_plan_get_info", "nlpr_batch_create", "nlpr_batch_workspace_size",
                    "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
-                   "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor"])
+                   "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor",
+                   "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward"])
 
 
 class NlprError(RuntimeError):
@@ -126,6 +127,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     dp = ctypes.POINTER(ctypes.c_double)
     lib.nlpr_monitor.argtypes = [vp, dp, i32, ctypes.POINTER(i32)]
     lib.nlpr_batch_monitor.argtypes = [vp, i32, dp, i32, ctypes.POINTER(i32)]
+    lib.nlpr_grad_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.nlpr_forward.argtypes = [vp, vp, vp, vp, vp, sz, vp, sz, vp]
+    lib.nlpr_backward.argtypes = [vp, vp, vp, vp, vp, sz, vp, sz, vp, sz, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("nlpr_status_string", "nlpr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -273,6 +277,46 @@ class Plan:
         """Monitor records of the last solve, [n][8] float64 (fields MON_FIELDS)."""
         return _read_monitor(lambda buf, cap, n: load().nlpr_monitor(self.handle, buf, cap, n))
 
+    # ---- reverse mode
+    def grad_sizes(self) -> Tuple[int, int]:
+        ck, gws = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().nlpr_grad_sizes(self.handle, ctypes.byref(ck), ctypes.byref(gws)))
+        return ck.value, gws.value
+
+    def forward(self, Yl, Yh, Z=None, ws=None, ck=None, stream=None):
+        """Solve and keep the checkpoints the reverse pass needs; returns (Z, ws, ck)."""
+        import torch
+        ckb, _ = self.grad_sizes()
+        if Z is None:
+            Z = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+        if ws is None:
+            ws = self.alloc_workspace()
+        if ck is None:
+            ck = torch.empty(max(ckb, 1), dtype=torch.uint8, device="cuda")
+        _check(load().nlpr_forward(self.handle, _ptr(Yl), _ptr(Yh), _ptr(Z), _ptr(ws),
+                                   ws.numel() * ws.element_size(), _ptr(ck),
+                                   ck.numel() * ck.element_size(), _stream_handle(stream)))
+        return Z, ws, ck
+
+    def backward(self, Yl, Yh, dZ, ws, ck, gws=None, stream=None):
+        """Gradients (dYl, dYh, dscal) of a loss with dloss/dZ = dZ; dscal is a device
+        float64 tensor [dlambda_2, drho]."""
+        import torch
+        _, gwsb = self.grad_sizes()
+        if gws is None:
+            gws = torch.empty(max(gwsb, 1), dtype=torch.uint8, device="cuda")
+        L, p, q = self.shape
+        d = self.params.d
+        dYl = torch.empty((L, p // d, q // d), dtype=torch.float32, device="cuda")
+        dYh = torch.empty((self.params.Lh, p, q), dtype=torch.float32, device="cuda")
+        dscal = torch.empty(2, dtype=torch.float64, device="cuda")
+        _check(load().nlpr_backward(self.handle, _ptr(Yl), _ptr(Yh), _ptr(dZ.contiguous()),
+                                    _ptr(ws), ws.numel() * ws.element_size(), _ptr(ck),
+                                    ck.numel() * ck.element_size(), _ptr(gws),
+                                    gws.numel() * gws.element_size(), _ptr(dYl), _ptr(dYh),
+                                    _ptr(dscal), _stream_handle(stream)))
+        return dYl, dYh, dscal
+
 
 def _read_monitor(call) -> np.ndarray:
     n = ctypes.c_int32()
@@ -381,6 +425,52 @@ class Batch:
         """Monitor records of one scene from the last batched solve, [n][8] float64."""
         return _read_monitor(
             lambda buf, cap, n: load().nlpr_batch_monitor(self.handle, scene, buf, cap, n))
+
+
+def _autograd_function():
+    import torch
+
+    class NLPRFunction(torch.autograd.Function):
+        """Z = X^(iters) of the unrolled ADMM as a differentiable function of
+        (Y_l, Y_h, lambda_2, rho); the backward pass is the library's hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, Yl, Yh, lam, rho, spec):
+            kw = dict(spec)
+            kw["lam"] = float(lam)
+            kw["rho"] = float(rho)
+            plan = Plan(**kw)
+            Yl_c, Yh_c = Yl.detach().contiguous(), Yh.detach().contiguous()
+            Z, ws, ck = plan.forward(Yl_c, Yh_c)
+            ctx.state = (plan, Yl_c, Yh_c, ws, ck)
+            return Z
+
+        @staticmethod
+        def backward(ctx, dZ):
+            plan, Yl, Yh, ws, ck = ctx.state
+            dYl, dYh, dscal = plan.backward(Yl, Yh, dZ, ws, ck)
+            ctx.state = None
+            s = dscal.to(torch.float32)
+            return dYl, dYh, s[0], s[1], None
+
+    return NLPRFunction
+
+
+_FN = None
+
+
+def fuse_differentiable(Yl, Yh, lam, rho, blur, R, d: int, K: int, Sw: int, iters: int, h: float,
+                        lam1: float = 1.0, flags: int = 0):
+    """Z = X^(iters) from Y_l [L][p/d][q/d] and Y_h [Lh][p][q] (float32 device tensors) and
+    the 0-dim tensors lam (lambda_2) and rho; differentiable in all four."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_function()
+    L, _, _ = Yl.shape
+    Lh, p, q = Yh.shape
+    spec = dict(p=p, q=q, L=L, Lh=Lh, d=d, blur=blur, R=R, K=K, Sw=Sw, iters=iters, h=h,
+                lam1=lam1, flags=flags)
+    return _FN.apply(Yl, Yh, lam, rho, spec)
 
 
 def fuse(Yl, Yh, blur, R, d: int, lam: float, K: int, Sw: int, rho: float, iters: int, h: float,

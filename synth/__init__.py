@@ -49,7 +49,7 @@ class SceneSpec:
     d: int
     blur_radius: int
     blur_sigma: float
-    R_kind: str  # "random1" | "bell1" | "gauss4" | "random" (L x Lh nonneg, cols sum 1) | "identity"
+    R_kind: str  # "random1" | "bell1" | "gauss3" | "gauss4" | "random" (L x Lh nonneg, cols sum 1) | "identity"
     Lh: int
     snr_l: float
     snr_h: float
@@ -100,6 +100,10 @@ CONFIGS: Dict[str, SceneSpec] = {
     # 512x512x128 HS+MS: four overlapping Gaussian band responses, 30 dB, patch 5x5, window 11x11
     "c3": SceneSpec("c3", 512, 512, 128, 4, 4, 2.5, "gauss4", 4, 30.0, 30.0, 12, 32, 8.0,
                     K=2, Sw=5, iters=100, seed=3),
+    # differentiated form: 256x256x31, 7x7 blur sigma 2, d=4, three overlapping Gaussian band
+    # responses (3-band MS guide), 30 dB, patch 3x3, window 3x3, 20 unrolled iterations
+    "c5": SceneSpec("c5", 256, 256, 31, 4, 3, 2.0, "gauss3", 3, 30.0, 30.0, 12, 32, 8.0,
+                    K=1, Sw=1, iters=20, seed=5),
 }
 
 
@@ -168,6 +172,9 @@ def _response(rng, kind, L, Lh):
     elif kind == "gauss4":
         R = np.stack([np.exp(-((c - (2 * j + 1) * L / 8.0) ** 2) / (2 * (L / 8.0) ** 2))
                       for j in range(4)], axis=1)
+    elif kind == "gauss3":
+        R = np.stack([np.exp(-((c - (2 * j + 1) * L / 6.0) ** 2) / (2 * (L / 6.0) ** 2))
+                      for j in range(3)], axis=1)
     elif kind == "random":
         R = rng.uniform(0.0, 1.0, size=(L, Lh))
     elif kind == "identity":

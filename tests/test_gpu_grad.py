@@ -1,0 +1,155 @@
+"""GPU reverse mode: gradients of a loss of X^(T) with respect to Y_l, Y_h, lambda_2 and rho
+through T unrolled iterations, against the FP64 reference gradient (torch autograd through
+the literal iteration, ``oracle.nlpr_grad``) and against central finite differences.
+
+Tolerances.  Against the FP64 reference: 1e-3 relative (L2 norm for the images), the bar
+the differentiated workload sets.  The FP32 finite differences are held to 1e-2.  For
+lambda_2 and rho they use a relative step of 1e-3.  For the images they use 1e-4: the loss
+is only piecewise smooth (every soft-threshold decision is a kink, and moving Y_h moves
+the thresholds), and at this workload a step of 1e-3 along Y_h already crosses enough
+kinks to move the quotient by about 3 % (0.3 % at 1e-4, measured).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import nlpr_grad as og
+from oracle import nlpr_oracle as o
+from paper_2210_04184_amd import nlpr
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) /
+                 max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def scene(p, q, L, Lh, d, r, K, Sw, iters, seed=13):
+    return synth.make_scene(synth.small_spec(p=p, q=q, L=L, Lh=Lh, d=d, blur_radius=r, K=K,
+                                             Sw=Sw, iters=iters, seed=seed, tile=8))
+
+
+def gpu_grad(sc, flags=0, **over):
+    plan = nlpr.Plan.from_scene(sc, flags=flags, **over)
+    Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+    Z, ws, ck = plan.forward(Yl, Yh)
+    Zt = torch.from_numpy(sc.Z).cuda()
+    Zd = Z.double()
+    loss = float(torch.mean((Zd - Zt) ** 2))
+    dZ = (2.0 * (Zd - Zt) / Zd.numel()).float()
+    dYl, dYh, ds = plan.backward(Yl, Yh, dZ, ws, ck)
+    s = host(ds)
+    return loss, host(dYl), host(dYh), float(s[0]), float(s[1]), host(Z)
+
+
+SHAPES = [
+    (48, 36, 3, 3, 2, 1, 1, 1, 6),      # radix 3, 3-band guide, 3x3 window
+    (32, 32, 4, 1, 4, 2, 1, 2, 5),      # PAN guide, 5x5 window
+    (48, 24, 2, 2, 2, 1, 2, 1, 4),      # 5x5 patch, several sweep tiles
+    (64, 64, 8, 3, 4, 3, 1, 1, 20),     # the differentiated workload's operators, T = 20
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gradient_matches_fp64_reference(shape):
+    *sz, T = shape
+    sc = scene(*sz, iters=T)
+    loss, gYl, gYh, glam, grho, Z = gpu_grad(sc)
+    pr = o.Problem.from_scene(sc)
+    ref = og.gradient(sc.Yl.astype(np.float64), sc.Yh.astype(np.float64), pr, T, sc.Z)
+    assert loss == pytest.approx(ref[0], rel=1e-4)
+    assert rel(gYl, ref[1]) <= 1e-3
+    assert rel(gYh, ref[2]) <= 1e-3
+    assert glam == pytest.approx(ref[3], rel=1e-3)
+    assert grho == pytest.approx(ref[4], rel=1e-3)
+
+
+@pytest.mark.parametrize("variant", ["unweighted", "local", "zero_init", "no_window", "lam0"])
+def test_gradient_variants_match_fp64_reference(variant):
+    sc = scene(32, 32, 3, 2, 4, 1, 1, 1, iters=5, seed=17)
+    flags, over, okw, init = 0, {}, {}, "upsample"
+    if variant == "unweighted":
+        flags, okw = nlpr.UNWEIGHTED, dict(unweighted=True)
+    elif variant == "local":
+        flags, okw = nlpr.LOCAL_WINDOW, dict(local=True)
+    elif variant == "zero_init":
+        flags, init = nlpr.INIT_ZERO, "zero"
+    elif variant == "no_window":
+        over, okw = dict(Sw=0), dict(S=0)
+    else:
+        over, okw = dict(lam=0.0), dict(lam=0.0)
+    loss, gYl, gYh, glam, grho, _ = gpu_grad(sc, flags=flags, **over)
+    pr = o.Problem.from_scene(sc, **okw)
+    ref = og.gradient(sc.Yl.astype(np.float64), sc.Yh.astype(np.float64), pr, 5, sc.Z,
+                      init=init)
+    assert rel(gYl, ref[1]) <= 1e-3
+    assert rel(gYh, ref[2]) <= 1e-3
+    assert glam == pytest.approx(ref[3], rel=1e-3, abs=1e-12)
+    assert grho == pytest.approx(ref[4], rel=1e-3)
+
+
+def test_forward_equals_solve_and_backward_repeats_bit_for_bit():
+    sc = scene(48, 36, 3, 3, 2, 1, 1, 1, iters=6)
+    plan = nlpr.Plan.from_scene(sc)
+    Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+    Zs, _ = nlpr.Plan.from_scene(sc).solve(Yl, Yh)
+    Z, ws, ck = plan.forward(Yl, Yh)
+    assert torch.equal(Z, Zs)
+    dZ = torch.randn_like(Z)
+    a = plan.backward(Yl, Yh, dZ, ws, ck)
+    b = plan.backward(Yl, Yh, dZ, ws, ck)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_autograd_function_matches_the_plan_calls():
+    sc = scene(32, 32, 4, 1, 4, 2, 1, 2, iters=5)
+    Yl = dev(sc.Yl).requires_grad_()
+    Yh = dev(sc.Yh).requires_grad_()
+    lam = torch.tensor(sc.spec.lam, requires_grad=True)
+    rho = torch.tensor(sc.spec.rho, requires_grad=True)
+    Z = nlpr.fuse_differentiable(Yl, Yh, lam, rho, sc.blur, sc.R, sc.spec.d, sc.spec.K,
+                                 sc.spec.Sw, sc.spec.iters, sc.h)
+    Zt = torch.from_numpy(sc.Z).float().cuda()
+    torch.mean((Z - Zt) ** 2).backward()
+    _, gYl, gYh, glam, grho, _ = gpu_grad(sc)
+    assert rel(host(Yl.grad), gYl) <= 1e-5
+    assert rel(host(Yh.grad), gYh) <= 1e-5
+    assert float(lam.grad) == pytest.approx(glam, rel=1e-5)
+    assert float(rho.grad) == pytest.approx(grho, rel=1e-5)
+
+
+def test_differentiated_workload_against_finite_differences():
+    """256 x 256 x 31 bands, 3-band guide, 7x7 blur, d = 4, 3x3 patch and window, 20
+    unrolled iterations: central differences at a relative step of 1e-3 for lambda_2 and
+    rho, and of 1e-4 along one random direction for Y_l and for Y_h."""
+    sc = synth.make_scene(synth.config("c5"))
+    loss, gYl, gYh, glam, grho, _ = gpu_grad(sc)
+    assert np.isfinite(gYl).all() and np.isfinite(gYh).all()
+    Zt = torch.from_numpy(sc.Z).cuda()
+
+    def loss_at(Yl=sc.Yl, Yh=sc.Yh, **over):
+        Z, _ = nlpr.Plan.from_scene(sc, **over).solve(dev(Yl), dev(Yh))
+        return float(torch.mean((Z.double() - Zt) ** 2))
+
+    for name, val, g in (("lam", sc.spec.lam, glam), ("rho", sc.spec.rho, grho)):
+        h = 1e-3 * val
+        fd = (loss_at(**{name: val + h}) - loss_at(**{name: val - h})) / (2 * h)
+        assert g == pytest.approx(fd, rel=1e-2), name
+    rng = np.random.default_rng(4)
+    for name, arr, g in (("Yl", sc.Yl, gYl), ("Yh", sc.Yh, gYh)):
+        v = rng.standard_normal(arr.shape)
+        h = 1e-4 * float(np.abs(arr).mean())
+        fd = (loss_at(**{name: arr + h * v}) - loss_at(**{name: arr - h * v})) / (2 * h)
+        assert float(np.sum(g * v)) == pytest.approx(fd, rel=1e-2), name
