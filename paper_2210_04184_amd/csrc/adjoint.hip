@@ -244,12 +244,14 @@ mubar_reduce_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ i
   const int i = rem / q, col = rem - (rem / q) * q;
   const gfloat* mup = gslot<const gfloat>(S, mup_s);
   float acc = 0.f;
-  for (int c = 0; c < S.L; ++c)
-    for (int tl = 0; tl < ntiles; ++tl) {
-      // extended row er of tile tl is image row (tl R - K + er) mod p
-      for (int er = wrapg(i - tl * R + S.K, p); er < ER; er += p)
+  for (int tl = 0; tl < ntiles; ++tl) {
+    // extended row er of tile tl is image row (tl R - K + er) mod p
+    const int er0 = wrapg(i - tl * R + S.K, p);
+    if (er0 >= ER) continue;
+    for (int c = 0; c < S.L; ++c)
+      for (int er = er0; er < ER; er += p)
         acc += mup[((((size_t)c * ntiles + tl) * S.npairs + n) * ER + er) * q + col];
-    }
+  }
   gslot<gfloat>(S, mub_s)[e] = acc;
 }
 
