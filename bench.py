@@ -123,8 +123,15 @@ def cpu_baseline(seconds_target: float = 15.0):
             if time.perf_counter() - t0 >= seconds_target:
                 break
         dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": spec.p * spec.q * spec.L * iters / dt, "unit": "pixel*band*iter/s",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", "host": {"cpu": model, "cpu_count": os.cpu_count()},
             "sample": f"literal FP64 oracle, 64x64x16 bands, Lh=4, patch 5x5, window 11x11, "
                       f"{iters} iterations incl. weights/setup in {dt:.1f} s, 1 thread"}
 

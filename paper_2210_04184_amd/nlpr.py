@@ -484,3 +484,11 @@ def fuse(Yl, Yh, blur, R, d: int, lam: float, K: int, Sw: int, rho: float, iters
     finally:
         plan.close()
     return Z
+
+
+def solve(Yl, Yh, blur, d: int, R, lam: float, K: int, Sw: int, rho: float, iters: int, h: float,
+          lam1: float = 1.0, stream=None):
+    """The call of the problem statement: Z from Y_l, Y_h, the blur b, the decimation d,
+    R, lambda_2, the patch and window radii, rho, the iteration count and the weight width
+    h (same as ``fuse`` with the arguments in this order)."""
+    return fuse(Yl, Yh, blur, R, d, lam, K, Sw, rho, iters, h, lam1=lam1, stream=stream)

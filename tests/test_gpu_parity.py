@@ -301,3 +301,12 @@ def test_check_finite_reports_nan_input():
     assert e.value.status == nlpr.ERR_NUMERICAL
     Z, _ = plan.solve(dev(sc.Yl), dev(sc.Yh))
     assert np.isfinite(host(Z)).all()
+
+
+def test_module_level_solve_wrapper():
+    # nlpr.solve(Yl, Yh, blur, d, R, lam, K, Sw, rho, iters, h) allocates its own workspace
+    sc = scene_for("radix3")
+    s = sc.spec
+    Z = nlpr.solve(dev(sc.Yl), dev(sc.Yh), sc.blur, s.d, sc.R, s.lam, s.K, s.Sw, s.rho,
+                   s.iters, sc.h)
+    assert rel_rmse(host(Z), solve_oracle(sc)) <= 1e-4
