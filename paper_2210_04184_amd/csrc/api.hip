@@ -366,7 +366,18 @@ int batch_build(Batch& B) {
   int rc;
   if ((rc = simple(KD_WEIGHTS, weights_blocks, weights_lds, block256))) return rc;
   if ((rc = simple(KD_PLANE, plane_blocks, no_lds, block256))) return rc;
-  if ((rc = simple(KD_CONV, conv_blocks, conv_lds, block256))) return rc;
+  for (int cls : {1, 2, 4, 8, kMaxBlurRadius}) {      // blur convolution by radius class
+    std::vector<int2> it;
+    size_t l = 0;
+    for (int s = 0; s < n; ++s) {
+      const Plan& P = *B.scenes[s];
+      if (conv_class(P.prm.blur_radius) != cls) continue;
+      const int c = conv_blocks(P);
+      for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+      l = std::max(l, conv_lds(P));
+    }
+    if (!it.empty() && (rc = add_group(B, KD_CONV, it, 256, l, cls, 0))) return rc;
+  }
   for (int cls : {1, 4, kMaxLh}) {
     std::vector<int2> it;
     for (int s = 0; s < n; ++s) {

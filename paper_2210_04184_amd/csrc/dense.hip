@@ -462,8 +462,12 @@ __global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
 // whose sweep never runs.  Local block = (band, tile row, tile col), tile
 // 16 x 64; each thread produces 4 consecutive outputs of one row, reusing the LDS row it
 // reads for all 4.
+// The blur radius is a template bound RM >= r (1, 2, 4, 8 or 16): the tile carries an RM
+// halo and the taps are zero-padded to (2 RM + 1)^2, so each thread keeps the 4 + 2 RM input
+// values of a tap row in registers and the tap loop is unrolled.  Padded taps add exact
+// zeros, so the sum equals the (2r+1)^2 one.
 constexpr int CV_Y = 16, CV_X = 64;
-template <bool TR>
+template <bool TR, int RM>
 __global__ void __launch_bounds__(256)
 conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int in_s, int out_s,
             int add1_s, int add2_s, int halo_s, int reg_mask) {
@@ -476,7 +480,8 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   const int rem = it.y - c * gx * gy;
   const int y0 = (rem / gx) * CV_Y, x0 = (rem % gx) * CV_X;
   const int w = 2 * r + 1;
-  const int TY = CV_Y + 2 * r, TX = CV_X + 2 * r;
+  constexpr int W2 = 2 * RM + 1;
+  constexpr int TY = CV_Y + 2 * RM, TX = CV_X + 2 * RM;
   float* tile = csh;
   float* tp = csh + TY * TX;
   const size_t plane = (size_t)p * q;
@@ -484,24 +489,40 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   const int xb = (threadIdx.x & 15) * 4;     // 4 outputs per thread
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   // in_s < 0: no convolution, out = add1 + add2 + halo fold (uniform over the launch)
-  const int rr = in_s < 0 ? -1 : r;
   if (in_s >= 0) {
     const gfloat* inc = gslot<const gfloat>(S, in_s) + (size_t)c * plane;
-    for (int idx = threadIdx.x; idx < w * w; idx += blockDim.x) tp[idx] = as_global(S.blur)[idx];
-    for (int idx = threadIdx.x; idx < TY * TX; idx += blockDim.x) {
-      const int yy = idx / TX, xx = idx % TX;
-      tile[idx] = inc[(size_t)wrapi(y0 - r + yy, p) * q + wrapi(x0 - r + xx, q)];
+    for (int idx = threadIdx.x; idx < W2 * W2; idx += blockDim.x) {
+      const int a = idx / W2 - RM, b = idx - (idx / W2) * W2 - RM;
+      tp[idx] = (a >= -r && a <= r && b >= -r && b <= r)
+                    ? as_global(S.blur)[(a + r) * w + (b + r)] : 0.f;
+    }
+    // tile with a circular RM halo: thread = column (coalesced), rows strided by 2; one wrap
+    // of the column per thread, rows wrapped incrementally (TX <= 96 <= 128 columns)
+    const int lane = threadIdx.x & 127;
+    if (lane < TX) {
+      const int gxx = wrapi(x0 - RM + lane, q);
+      int yy = threadIdx.x >> 7;
+      int gyy = wrapi(y0 - RM + yy, p);
+      for (; yy < TY; yy += 2) {
+        tile[yy * TX + lane] = inc[(size_t)gyy * q + gxx];
+        gyy += 2;
+        if (gyy >= p) gyy -= p;   // p >= 8
+      }
     }
     __syncthreads();
-  }
-  for (int m1 = -rr; m1 <= rr; ++m1) {
-    const float* trow = tile + (TR ? (y + r + m1) : (y + r - m1)) * TX + xb;
-    const float* tap = tp + (m1 + r) * w;
-    for (int m2 = -r; m2 <= r; ++m2) {
-      const float b = tap[m2 + r];
-      const int o = TR ? (r + m2) : (r - m2);
+    for (int m1 = -RM; m1 <= RM; ++m1) {
+      const float* trow = tile + (TR ? (y + RM + m1) : (y + RM - m1)) * TX + xb;
+      const float* tap = tp + (m1 + RM) * W2;
+      float rv[4 + 2 * RM];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[e] += b * trow[o + e];
+      for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+#pragma unroll
+      for (int m2 = -RM; m2 <= RM; ++m2) {
+        const float b = tap[m2 + RM];
+        const int o = TR ? (RM + m2) : (RM - m2);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += b * rv[o + e];
+      }
     }
   }
   const int gy2 = y0 + y;
@@ -511,20 +532,43 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   const gfloat* a2 = (reg || !(reg_mask & 2)) ? gslot<const gfloat>(S, add2_s) : nullptr;
   const gfloat* hb = reg ? gslot<const gfloat>(S, halo_s) : nullptr;
   gfloat* out = gslot<gfloat>(S, out_s);
+  const int gx0 = x0 + xb;
+  const size_t o0 = (size_t)c * plane + (size_t)gy2 * q + gx0;
+  // halo rows folded into image row gy2: halo row h of the tile starting at row
+  // gy2 + H - h (when that is a tile start); the same for the four columns
+  const int H = hb ? S.halo : 0, R = S.rows;
+  const uintptr_t align = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(a1) |
+                          reinterpret_cast<uintptr_t>(a2) | reinterpret_cast<uintptr_t>(hb);
+  if (gx0 + 3 < q && (align & 15) == 0) {
+    float4 v = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    if (a1) {
+      const float4 t = ldg4(a1 + o0);
+      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+    }
+    if (a2) {
+      const float4 t = ldg4(a2 + o0);
+      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+    }
+    for (int h = 0; h < H; ++h) {
+      const int r0 = wrapi(gy2 + H - h, p);
+      if (r0 % R) continue;
+      const float4 t = ldg4(hb + (((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx0);
+      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+    }
+    stg4(out + o0, v);
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int gx2 = x0 + xb + e;
+    const int gx2 = gx0 + e;
     if (gx2 >= q) continue;
-    const size_t o = (size_t)c * plane + (size_t)gy2 * q + gx2;
+    const size_t o = o0 + e;
     float v = acc[e];
     if (a1) v += a1[o];
     if (a2) v += a2[o];
-    if (hb) {
-      const int H = S.halo, R = S.rows;
-      for (int h = 0; h < H; ++h) {
-        const int r0 = wrapi(gy2 + H - h, p);
-        if (r0 % R == 0) v += hb[(((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx2];
-      }
+    for (int h = 0; h < H; ++h) {
+      const int r0 = wrapi(gy2 + H - h, p);
+      if (r0 % R == 0) v += hb[(((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx2];
     }
     out[o] = v;
   }
@@ -639,8 +683,8 @@ int conv_blocks(const Plan& P) {
   return ceil_div(P.prm.q, CV_X) * ceil_div(P.prm.p, CV_Y) * P.Lx;
 }
 size_t conv_lds(const Plan& P) {
-  const int r = P.prm.blur_radius;
-  return (size_t)((CV_Y + 2 * r) * (CV_X + 2 * r) + (2 * r + 1) * (2 * r + 1)) * sizeof(float);
+  const int rm = conv_class(P.prm.blur_radius);
+  return (size_t)((CV_Y + 2 * rm) * (CV_X + 2 * rm) + (2 * rm + 1) * (2 * rm + 1)) * sizeof(float);
 }
 int pixel_blocks(const Plan& P) { return ceil_div(P.prm.p * P.prm.q, 256); }
 
@@ -694,13 +738,38 @@ int launch_finite(const Batch& B, int z, int* flag, hipStream_t s) {
   return launch_groups(B, KD_PLANE, "finite_kernel", finite_kernel, s, z, flag);
 }
 
+int conv_class(int r) {
+  for (int rm : {1, 2, 4, 8}) if (r <= rm) return rm;
+  return kMaxBlurRadius;
+}
+
+template <int RM>
+int launch_conv_rm(const Group& g, const Batch& B, int in, int out, bool transpose, int add1,
+                   int add2, int halo, int reg_mask, hipStream_t s) {
+  auto kern = transpose ? conv_kernel<true, RM> : conv_kernel<false, RM>;
+  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(256), g.lds, s, B.d_desc, g.d_items, in, out, add1,
+                     add2, halo, reg_mask);
+  NLPR_LAUNCH_CHECK("conv_kernel");
+  return NLPR_OK;
+}
+
+// one launch per blur-radius class (key0 = RM)
 int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int add2, int halo,
                 int reg_mask, hipStream_t s) {
-  if (transpose)
-    return launch_groups(B, KD_CONV, "conv_kernel<T>", conv_kernel<true>, s, in, out, add1, add2,
-                         halo, reg_mask);
-  return launch_groups(B, KD_CONV, "conv_kernel", conv_kernel<false>, s, in, out, add1, add2, halo,
-                       reg_mask);
+  for (const Group& g : B.groups[KD_CONV]) {
+    if (!g.nitems) continue;
+    int rc;
+    switch (g.key0) {
+      case 1: rc = launch_conv_rm<1>(g, B, in, out, transpose, add1, add2, halo, reg_mask, s); break;
+      case 2: rc = launch_conv_rm<2>(g, B, in, out, transpose, add1, add2, halo, reg_mask, s); break;
+      case 4: rc = launch_conv_rm<4>(g, B, in, out, transpose, add1, add2, halo, reg_mask, s); break;
+      case 8: rc = launch_conv_rm<8>(g, B, in, out, transpose, add1, add2, halo, reg_mask, s); break;
+      default:
+        rc = launch_conv_rm<kMaxBlurRadius>(g, B, in, out, transpose, add1, add2, halo, reg_mask, s);
+    }
+    if (rc) return rc;
+  }
+  return NLPR_OK;
 }
 
 int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,

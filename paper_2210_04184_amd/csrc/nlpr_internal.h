@@ -262,6 +262,7 @@ int cols_blocks(const Plan& P);
 int sweep_blocks(const Plan& P);
 size_t weights_lds(const Plan& P);
 size_t conv_lds(const Plan& P);
+int conv_class(int r);                // template bound of a blur radius: 1, 2, 4, 8 or 16
 size_t rows_lds(const Plan& P);
 size_t cols_lds(const Plan& P);
 
