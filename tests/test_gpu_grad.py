@@ -58,6 +58,10 @@ SHAPES = [
     (32, 32, 4, 1, 4, 2, 1, 2, 5),      # PAN guide, 5x5 window
     (48, 24, 2, 2, 2, 1, 2, 1, 4),      # 5x5 patch, several sweep tiles
     (64, 64, 8, 3, 4, 3, 1, 1, 20),     # the differentiated workload's operators, T = 20
+    (24, 192, 2, 2, 4, 1, 1, 1, 4),     # three 64-column weight tiles, ragged sweep tiles
+    (32, 24, 2, 1, 2, 1, 0, 2, 4),      # 1 x 1 patch (pixel differences)
+    (24, 24, 1, 1, 2, 1, 3, 1, 3),      # 7 x 7 patch
+    (18, 24, 1, 2, 2, 1, 4, 1, 3),      # 9 x 9 patch
 ]
 
 
@@ -153,3 +157,28 @@ def test_differentiated_workload_against_finite_differences():
         h = 1e-4 * float(np.abs(arr).mean())
         fd = (loss_at(**{name: arr + h * v}) - loss_at(**{name: arr - h * v})) / (2 * h)
         assert float(np.sum(g * v)) == pytest.approx(fd, rel=1e-2), name
+
+
+def test_reverse_mode_rejects_what_it_does_not_cover():
+    sc = scene(32, 32, 4, 1, 4, 2, 1, 2, iters=3)
+    Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+    for kw in (dict(flags=nlpr.FUSED_S), dict(E=np.eye(4, dtype=np.float32)[:2]),
+               dict(flags=nlpr.STATE_IN)):
+        plan = nlpr.Plan.from_scene(sc, **kw)
+        with pytest.raises(nlpr.NlprError) as e:
+            plan.grad_sizes()
+        assert e.value.status in (nlpr.ERR_UNSUPPORTED_SHAPE, nlpr.ERR_INVALID_ARG)
+    plan = nlpr.Plan.from_scene(sc)
+    ckb, gwsb = plan.grad_sizes()
+    Z, ws, ck = plan.forward(Yl, Yh)
+    small = torch.empty(gwsb - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(nlpr.NlprError) as e:
+        plan.backward(Yl, Yh, torch.zeros_like(Z), ws, ck, gws=small)
+    assert e.value.status == nlpr.ERR_WORKSPACE_TOO_SMALL
+    with pytest.raises(nlpr.NlprError) as e:
+        plan.forward(Yl, Yh, ck=torch.empty(ckb - 256, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == nlpr.ERR_WORKSPACE_TOO_SMALL
+    # a host pointer where a device buffer is needed
+    with pytest.raises(nlpr.NlprError) as e:
+        plan.backward(Yl, Yh, torch.zeros(Z.shape), ws, ck)
+    assert e.value.status == nlpr.ERR_INVALID_ARG
