@@ -178,7 +178,18 @@ def test_reverse_mode_rejects_what_it_does_not_cover():
     with pytest.raises(nlpr.NlprError) as e:
         plan.forward(Yl, Yh, ck=torch.empty(ckb - 256, dtype=torch.uint8, device="cuda"))
     assert e.value.status == nlpr.ERR_WORKSPACE_TOO_SMALL
-    # a host pointer where a device buffer is needed
-    with pytest.raises(nlpr.NlprError) as e:
+    # a host buffer where a device buffer is needed: the binding refuses it, and so does the
+    # library when a host pointer reaches the C ABI directly
+    with pytest.raises(ValueError):
         plan.backward(Yl, Yh, torch.zeros(Z.shape), ws, ck)
-    assert e.value.status == nlpr.ERR_INVALID_ARG
+    import ctypes
+    host_dz = np.zeros(Z.shape, dtype=np.float32)
+    gws = torch.empty(gwsb, dtype=torch.uint8, device="cuda")
+    dYl, dYh = torch.empty_like(Yl), torch.empty_like(Yh)
+    ds = torch.empty(2, dtype=torch.float64, device="cuda")
+    rc = nlpr.load().nlpr_backward(plan.handle, Yl.data_ptr(), Yh.data_ptr(),
+                                   host_dz.ctypes.data_as(ctypes.c_void_p), ws.data_ptr(),
+                                   ws.numel(), ck.data_ptr(), ck.numel(), gws.data_ptr(),
+                                   gws.numel(), dYl.data_ptr(), dYh.data_ptr(), ds.data_ptr(),
+                                   None)
+    assert rc == nlpr.ERR_INVALID_ARG
