@@ -291,7 +291,7 @@ pupdate_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ it
     gfloat* GYh = gslot<gfloat>(S, gyh_s);
     const gfloat* R = as_global(S.R);
     const gfloat* G = as_global(S.G);
-    const float rho = S.rho, inv = S.inv_1prho, rr = S.rho * S.inv_1prho;
+    const float inv = S.inv_1prho, rr = S.rho * S.inv_1prho;   // 1/(1+rho), rho/(1+rho)
     const int i1 = j / q, i2 = j - (j / q) * q;
     const bool sampled = (i1 % d == 0) && (i2 % d == 0);
     const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
@@ -356,7 +356,6 @@ pupdate_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ it
         L1b[o] = -w1b;
       }
     }
-    (void)rho;
   }
   block_sum256(acc);
   if (threadIdx.x == 0) {
