@@ -52,7 +52,27 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
     os.replace(tmp, LIB)
+    build_c_driver()
     return LIB
+
+
+C_DRIVER_SRC = os.path.join(ROOT, "tests", "c", "abi_solve.c")
+C_DRIVER = os.path.join(ROOT, "tests", "c", "abi_solve")
+
+
+def build_c_driver() -> str:
+    """The C program the ABI test runs: plain C against include/nlpr.h, linked to
+    libnlpr.so (found next to it at run time through its rpath) and the HIP runtime."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    cmd = [shutil.which("gcc") or "gcc", "-O2", "-std=c11", "-D__HIP_PLATFORM_AMD__",
+           "-I", INCLUDE, "-I", os.path.join(rocm, "include"), C_DRIVER_SRC,
+           "-L", HERE, "-lnlpr", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/../../paper_2210_04184_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", C_DRIVER]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"C driver build failed:\n{res.stderr}")
+    return C_DRIVER
 
 
 if __name__ == "__main__":
