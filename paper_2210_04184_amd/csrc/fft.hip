@@ -161,23 +161,45 @@ __global__ void fft_rows_fwd(const SceneDesc* __restrict__ sd, const int2* __res
   const gfloat* C = gslot<const gfloat>(S, c_s);
   const gfloat* Ca = C + (size_t)(2 * m) * plane;
   const gfloat* Cb = (2 * m + 1 < L) ? C + (size_t)(2 * m + 1) * plane : nullptr;
-  for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
-    const int l = e / q, i = e - l * q, r = row0 + l;
-    float2 v = make_float2(0.f, 0.f);
-    if (r < p) {
-      v.x = Ca[(size_t)r * q + i];
-      if (Cb) v.y = Cb[(size_t)r * q + i];
+  // 16-byte loads (4 points of a row; q % 4 == 0) when the buffer allows, else 4-byte ones
+  if ((reinterpret_cast<uintptr_t>(C) & 15) == 0) {
+    const int q4 = q >> 2;
+    for (int e = threadIdx.x; e < lpb * q4; e += blockDim.x) {
+      const int l = e / q4, i4 = e - l * q4, r = row0 + l;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+      if (r < p) {
+        a = ldg4(Ca + (size_t)r * q + 4 * i4);
+        if (Cb) b = ldg4(Cb + (size_t)r * q + 4 * i4);
+      }
+      float2* d = sh + l * q + 4 * i4;
+      d[0] = make_float2(a.x, b.x);
+      d[1] = make_float2(a.y, b.y);
+      d[2] = make_float2(a.z, b.z);
+      d[3] = make_float2(a.w, b.w);
     }
-    sh[e] = v;
+  } else {
+    for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
+      const int l = e / q, i = e - l * q, r = row0 + l;
+      float2 v = make_float2(0.f, 0.f);
+      if (r < p) {
+        v.x = Ca[(size_t)r * q + i];
+        if (Cb) v.y = Cb[(size_t)r * q + i];
+      }
+      sh[e] = v;
+    }
   }
   __syncthreads();
   const int g = threadIdx.x / tpl;
   const int t = (g < lpb) ? threadIdx.x - g * tpl : tpl;
   fft_line<false>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl);
   gfloat* Fm = gslot<gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex, interleaved
-  for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
-    const int l = e / q, i = e - l * q, r = row0 + l;
-    if (r < p) stg2(Fm + 2 * ((size_t)r * q + i), sh[e]);
+  const int q2 = q >> 1;                // two complex points per 16-byte store
+  for (int e = threadIdx.x; e < lpb * q2; e += blockDim.x) {
+    const int l = e / q2, i2 = e - l * q2, r = row0 + l;
+    if (r < p) {
+      const float2 u = sh[l * q + 2 * i2], w = sh[l * q + 2 * i2 + 1];
+      stg4(Fm + 2 * ((size_t)r * q + 2 * i2), make_float4(u.x, u.y, w.x, w.y));
+    }
   }
 }
 
@@ -209,9 +231,28 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
     const int bc = cblk * cbb + l % cbb;
     return bc < qd ? bc + (l / cbb) * qd : -1;
   };
-  for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
-    const int i = e / cb, l = e - i * cb, col = column(l);
-    sh[l * p + i] = (col >= 0) ? ldg2(Fm + 2 * ((size_t)i * q + col)) : make_float2(0.f, 0.f);
+  // plain layout with an even block width: two neighbouring columns per 16-byte access
+  const bool pairs = !S.fused && (cb & 1) == 0;
+  if (pairs) {
+    const int cb2 = cb >> 1;
+    for (int e = threadIdx.x; e < cb2 * p; e += blockDim.x) {
+      const int i = e / cb2, l = 2 * (e - i * cb2), col = cblk * cb + l;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (col + 1 < q) {
+        v = ldg4(Fm + 2 * ((size_t)i * q + col));
+      } else if (col < q) {
+        const float2 u = ldg2(Fm + 2 * ((size_t)i * q + col));
+        v.x = u.x;
+        v.y = u.y;
+      }
+      sh[l * p + i] = make_float2(v.x, v.y);
+      sh[(l + 1) * p + i] = make_float2(v.z, v.w);
+    }
+  } else {
+    for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
+      const int i = e / cb, l = e - i * cb, col = column(l);
+      sh[l * p + i] = (col >= 0) ? ldg2(Fm + 2 * ((size_t)i * q + col)) : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   const int G = blockDim.x / tpl;
@@ -279,6 +320,18 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
       fft_line<true>(sh + (act ? l : 0) * p, S.fp, act ? tl : tpl, tpl);
     }
   }
+  if (pairs) {
+    const int cb2 = cb >> 1;
+    for (int e = threadIdx.x; e < cb2 * p; e += blockDim.x) {
+      const int i = e / cb2, l = 2 * (e - i * cb2), col = cblk * cb + l;
+      const float2 u = sh[l * p + i], w = sh[(l + 1) * p + i];
+      if (col + 1 < q)
+        stg4(Fm + 2 * ((size_t)i * q + col), make_float4(u.x, u.y, w.x, w.y));
+      else if (col < q)
+        stg2(Fm + 2 * ((size_t)i * q + col), u);
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < cb * p; e += blockDim.x) {
     const int i = e / cb, l = e - i * cb, col = column(l);
     if (col >= 0) stg2(Fm + 2 * ((size_t)i * q + col), sh[l * p + i]);
@@ -296,9 +349,13 @@ __global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __res
   const int m = it.y / nrb, row0 = (it.y - m * nrb) * lpb;
   const size_t plane = (size_t)p * q;
   const gfloat* Fm = gslot<const gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex
-  for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
-    const int l = e / q, i = e - l * q, r = row0 + l;
-    sh[e] = (r < p) ? ldg2(Fm + 2 * ((size_t)r * q + i)) : make_float2(0.f, 0.f);
+  const int q2 = q >> 1;                // two complex points per 16-byte load
+  for (int e = threadIdx.x; e < lpb * q2; e += blockDim.x) {
+    const int l = e / q2, i2 = e - l * q2, r = row0 + l;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r < p) v = ldg4(Fm + 2 * ((size_t)r * q + 2 * i2));
+    sh[l * q + 2 * i2] = make_float2(v.x, v.y);
+    sh[l * q + 2 * i2 + 1] = make_float2(v.z, v.w);
   }
   __syncthreads();
   const int g = threadIdx.x / tpl;
@@ -310,6 +367,32 @@ __global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __res
   const gfloat* Ad = add_s < 0 ? nullptr : gslot<const gfloat>(S, add_s);
   const gfloat* Aa = Ad ? Ad + (size_t)(2 * m) * plane : nullptr;
   const gfloat* Ab = (Ad && Xb) ? Ad + (size_t)(2 * m + 1) * plane : nullptr;
+  const uintptr_t align = reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Ad);
+  if ((align & 15) == 0) {              // 16-byte stores of 4 points of a row (q % 4 == 0)
+    const int q4 = q >> 2;
+    for (int e = threadIdx.x; e < lpb * q4; e += blockDim.x) {
+      const int l = e / q4, i4 = e - l * q4, r = row0 + l;
+      if (r >= p) continue;
+      const float2* s4 = sh + l * q + 4 * i4;
+      const float2 v0 = s4[0], v1 = s4[1], v2 = s4[2], v3 = s4[3];
+      const size_t o = (size_t)r * q + 4 * i4;
+      float4 a = make_float4(v0.x, v1.x, v2.x, v3.x);
+      if (Aa) {
+        const float4 t = ldg4(Aa + o);
+        a.x += t.x; a.y += t.y; a.z += t.z; a.w += t.w;
+      }
+      stg4(Xa + o, a);
+      if (Xb) {
+        float4 b = make_float4(v0.y, v1.y, v2.y, v3.y);
+        if (Ab) {
+          const float4 t = ldg4(Ab + o);
+          b.x += t.x; b.y += t.y; b.z += t.z; b.w += t.w;
+        }
+        stg4(Xb + o, b);
+      }
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < lpb * q; e += blockDim.x) {
     const int l = e / q, i = e - l * q, r = row0 + l;
     if (r < p) {
