@@ -31,6 +31,28 @@ __device__ __forceinline__ void st4_nt(gfloat* p, float4 v) {
   __builtin_nontemporal_store(w, (gv4f*)p);
 }
 
+// Sum of v[k] over the NW waves of the workgroup, in a fixed order; thread 0 gets it.
+template <int N, int NW>
+__device__ __forceinline__ void block_sum_waves(double (&v)[N]) {
+  __shared__ double red[N][NW];
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[k][w] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a = 0.0;
+      for (int i = 0; i < NW; ++i) a += red[k][i];
+      v[k] = a;
+    }
+  __syncthreads();
+}
+
 template <int N>
 __device__ __forceinline__ void block_sum256(double (&v)[N]) {
   __shared__ double red[N][4];
@@ -256,112 +278,173 @@ mubar_reduce_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ i
 }
 
 // ----------------------------------------------------------------------- P-update adjoint
-// One thread per pixel.  Inputs: X, BX of the iteration, Y_l, Y_h, Lambda1 and Lambda2
-// before the update; adjoints W1' (= B C'), W2' (= C'), Lambda1'', Lambda2'' of the
-// outputs.  Outputs: BX', X' of this step, Lambda'' of the inputs (in place), Y_l' and Y_h'
-// accumulated, and per workgroup two FP64 partial sums of rho', added to the workgroup's
-// own slot (repeatable across iterations): through P1, and through G, where
-// G' = sum res s^T and dG/drho = -G G / lambda1 give -res^T G (G s) / lambda1 per pixel.
+// Work item = 256 pixels; NC threads per pixel (1 for large images; for small ones 4, or 2
+// with up to 16 guide bands, which need more registers), each owning a contiguous share of
+// the bands.  Inputs: X, BX of the iteration, Y_l,
+// Y_h, Lambda1 and Lambda2 before the update; adjoints W1' (= B C'), W2' (= C'), Lambda1'',
+// Lambda2'' of the outputs.  Outputs: BX', X' of this step, Lambda'' of the inputs (in
+// place), Y_l' and Y_h' accumulated, and per workgroup two FP64 partial sums of rho', added
+// to the workgroup's own slot (repeatable across iterations): through P1, and through G,
+// where G' = sum res s^T and dG/drho = -G G / lambda1 give -res^T G (G s) / lambda1 per
+// pixel.  The band sums res = Y_h - A0 R and s = P2' R are formed per share and added in
+// LDS in a fixed order.
+// Bands [c0, c1) of one pixel in the P-update adjoint: X', Lambda2'', BX', Lambda1'' and
+// Y_l' of the step; returns the pixel's rho' share through P1.  Restrict parameters let the
+// compiler read R with scalar loads across the stores.
 template <int LHM>
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ double pupdate_bwd_write(
+    const gfloat* __restrict__ BX, const gfloat* __restrict__ Yl, const gfloat* __restrict__ L1,
+    const gfloat* __restrict__ W1b, const gfloat* __restrict__ W2b, gfloat* __restrict__ L1b,
+    gfloat* __restrict__ L2b, gfloat* __restrict__ BXb, gfloat* __restrict__ Xp,
+    gfloat* __restrict__ GYl, const gfloat* __restrict__ R, const float (&v)[LHM], size_t plane,
+    size_t lplane, size_t lj, bool sampled, int Lh, float inv, float rr, int c0, int c1, int j) {
+  double acc = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const size_t o = (size_t)c * plane + j;
+    float corr = 0.f;
+#pragma unroll
+    for (int h = 0; h < LHM; ++h)
+      if (h < Lh) corr += v[h] * R[c * Lh + h];
+    const float w2b = W2b[o], l2b = L2b[o];
+    const float a0b = (2.f * w2b + l2b) - corr;           // A0' = P2' - P2' R G R^T
+    Xp[o] = -w2b - l2b + a0b;
+    L2b[o] = w2b + l2b - a0b;
+    const float w1b = W1b[o], l1b = L1b[o];
+    if (sampled) {
+      const float p1b = 2.f * w1b + l1b;
+      const float y = Yl[c * lplane + lj];
+      BXb[o] = -w1b - l1b + p1b * rr;
+      L1b[o] = w1b + l1b - p1b * rr;
+      GYl[c * lplane + lj] += p1b * inv;
+      acc += (double)p1b * ((double)BX[o] - (double)L1[o] - (double)y) * (double)inv *
+             (double)inv;
+    } else {
+      BXb[o] = w1b;
+      L1b[o] = -w1b;
+    }
+  }
+  return acc;
+}
+
+template <int LHM, int PB_NC>
+__global__ void __launch_bounds__(256 * PB_NC)
 pupdate_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
                    int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1b_s, int w2b_s,
                    int l1b_s, int l2b_s, int bxb_s, int xp_s, int gyl_s, int gyh_s, int part_s) {
+  __shared__ float part[PB_NC > 1 ? PB_NC : 1][PB_NC > 1 ? LHM : 1][PB_NC > 1 ? 256 : 1];
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
   const int p = S.p, q = S.q, L = S.L, Lh = S.Lh, d = S.d;
   const size_t plane = (size_t)p * q;
-  const int j = it.y * 256 + threadIdx.x;
+  // the band share is uniform over a wave (256 threads per share); readfirstlane lets the
+  // band loops index R and G with scalar loads
+  const int pix = threadIdx.x & 255;
+  const int ch = PB_NC == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+  const int j = it.y * 256 + pix;
   const bool act = j < (int)plane;
-  double acc[2] = {0.0, 0.0};
-  if (act) {
-    const gfloat* X = gslot<const gfloat>(S, x_s);
-    const gfloat* BX = gslot<const gfloat>(S, bx_s);
-    const gfloat* Yl = gslot<const gfloat>(S, yl_s);
-    const gfloat* Yh = gslot<const gfloat>(S, yh_s);
-    const gfloat* L1 = gslot<const gfloat>(S, l1_s);
-    const gfloat* L2 = gslot<const gfloat>(S, l2_s);
-    const gfloat* W1b = gslot<const gfloat>(S, w1b_s);
-    const gfloat* W2b = gslot<const gfloat>(S, w2b_s);
-    gfloat* L1b = gslot<gfloat>(S, l1b_s);
-    gfloat* L2b = gslot<gfloat>(S, l2b_s);
-    gfloat* BXb = gslot<gfloat>(S, bxb_s);
-    gfloat* Xp = gslot<gfloat>(S, xp_s);
-    gfloat* GYl = gslot<gfloat>(S, gyl_s);
-    gfloat* GYh = gslot<gfloat>(S, gyh_s);
-    const gfloat* R = as_global(S.R);
-    const gfloat* G = as_global(S.G);
-    const float inv = S.inv_1prho, rr = S.rho * S.inv_1prho;   // 1/(1+rho), rho/(1+rho)
-    const int i1 = j / q, i2 = j - (j / q) * q;
-    const bool sampled = (i1 % d == 0) && (i2 % d == 0);
-    const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
-    const size_t lplane = (size_t)(p / d) * (q / d);
-    float res[LHM], sv[LHM], v[LHM];
+  const int c0 = (L * ch) / PB_NC, c1 = (L * (ch + 1)) / PB_NC;
+  const gfloat* X = gslot<const gfloat>(S, x_s);
+  const gfloat* L2 = gslot<const gfloat>(S, l2_s);
+  const gfloat* W2b = gslot<const gfloat>(S, w2b_s);
+  gfloat* L2b = gslot<gfloat>(S, l2b_s);
+  const gfloat* R = as_global(S.R);
+  const gfloat* G = as_global(S.G);
+  float rp[LHM], sp[LHM];
 #pragma unroll
-    for (int h = 0; h < LHM; ++h) {
-      res[h] = (h < Lh) ? Yh[h * plane + j] : 0.f;
-      sv[h] = 0.f;
-    }
-    for (int c = 0; c < L; ++c) {      // res = Y_h - A0 R,  s = P2' R
+  for (int h = 0; h < LHM; ++h) rp[h] = sp[h] = 0.f;
+  if (act)
+    for (int c = c0; c < c1; ++c) {      // this quarter's A0 R and P2' R
       const size_t o = (size_t)c * plane + j;
       const float a0 = X[o] - L2[o];
       const float p2b = 2.f * W2b[o] + L2b[o];
 #pragma unroll
       for (int h = 0; h < LHM; ++h)
         if (h < Lh) {
-          res[h] -= a0 * R[c * Lh + h];
-          sv[h] += p2b * R[c * Lh + h];
+          rp[h] += a0 * R[c * Lh + h];
+          sp[h] += p2b * R[c * Lh + h];
         }
     }
+  float res[LHM], sv[LHM];
+  if constexpr (PB_NC == 1) {             // one thread per pixel: no exchange
 #pragma unroll
-    for (int h2 = 0; h2 < LHM; ++h2) {  // v = s G  (G symmetric);  Y_h' += v;  G' += res s^T
+    for (int h = 0; h < LHM; ++h) {
+      res[h] = rp[h];
+      sv[h] = sp[h];
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) part[ch][h][pix] = rp[h];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) {
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < PB_NC; ++k) a += part[k][h][pix];
+      res[h] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) part[ch][h][pix] = sp[h];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) {
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < PB_NC; ++k) a += part[k][h][pix];
+      sv[h] = a;
+    }
+  }
+  double acc[2] = {0.0, 0.0};
+  if (act) {
+    const gfloat* BX = gslot<const gfloat>(S, bx_s);
+    const gfloat* Yl = gslot<const gfloat>(S, yl_s);
+    const gfloat* Yh = gslot<const gfloat>(S, yh_s);
+    const gfloat* L1 = gslot<const gfloat>(S, l1_s);
+    const gfloat* W1b = gslot<const gfloat>(S, w1b_s);
+    gfloat* L1b = gslot<gfloat>(S, l1b_s);
+    gfloat* BXb = gslot<gfloat>(S, bxb_s);
+    gfloat* Xp = gslot<gfloat>(S, xp_s);
+    gfloat* GYl = gslot<gfloat>(S, gyl_s);
+    gfloat* GYh = gslot<gfloat>(S, gyh_s);
+    const float inv = S.inv_1prho, rr = S.rho * S.inv_1prho;   // 1/(1+rho), rho/(1+rho)
+    const int i1 = j / q, i2 = j - (j / q) * q;
+    const bool sampled = (i1 % d == 0) && (i2 % d == 0);
+    const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
+    const size_t lplane = (size_t)(p / d) * (q / d);
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) res[h] = (h < Lh) ? Yh[h * plane + j] - res[h] : 0.f;
+    float v[LHM];                        // v = s G  (G symmetric)
+#pragma unroll
+    for (int h2 = 0; h2 < LHM; ++h2) {
       float t = 0.f;
 #pragma unroll
       for (int h = 0; h < LHM; ++h)
         if (h < Lh && h2 < Lh) t += sv[h] * G[h * Lh + h2];
       v[h2] = t;
-      if (h2 < Lh) GYh[h2 * plane + j] += t;
     }
-    float rg = 0.f;                     // res^T G v, v = G s
+    if (ch == 0) {                       // the pixel's Y_h' and rho' share through G, once
+      float rg = 0.f;                    // res^T G v
 #pragma unroll
-    for (int h2 = 0; h2 < LHM; ++h2) {
-      float w = 0.f;
+      for (int h2 = 0; h2 < LHM; ++h2) {
+        float w = 0.f;
 #pragma unroll
-      for (int h = 0; h < LHM; ++h)
-        if (h < Lh && h2 < Lh) w += v[h] * G[h * Lh + h2];
-      rg += res[h2] * w;
-    }
-    acc[1] = -(double)rg / S.lam1_d;
-    for (int c = 0; c < L; ++c) {
-      const size_t o = (size_t)c * plane + j;
-      float corr = 0.f;
-#pragma unroll
-      for (int h = 0; h < LHM; ++h)
-        if (h < Lh) corr += v[h] * R[c * Lh + h];
-      const float w2b = W2b[o], l2b = L2b[o];
-      const float a0b = (2.f * w2b + l2b) - corr;           // A0' = P2' - P2' R G R^T
-      Xp[o] = -w2b - l2b + a0b;
-      L2b[o] = w2b + l2b - a0b;
-      const float w1b = W1b[o], l1b = L1b[o];
-      if (sampled) {
-        const float p1b = 2.f * w1b + l1b;
-        const float y = Yl[c * lplane + lj];
-        BXb[o] = -w1b - l1b + p1b * rr;
-        L1b[o] = w1b + l1b - p1b * rr;
-        GYl[c * lplane + lj] += p1b * inv;
-        acc[0] += (double)p1b * ((double)BX[o] - (double)L1[o] - (double)y) * (double)inv *
-                  (double)inv;
-      } else {
-        BXb[o] = w1b;
-        L1b[o] = -w1b;
+        for (int h = 0; h < LHM; ++h)
+          if (h < Lh && h2 < Lh) w += v[h] * G[h * Lh + h2];
+        rg += res[h2] * w;
       }
+      acc[1] = -(double)rg / S.lam1_d;
+#pragma unroll
+      for (int h = 0; h < LHM; ++h)      // after every read of G (stores would order them)
+        if (h < Lh) GYh[h * plane + j] += v[h];
     }
+    acc[0] = pupdate_bwd_write<LHM>(BX, Yl, L1, W1b, W2b, L1b, L2b, BXb, Xp, GYl, R, v, plane,
+                                    lplane, lj, sampled, Lh, inv, rr, c0, c1, j);
   }
-  block_sum256(acc);
+  block_sum_waves<2, 4 * PB_NC>(acc);
   if (threadIdx.x == 0) {
-    gdouble* part = gslot<gdouble>(S, part_s) + 2 * (size_t)it.y;
-    part[0] += acc[0];
-    part[1] += acc[1];
+    gdouble* prt = gslot<gdouble>(S, part_s) + 2 * (size_t)it.y;
+    prt[0] += acc[0];
+    prt[1] += acc[1];
   }
 }
 
@@ -625,23 +708,31 @@ int launch_mubar_reduce(const Batch& B, int mup, int mub, hipStream_t s) {
   return launch_kind(B, KD_MUPLANE, "mubar_reduce_kernel", mubar_reduce_kernel, s, mup, mub);
 }
 
+template <int LHM, int NC>
+void launch_pb(const Batch& B, const Group& g, int x, int bx, int yl, int yh, int l1, int l2,
+               int w1b, int w2b, int l1b, int l2b, int bxb, int xp, int gyl, int gyh, int part,
+               hipStream_t s) {
+  hipLaunchKernelGGL((pupdate_bwd_kernel<LHM, NC>), dim3(g.nitems), dim3(256 * NC), 0, s,
+                     B.d_desc, g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl,
+                     gyh, part);
+}
+
 int launch_pupdate_bwd(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1b,
                        int w2b, int l1b, int l2b, int bxb, int xp, int gyl, int gyh, int part,
                        hipStream_t s) {
   for (const Group& g : B.groups[KD_PIXEL]) {
     if (!g.nitems) continue;
-    if (g.key0 == 1)
-      hipLaunchKernelGGL(pupdate_bwd_kernel<1>, dim3(g.nitems), dim3(256), 0, s, B.d_desc,
-                         g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl, gyh,
-                         part);
-    else if (g.key0 == 4)
-      hipLaunchKernelGGL(pupdate_bwd_kernel<4>, dim3(g.nitems), dim3(256), 0, s, B.d_desc,
-                         g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl, gyh,
-                         part);
-    else
-      hipLaunchKernelGGL(pupdate_bwd_kernel<kMaxLh>, dim3(g.nitems), dim3(256), 0, s, B.d_desc,
-                         g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl, gyh,
-                         part);
+    const bool split = g.key1 == 4;
+#define NLPR_PB(LHM, NC) \
+  launch_pb<LHM, NC>(B, g, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl, gyh, part, s)
+    if (g.key0 == 1) {
+      if (split) NLPR_PB(1, 4); else NLPR_PB(1, 1);
+    } else if (g.key0 == 4) {
+      if (split) NLPR_PB(4, 4); else NLPR_PB(4, 1);
+    } else {
+      if (split) NLPR_PB(kMaxLh, 2); else NLPR_PB(kMaxLh, 1);   // registers: 2 at most
+    }
+#undef NLPR_PB
     NLPR_LAUNCH_CHECK("pupdate_bwd_kernel");
   }
   return NLPR_OK;

@@ -378,15 +378,20 @@ int batch_build(Batch& B) {
     }
     if (!it.empty() && (rc = add_group(B, KD_CONV, it, 256, l, cls, 0))) return rc;
   }
+  // per-pixel launches by guide-band class (key0); key1 = threads per pixel, 4 (bands of a
+  // pixel split) when the launch covers few pixels in all, else 1
   for (int cls : {1, 4, kMaxLh}) {
     std::vector<int2> it;
+    size_t pixels = 0;
     for (int s = 0; s < n; ++s) {
       const Plan& P = *B.scenes[s];
       if (lh_class(P.prm.Lh) != cls) continue;
+      pixels += (size_t)P.prm.p * P.prm.q;
       const int c = pixel_blocks(P);
       for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
     }
-    if (!it.empty() && (rc = add_group(B, KD_PIXEL, it, 256, 0, cls, 0))) return rc;
+    if (!it.empty() && (rc = add_group(B, KD_PIXEL, it, 256, 0, cls, pixel_split(pixels))))
+      return rc;
   }
   // scenes with a subspace basis: low-resolution projections / P1, and Z = X E
   for (Kind kind : {KD_LOWRES, KD_COMPOSE}) {

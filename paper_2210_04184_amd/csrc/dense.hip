@@ -295,16 +295,21 @@ p1_subspace_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ it
       l1[k] = L1[k * plane + j];
       v[k] = rho * bx[k] + yle[(size_t)k * nl + m] - rho * l1[k];
     }
+  float p1[kMaxLs];                       // every read of M before the first store
+#pragma unroll
+  for (int k2 = 0; k2 < kMaxLs; ++k2) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMaxLs; ++k)
+      if (k < Ls && k2 < Ls) t += v[k] * M[k * Ls + k2];
+    p1[k2] = t;
+  }
 #pragma unroll
   for (int k2 = 0; k2 < kMaxLs; ++k2)
     if (k2 < Ls) {
-      float p1 = 0.f;
-#pragma unroll
-      for (int k = 0; k < kMaxLs; ++k)
-        if (k < Ls) p1 += v[k] * M[k * Ls + k2];
-      const float l1n = l1[k2] - (bx[k2] - p1);
+      const float l1n = l1[k2] - (bx[k2] - p1[k2]);
       L1[k2 * plane + j] = l1n;
-      W1[k2 * plane + j] = p1 + l1n;
+      W1[k2 * plane + j] = p1[k2] + l1n;
     }
 }
 
@@ -575,7 +580,10 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
 }
 
 // ---------------------------------------------------------------------------- pupdate
-// One thread per pixel; bands are visited twice.  With E = I:
+// Work item = 256 pixels; a workgroup of 256 NC threads gives each pixel NC threads (1, or
+// 4 when the launch covers few pixels in all, so that it still fills the GPU), each owning
+// a contiguous share of the bands.
+// With E = I:
 //   P1 = (rho BX + Y_l - rho Lambda1) / (1 + rho)  on sampled pixels (S^T S = 1)
 //   P1 = BX - Lambda1                              elsewhere            (eq. (Qh_update))
 //   P2 = (X - Lambda2 + lambda1/rho Y_h R^T) F,  F = (I + lambda1/rho R R^T)^{-1}
@@ -584,39 +592,39 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
 // G = (rho/lambda1 I + R^T R)^{-1}: Woodbury gives F = I - R G R^T and the push-through
 // identity R^T F = (I + lambda1/rho R^T R)^{-1} R^T turns lambda1/rho Y_h R^T F into
 // Y_h G R^T.  The rearrangement is exact and keeps every FP32 term O(|X|) instead of
-// O(lambda1/rho |Y_h|), which avoids a large cancellation.
+// O(lambda1/rho |Y_h|), which avoids a large cancellation.  The contraction A0 R over
+// bands is summed per band share and the parts are added in share order (through LDS when a
+// pixel has several threads).
 //   Lambda1 -= BX - P1,  Lambda2 -= X - P2;  W1 = P1 + Lambda1,  W2 = P2 + Lambda2
+// Band shares of the contraction A0 R in the P-update: fixed, so that the sum is the same
+// whichever number of threads a pixel has.
+constexpr int kPuShares = 4;
+
+// rp += sum over bands [c0, c1) of (X - Lambda2)_c R_c, one fused multiply-add per term.
 template <int LHM>
-__device__ __forceinline__ void pupdate_body(
-    const gfloat* __restrict__ X, const gfloat* __restrict__ BX, const gfloat* __restrict__ Yl,
-    const gfloat* __restrict__ Yh, gfloat* __restrict__ L1, gfloat* __restrict__ L2,
-    gfloat* __restrict__ W1, gfloat* __restrict__ W2, const gfloat* __restrict__ R,
-    const gfloat* __restrict__ G, int p, int q, int L, int Lh, int d, float rho, float inv_1prho,
-    int p1mode, int j) {
-  const size_t plane = (size_t)p * q;
-  const int i1 = j / q, i2 = j - i1 * q;
-  const bool sampled = (i1 % d == 0) && (i2 % d == 0);
-  const size_t lj = (size_t)(i1 / d) * (q / d) + i2 / d;
-  const size_t lplane = (size_t)(p / d) * (q / d);
-  float res[LHM];
-#pragma unroll
-  for (int h = 0; h < LHM; ++h) res[h] = (h < Lh) ? Yh[h * plane + j] : 0.f;
-  for (int c = 0; c < L; ++c) {           // res = Y_h - A0 R
+__device__ __forceinline__ void pupdate_share(const gfloat* __restrict__ X,
+                                              const gfloat* __restrict__ L2,
+                                              const gfloat* __restrict__ R, float (&rp)[LHM],
+                                              size_t plane, int Lh, int c0, int c1, int j) {
+  for (int c = c0; c < c1; ++c) {
     const float a0 = X[c * plane + j] - L2[c * plane + j];
 #pragma unroll
     for (int h = 0; h < LHM; ++h)
-      if (h < Lh) res[h] -= a0 * R[c * Lh + h];
+      if (h < Lh) rp[h] = __builtin_fmaf(a0, R[c * Lh + h], rp[h]);
   }
-  float u[LHM];                           // u = res G
-#pragma unroll
-  for (int h2 = 0; h2 < LHM; ++h2) {
-    float s = 0.f;
-#pragma unroll
-    for (int h = 0; h < LHM; ++h)
-      if (h < Lh && h2 < Lh) s += res[h] * G[h * Lh + h2];
-    u[h2] = s;
-  }
-  for (int c = 0; c < L; ++c) {
+}
+
+// Bands [c0, c1) of one pixel: P2, Lambda2, W2 and (per p1mode) P1, Lambda1, W1.  The
+// pointers arrive as restrict parameters so that the compiler may read R with scalar loads
+// across the stores (restrict on local pointer variables is not used for that).
+template <int LHM>
+__device__ __forceinline__ void pupdate_write(
+    const gfloat* __restrict__ X, const gfloat* __restrict__ BX, const gfloat* __restrict__ Yl,
+    gfloat* __restrict__ L1, gfloat* __restrict__ L2, gfloat* __restrict__ W1,
+    gfloat* __restrict__ W2, const gfloat* __restrict__ R, const float (&u)[LHM], size_t plane,
+    size_t lplane, size_t lj, bool sampled, int p1mode, int Lh, float rho, float inv_1prho,
+    int c0, int c1, int j) {
+  for (int c = c0; c < c1; ++c) {
     const size_t o = c * plane + j;
     float corr = 0.f;
 #pragma unroll
@@ -627,8 +635,6 @@ __device__ __forceinline__ void pupdate_body(
     const float l2n = l2 - (x - p2);
     L2[o] = l2n;
     W2[o] = p2 + l2n;
-    // p1mode 1: a basis couples the sampled pixels across bands (p1_subspace_kernel);
-    // p1mode 2: fused-S splitting, no P1
     if (p1mode == 2 || (sampled && p1mode == 1)) continue;
     const float bx = BX[o], l1 = L1[o];
     const float p1 = sampled ? (rho * bx + Yl[c * lplane + lj] - rho * l1) * inv_1prho : bx - l1;
@@ -638,20 +644,84 @@ __device__ __forceinline__ void pupdate_body(
   }
 }
 
-template <int LHM>
-__global__ void __launch_bounds__(256)
+template <int LHM, int PU_NC>
+__global__ void __launch_bounds__(256 * PU_NC)
 pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
                int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1_s, int w2_s) {
+  __shared__ float part[PU_NC > 1 ? PU_NC : 1][PU_NC > 1 ? LHM : 1][PU_NC > 1 ? 256 : 1];
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
-  const int j = it.y * 256 + threadIdx.x;
-  if (j >= S.p * S.q) return;
-  pupdate_body<LHM>(gslot<const gfloat>(S, x_s), gslot<const gfloat>(S, bx_s),
-                    gslot<const gfloat>(S, yl_s), gslot<const gfloat>(S, yh_s),
-                    gslot<gfloat>(S, l1_s), gslot<gfloat>(S, l2_s), gslot<gfloat>(S, w1_s),
-                    gslot<gfloat>(S, w2_s), as_global(S.R), as_global(S.G),
-                    S.p, S.q, S.L, S.Lh, S.d, S.rho, S.inv_1prho,
-                    S.fused ? 2 : (S.subspace ? 1 : 0), j);
+  const int p = S.p, q = S.q, L = S.L, Lh = S.Lh, d = S.d;
+  // the band share is uniform over a wave (256 threads per share); readfirstlane lets the
+  // band loops index R and G with scalar loads
+  const int pix = threadIdx.x & 255;
+  const int ch = PU_NC == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+  const int j = it.y * 256 + pix;
+  const size_t plane = (size_t)p * q;
+  const bool act = j < (int)plane;
+  const int c0 = (L * ch) / PU_NC, c1 = (L * (ch + 1)) / PU_NC;   // this thread's bands
+  const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
+  gfloat* __restrict__ L2 = gslot<gfloat>(S, l2_s);
+  const gfloat* __restrict__ R = as_global(S.R);
+  const gfloat* __restrict__ G = as_global(S.G);
+  const gfloat* __restrict__ Yh = gslot<const gfloat>(S, yh_s);
+  // res = Y_h - A0 R.  The bands form kPuShares contiguous shares; each share's part of A0 R
+  // is summed on its own and the parts are added in share order, so the result does not
+  // depend on how many threads a pixel has.
+  float res[LHM];
+  if constexpr (PU_NC == 1) {
+    // one thread per pixel: the parts are added in registers, and no barrier sits between
+    // the two band loops (with one the memory-bound loops of different waves do not overlap)
+    if (!act) return;
+    float a[LHM];
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) a[h] = 0.f;
+    for (int k = 0; k < kPuShares; ++k) {
+      float rp[LHM];
+#pragma unroll
+      for (int h = 0; h < LHM; ++h) rp[h] = 0.f;
+      pupdate_share<LHM>(X, L2, R, rp, plane, Lh, (L * k) / kPuShares,
+                         (L * (k + 1)) / kPuShares, j);
+#pragma unroll
+      for (int h = 0; h < LHM; ++h) a[h] += rp[h];
+    }
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) res[h] = (h < Lh) ? Yh[h * plane + j] - a[h] : 0.f;
+  } else {
+    static_assert(PU_NC == kPuShares, "one share per thread");
+    float rp[LHM];
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) rp[h] = 0.f;
+    if (act) pupdate_share<LHM>(X, L2, R, rp, plane, Lh, c0, c1, j);
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) part[ch][h][pix] = rp[h];
+    __syncthreads();
+    if (!act) return;
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) {
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < PU_NC; ++k) a += part[k][h][pix];
+      res[h] = (h < Lh) ? Yh[h * plane + j] - a : 0.f;
+    }
+  }
+  float u[LHM];                           // u = res G
+#pragma unroll
+  for (int h2 = 0; h2 < LHM; ++h2) {
+    float sum = 0.f;
+#pragma unroll
+    for (int h = 0; h < LHM; ++h)
+      if (h < Lh && h2 < Lh) sum += res[h] * G[h * Lh + h2];
+    u[h2] = sum;
+  }
+  const int i1 = j / q, i2 = j - i1 * q;
+  // p1mode 1: a basis couples the sampled pixels across bands (p1_subspace_kernel);
+  // p1mode 2: fused-S splitting, no P1
+  pupdate_write<LHM>(X, gslot<const gfloat>(S, bx_s), gslot<const gfloat>(S, yl_s),
+                     gslot<gfloat>(S, l1_s), L2, gslot<gfloat>(S, w1_s), gslot<gfloat>(S, w2_s),
+                     R, u, plane, (size_t)(p / d) * (q / d),
+                     (size_t)(i1 / d) * (q / d) + i2 / d, (i1 % d == 0) && (i2 % d == 0),
+                     S.fused ? 2 : (S.subspace ? 1 : 0), Lh, S.rho, S.inv_1prho, c0, c1, j);
 }
 
 template <typename Kern, typename... Args>
@@ -772,20 +842,30 @@ int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int a
   return NLPR_OK;
 }
 
+template <int LHM, int NC>
+void launch_pu(const Batch& B, const Group& g, int x, int bx, int yl, int yh, int l1, int l2,
+               int w1, int w2, hipStream_t s) {
+  hipLaunchKernelGGL((pupdate_kernel<LHM, NC>), dim3(g.nitems), dim3(256 * NC), 0, s, B.d_desc,
+                     g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
+}
+
 int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,
                    hipStream_t s) {
-  // one launch per guide-band class (key0 = 1, 4 or 16 register slots)
+  // one launch per guide-band class (key0 = 1, 4 or 16 register slots) and threads per
+  // pixel (key1 = 1 or 4)
   for (const Group& g : B.groups[KD_PIXEL]) {
     if (!g.nitems) continue;
-    if (g.key0 == 1)
-      hipLaunchKernelGGL(pupdate_kernel<1>, dim3(g.nitems), dim3(g.block), 0, s, B.d_desc,
-                         g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
-    else if (g.key0 == 4)
-      hipLaunchKernelGGL(pupdate_kernel<4>, dim3(g.nitems), dim3(g.block), 0, s, B.d_desc,
-                         g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
-    else
-      hipLaunchKernelGGL(pupdate_kernel<kMaxLh>, dim3(g.nitems), dim3(g.block), 0, s, B.d_desc,
-                         g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
+    const bool split = g.key1 == 4;
+    if (g.key0 == 1) {
+      if (split) launch_pu<1, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+      else launch_pu<1, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+    } else if (g.key0 == 4) {
+      if (split) launch_pu<4, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+      else launch_pu<4, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+    } else {
+      if (split) launch_pu<kMaxLh, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+      else launch_pu<kMaxLh, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+    }
     NLPR_LAUNCH_CHECK("pupdate_kernel");
   }
   return NLPR_OK;

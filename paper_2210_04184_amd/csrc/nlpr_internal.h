@@ -276,6 +276,9 @@ int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int a
 int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,
                    hipStream_t s);
 int lh_class(int Lh);                // pupdate template class of a guide-band count: 1, 4 or 16
+// threads per pixel of a P-update launch over `pixels` pixels in all: 4 (bands split) below
+// 131072, where one thread per pixel would leave most of the GPU idle, else 1
+inline int pixel_split(size_t pixels) { return pixels < 131072 ? 4 : 1; }
 int lowres_blocks(const Plan& P);
 // with a subspace basis: Y_l E^T and Y_l E^+ (once per solve), the P1-update on sampled
 // pixels, and Z = X E

@@ -443,6 +443,8 @@ def _autograd_function():
             Yl_c, Yh_c = Yl.detach().contiguous(), Yh.detach().contiguous()
             Z, ws, ck = plan.forward(Yl_c, Yh_c)
             ctx.state = (plan, Yl_c, Yh_c, ws, ck)
+            ctx.scalar_meta = [(t.dtype, t.device) if isinstance(t, torch.Tensor) else None
+                               for t in (lam, rho)]
             return Z
 
         @staticmethod
@@ -450,8 +452,10 @@ def _autograd_function():
             plan, Yl, Yh, ws, ck = ctx.state
             dYl, dYh, dscal = plan.backward(Yl, Yh, dZ, ws, ck)
             ctx.state = None
-            s = dscal.to(torch.float32)
-            return dYl, dYh, s[0], s[1], None
+            g = []
+            for k, meta in enumerate(ctx.scalar_meta):   # in the dtype and place of lam / rho
+                g.append(None if meta is None else dscal[k].to(dtype=meta[0], device=meta[1]))
+            return dYl, dYh, g[0], g[1], None
 
     return NLPRFunction
 

@@ -102,3 +102,21 @@ def test_c4_batch_sample_matches_oracle():
         ref = o.solve(sc.Yl.astype(np.float64), sc.Yh.astype(np.float64),
                       o.Problem.from_scene(sc), sc.spec.iters).X
         assert rel(host(Zs[i]), ref) <= 1e-4, (i, sc.spec)
+
+
+@pytest.mark.parametrize("Lh", [1, 4, 16])
+def test_threads_per_pixel_do_not_change_the_result(Lh):
+    """A P-update launch over few pixels gives each pixel 4 threads (band shares added
+    through LDS), one over many pixels 1 thread (the same shares added in registers).  Three
+    256 x 192 scenes solved one at a time take the first form, together the second; both
+    must give the same bits, with every guide-band class."""
+    scenes = [synth.make_scene(synth.small_spec(p=256, q=192, L=7 + 3 * i, Lh=Lh, d=4,
+                                                blur_radius=2, K=1, Sw=1, iters=3,
+                                                seed=60 + i, tile=16))
+              for i in range(3)]
+    batch = nlpr.Batch.from_scenes(scenes)
+    Yls, Yhs = [dev(s.Yl) for s in scenes], [dev(s.Yh) for s in scenes]
+    Zs, _ = batch.solve(Yls, Yhs)
+    for i, sc in enumerate(scenes):
+        Z, _ = nlpr.Plan.from_scene(sc).solve(Yls[i], Yhs[i])
+        np.testing.assert_array_equal(host(Zs[i]), host(Z), err_msg=f"scene {i}")

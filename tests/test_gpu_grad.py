@@ -121,17 +121,20 @@ def test_autograd_function_matches_the_plan_calls():
     sc = scene(32, 32, 4, 1, 4, 2, 1, 2, iters=5)
     Yl = dev(sc.Yl).requires_grad_()
     Yh = dev(sc.Yh).requires_grad_()
-    lam = torch.tensor(sc.spec.lam, requires_grad=True)
-    rho = torch.tensor(sc.spec.rho, requires_grad=True)
+    lam = torch.tensor(sc.spec.lam, dtype=torch.float64, requires_grad=True)
+    rho = torch.tensor(sc.spec.rho, dtype=torch.float64, requires_grad=True)
     Z = nlpr.fuse_differentiable(Yl, Yh, lam, rho, sc.blur, sc.R, sc.spec.d, sc.spec.K,
                                  sc.spec.Sw, sc.spec.iters, sc.h)
     Zt = torch.from_numpy(sc.Z).float().cuda()
     torch.mean((Z - Zt) ** 2).backward()
-    _, gYl, gYh, glam, grho, _ = gpu_grad(sc)
-    assert rel(host(Yl.grad), gYl) <= 1e-5
-    assert rel(host(Yh.grad), gYh) <= 1e-5
-    assert float(lam.grad) == pytest.approx(glam, rel=1e-5)
-    assert float(rho.grad) == pytest.approx(grho, rel=1e-5)
+    # same plan parameters (lam, rho as float64) and the same MSE seed gradient: identical
+    plan = nlpr.Plan.from_scene(sc)
+    Zp, ws, ck = plan.forward(dev(sc.Yl), dev(sc.Yh))
+    Zc = Zp.detach().clone().requires_grad_()
+    torch.mean((Zc - Zt) ** 2).backward()          # the seed the autograd path receives
+    dYl, dYh, ds = plan.backward(dev(sc.Yl), dev(sc.Yh), Zc.grad, ws, ck)
+    assert torch.equal(Yl.grad, dYl) and torch.equal(Yh.grad, dYh)
+    assert float(lam.grad) == float(ds[0]) and float(rho.grad) == float(ds[1])
 
 
 def test_differentiated_workload_against_finite_differences():
