@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "nlpr_internal.h"
 
@@ -124,6 +125,35 @@ void scene_free(Plan* P) {
   delete P;
 }
 
+// A blur of rank one, b(a, c) = u(a) v(c) up to FP32 rounding (a Gaussian, for one), is
+// applied as a pass along rows and one along columns: 2 (2r+1) multiply-adds per output
+// instead of (2r+1)^2.  The factors come from the row and the column through the largest
+// tap, in FP64; the blur counts as rank one when no tap differs from u(a) v(c) by more than
+// 1e-6 of the largest (a Gaussian rounded to FP32 stays near 2e-7).  uv = u then v.
+bool separable_factors(const float* b, int r, std::vector<float>& uv) {
+  const int w = 2 * r + 1;
+  int a0 = 0, c0 = 0;
+  double bm = 0.0;
+  for (int a = 0; a < w; ++a)
+    for (int c = 0; c < w; ++c)
+      if (std::fabs((double)b[a * w + c]) > bm) {
+        bm = std::fabs((double)b[a * w + c]);
+        a0 = a;
+        c0 = c;
+      }
+  if (!(bm > 0.0) || !std::isfinite(bm)) return false;
+  std::vector<double> u(w), v(w);
+  for (int a = 0; a < w; ++a) u[a] = b[a * w + c0];
+  for (int c = 0; c < w; ++c) v[c] = (double)b[a0 * w + c] / (double)b[a0 * w + c0];
+  for (int a = 0; a < w; ++a)
+    for (int c = 0; c < w; ++c)
+      if (!(std::fabs((double)b[a * w + c] - u[a] * v[c]) <= 1e-6 * bm)) return false;
+  uv.resize(2 * w);
+  for (int a = 0; a < w; ++a) uv[a] = (float)u[a];
+  for (int c = 0; c < w; ++c) uv[w + c] = (float)v[c];
+  return true;
+}
+
 // Validate, upload the blur taps and R, precompute the tables, tune the FFT shapes and lay
 // out the scene's part of the workspace.
 int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_host,
@@ -163,7 +193,8 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
       hipMalloc(&P->d_invden, plane * sizeof(float)) != hipSuccess ||
       hipMalloc(&P->d_tw_p, p * sizeof(float2)) != hipSuccess ||
       hipMalloc(&P->d_tw_q, q * sizeof(float2)) != hipSuccess ||
-      hipMalloc(&P->d_blur, (2 * r + 1) * (2 * r + 1) * sizeof(float)) != hipSuccess ||
+      hipMalloc(&P->d_blur, ((2 * r + 1) * (2 * r + 1) + 2 * (2 * r + 1)) * sizeof(float)) !=
+          hipSuccess ||
       hipMalloc(&P->d_R, (size_t)L * Lh * sizeof(float)) != hipSuccess ||
       hipMalloc(&P->d_G, (size_t)Lh * Lh * sizeof(float)) != hipSuccess) {
     set_error("hipMalloc of plan tables failed");
@@ -178,6 +209,16 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
       hipMemcpy(P->d_R, R_host, (size_t)L * Lh * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("upload of the plan tables failed");
     return cleanup(NLPR_ERR_HIP);
+  }
+  {
+    std::vector<float> uv;
+    P->blur_separable = separable_factors(blur_host, r, uv);
+    if (P->blur_separable &&
+        hipMemcpy(P->d_blur + (2 * r + 1) * (2 * r + 1), uv.data(), uv.size() * sizeof(float),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("upload of the blur factors failed");
+      return cleanup(NLPR_ERR_HIP);
+    }
   }
   if (E_host) {
     if (hipMalloc(&P->d_E, (size_t)Lx * L * sizeof(float)) != hipSuccess ||
@@ -276,6 +317,8 @@ SceneDesc static_desc(const Plan& P) {
   d.taus = P.d_taus;
   d.invden = P.d_invden;
   d.blur = P.d_blur;
+  const int bw = 2 * q.blur_radius + 1;
+  d.bsep = P.blur_separable ? P.d_blur + bw * bw : nullptr;
   d.R = P.d_E ? P.d_Rt : P.d_R;
   d.G = P.d_G;
   d.fused = P.d_fia ? 1 : 0;
@@ -1022,7 +1065,7 @@ int nlpr_plan_get_info(const nlpr_plan* plan, nlpr_plan_info* info) {
   info->tile_rows = P.sweep.rows;
   info->ntiles = P.sweep.ntiles;
   info->halo_rows = P.sweep.halo;
-  info->reserved = 0;
+  info->blur_separable = P.blur_separable ? 1 : 0;
   info->sigma_elems = P.sz[B_SIGMA] / sizeof(float);
   return NLPR_OK;
 }

@@ -471,12 +471,16 @@ __global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
 // halo and the taps are zero-padded to (2 RM + 1)^2, so each thread keeps the 4 + 2 RM input
 // values of a tap row in registers and the tap loop is unrolled.  Padded taps add exact
 // zeros, so the sum equals the (2r+1)^2 one.
+// A rank-one blur b = u v^T (S.bsep) runs as a pass along rows over the tile and its halo
+// rows, h = v * in, kept in LDS, then one along columns, out = u * h: 2 (2 RM + 1) instead of
+// (2 RM + 1)^2 multiply-adds per output.
 constexpr int CV_Y = 16, CV_X = 64;
 template <bool TR, int RM>
 __global__ void __launch_bounds__(256)
 conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int in_s, int out_s,
             int add1_s, int add2_s, int halo_s, int reg_mask) {
-  extern __shared__ float csh[];
+  extern __shared__ float4 csh4[];           // 16-byte aligned: the rank-one pass stores float4
+  float* csh = reinterpret_cast<float*>(csh4);
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
   const int p = S.p, q = S.q, r = S.r;
@@ -496,10 +500,20 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   // in_s < 0: no convolution, out = add1 + add2 + halo fold (uniform over the launch)
   if (in_s >= 0) {
     const gfloat* inc = gslot<const gfloat>(S, in_s) + (size_t)c * plane;
-    for (int idx = threadIdx.x; idx < W2 * W2; idx += blockDim.x) {
-      const int a = idx / W2 - RM, b = idx - (idx / W2) * W2 - RM;
-      tp[idx] = (a >= -r && a <= r && b >= -r && b <= r)
-                    ? as_global(S.blur)[(a + r) * w + (b + r)] : 0.f;
+    const gfloat* uv = S.bsep ? as_global(S.bsep) : nullptr;
+    float* ht = tp;                          // rank one: TY x CV_X row-filtered tile
+    float* tu = ht + TY * CV_X;              // rank one: u, v zero-padded to 2 RM + 1
+    if (uv) {
+      for (int idx = threadIdx.x; idx < 2 * W2; idx += blockDim.x) {
+        const int m = (idx < W2 ? idx : idx - W2) - RM;
+        tu[idx] = (m >= -r && m <= r) ? uv[(idx < W2 ? 0 : w) + m + r] : 0.f;
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < W2 * W2; idx += blockDim.x) {
+        const int a = idx / W2 - RM, b = idx - (idx / W2) * W2 - RM;
+        tp[idx] = (a >= -r && a <= r && b >= -r && b <= r)
+                      ? as_global(S.blur)[(a + r) * w + (b + r)] : 0.f;
+      }
     }
     // tile with a circular RM halo: thread = column (coalesced), rows strided by 2; one wrap
     // of the column per thread, rows wrapped incrementally (TX <= 96 <= 128 columns)
@@ -515,18 +529,48 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
       }
     }
     __syncthreads();
-    for (int m1 = -RM; m1 <= RM; ++m1) {
-      const float* trow = tile + (TR ? (y + RM + m1) : (y + RM - m1)) * TX + xb;
-      const float* tap = tp + (m1 + RM) * W2;
-      float rv[4 + 2 * RM];
+    if (uv) {
+      const float* tv = tu + W2;
+      for (int yy = y; yy < TY; yy += CV_Y) {   // rows of the tile and of its halo
+        const float* trow = tile + yy * TX + xb;
+        float rv[4 + 2 * RM];
 #pragma unroll
-      for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+        for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+        float hs[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int m2 = -RM; m2 <= RM; ++m2) {
-        const float b = tap[m2 + RM];
-        const int o = TR ? (RM + m2) : (RM - m2);
+        for (int m2 = -RM; m2 <= RM; ++m2) {
+          const float b = tv[m2 + RM];
+          const int o = TR ? (RM + m2) : (RM - m2);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] += b * rv[o + e];
+          for (int e = 0; e < 4; ++e) hs[e] += b * rv[o + e];
+        }
+        *reinterpret_cast<float4*>(ht + yy * CV_X + xb) = make_float4(hs[0], hs[1], hs[2], hs[3]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m1 = -RM; m1 <= RM; ++m1) {
+        const float4 h =
+            *reinterpret_cast<const float4*>(ht + (TR ? (y + RM + m1) : (y + RM - m1)) * CV_X + xb);
+        const float b = tu[m1 + RM];
+        acc[0] += b * h.x;
+        acc[1] += b * h.y;
+        acc[2] += b * h.z;
+        acc[3] += b * h.w;
+      }
+    } else {
+      for (int m1 = -RM; m1 <= RM; ++m1) {
+        const float* trow = tile + (TR ? (y + RM + m1) : (y + RM - m1)) * TX + xb;
+        const float* tap = tp + (m1 + RM) * W2;
+        float rv[4 + 2 * RM];
+#pragma unroll
+        for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+#pragma unroll
+        for (int m2 = -RM; m2 <= RM; ++m2) {
+          const float b = tap[m2 + RM];
+          const int o = TR ? (RM + m2) : (RM - m2);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] += b * rv[o + e];
+        }
       }
     }
   }
@@ -753,8 +797,10 @@ int conv_blocks(const Plan& P) {
   return ceil_div(P.prm.q, CV_X) * ceil_div(P.prm.p, CV_Y) * P.Lx;
 }
 size_t conv_lds(const Plan& P) {
-  const int rm = conv_class(P.prm.blur_radius);
-  return (size_t)((CV_Y + 2 * rm) * (CV_X + 2 * rm) + (2 * rm + 1) * (2 * rm + 1)) * sizeof(float);
+  // tile + the larger of the (2 RM + 1)^2 taps and (rank one) the row-filtered tile with u, v
+  const int rm = conv_class(P.prm.blur_radius), w2 = 2 * rm + 1;
+  return (size_t)((CV_Y + 2 * rm) * (CV_X + 2 * rm) +
+                  std::max(w2 * w2, (CV_Y + 2 * rm) * CV_X + 2 * w2)) * sizeof(float);
 }
 int pixel_blocks(const Plan& P) { return ceil_div(P.prm.p * P.prm.q, 256); }
 

@@ -77,6 +77,7 @@ struct SceneDesc {
   const int2* taus;
   const float* invden;
   const float* blur;
+  const float* bsep;               // u then v (2r+1 each) of a rank-one blur b = u v^T, else null
   const float* R;
   const float* G;
   const float* E;                  // [Ls][Lz]
@@ -120,7 +121,8 @@ struct Plan {
   float2* d_tw_q = nullptr;
   LineFFT fp{}, fq{};
   FftShape fft{};
-  float* d_blur = nullptr;
+  float* d_blur = nullptr;          // (2r+1)^2 taps, then u and v when blur_separable
+  bool blur_separable = false;
   float* d_R = nullptr;
   float* d_G = nullptr;
   int Lx = 0;                     // bands of X: Ls with a basis, else L

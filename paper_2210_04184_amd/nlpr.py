@@ -86,7 +86,7 @@ class Params(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("npairs", ctypes.c_int32), ("npatch", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("ntiles", ctypes.c_int32),
-                ("halo_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("halo_rows", ctypes.c_int32), ("blur_separable", ctypes.c_int32),
                 ("sigma_elems", ctypes.c_size_t)]
 
 

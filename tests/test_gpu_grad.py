@@ -79,7 +79,8 @@ def test_gradient_matches_fp64_reference(shape):
     assert grho == pytest.approx(ref[4], rel=1e-3)
 
 
-@pytest.mark.parametrize("variant", ["unweighted", "local", "zero_init", "no_window", "lam0"])
+@pytest.mark.parametrize("variant", ["unweighted", "local", "zero_init", "no_window", "lam0",
+                                     "asymmetric_blur"])
 def test_gradient_variants_match_fp64_reference(variant):
     sc = scene(32, 32, 3, 2, 4, 1, 1, 1, iters=5, seed=17)
     flags, over, okw, init = 0, {}, {}, "upsample"
@@ -91,8 +92,12 @@ def test_gradient_variants_match_fp64_reference(variant):
         flags, init = nlpr.INIT_ZERO, "zero"
     elif variant == "no_window":
         over, okw = dict(Sw=0), dict(S=0)
-    else:
+    elif variant == "lam0":
         over, okw = dict(lam=0.0), dict(lam=0.0)
+    else:                                # B^T != B: the adjoint must swap the two directions
+        b = np.random.default_rng(8).uniform(0.0, 1.0, (3, 3))
+        b = np.asarray(b / b.sum(), dtype=np.float32)
+        over, okw = dict(blur=b), dict(b=b.astype(np.float64))
     loss, gYl, gYh, glam, grho, _ = gpu_grad(sc, flags=flags, **over)
     pr = o.Problem.from_scene(sc, **okw)
     ref = og.gradient(sc.Yl.astype(np.float64), sc.Yh.astype(np.float64), pr, 5, sc.Z,

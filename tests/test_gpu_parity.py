@@ -105,6 +105,47 @@ def test_blur_stages(name):
     assert rel_rmse(host(out), o.blur_T(X, pr.b)) < 1e-6
 
 
+def blur_of_kind(kind, r, seed):
+    """Normalised (2r+1)^2 taps: a Gaussian (symmetric, rank one), an asymmetric rank-one
+    outer product, or a general asymmetric kernel (full rank)."""
+    rng = np.random.default_rng(seed)
+    w = 2 * r + 1
+    if kind == "gaussian":
+        b = synth.gaussian_blur_taps(r, 0.6 * r + 0.5)
+    elif kind == "rank_one":
+        b = np.outer(rng.uniform(0.1, 1.0, w), rng.uniform(0.1, 1.0, w))
+    else:
+        b = rng.uniform(0.0, 1.0, (w, w))
+    return np.asarray(b / b.sum(), dtype=np.float32)
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "rank_one", "general"])
+@pytest.mark.parametrize("r", [1, 3, 8, 13])
+def test_blur_stages_by_kind(kind, r):
+    """Rank-one blurs run as a row and a column pass, others as the full 2-D sum; both
+    directions (B and B^T) of both forms, with asymmetric kernels so that a swapped
+    direction fails, and radii from four template classes."""
+    sc = synth.make_scene(synth.small_spec(p=48, q=72, L=3, Lh=1, d=2, blur_radius=r, K=1,
+                                           Sw=1, iters=2, seed=31, tile=8))
+    b = blur_of_kind(kind, r, 40 + r)
+    plan = nlpr.Plan.from_scene(sc, blur=b)
+    assert plan.info().blur_separable == (kind != "general")
+    X = f32(np.random.default_rng(2).uniform(-1, 1, (3, 48, 72)))
+    out = torch.empty_like(dev(X))
+    plan.stage(nlpr.STAGE_BLUR, [dev(X), out])
+    assert rel_rmse(host(out), o.blur(X, b.astype(np.float64))) < 1e-6
+    plan.stage(nlpr.STAGE_BLUR_T, [dev(X), out])
+    assert rel_rmse(host(out), o.blur_T(X, b.astype(np.float64))) < 1e-6
+
+
+@pytest.mark.parametrize("kind", ["rank_one", "general"])
+def test_solve_with_asymmetric_blur_matches_oracle(kind):
+    sc = scene_for("ragged", iters=10)
+    b = blur_of_kind(kind, 2, 7)
+    z, _, _ = solve_gpu(sc, blur=b)
+    assert rel_rmse(z, solve_oracle(sc, b=b.astype(np.float64))) <= 1e-4
+
+
 @pytest.mark.parametrize("name", list(SHAPES))
 def test_pupdate_stage(name):
     sc = scene_for(name)
