@@ -26,7 +26,7 @@ X in R^{n_h x L} (one row per pixel).  Here images are stored planar,
 ``X[c][i1][i2]`` (band, row, col), and converted to the paper's matrix form by
 ``to_mat`` whenever a formula multiplies on the band axis.
 
-Readings of points the paper leaves open (each one is listed in the design doc):
+Readings of points the paper leaves open:
   * The subspace basis E (L_s x L, Z = X E) is optional; without it E = I and X is Z.
   * With a basis, the default start is the least-squares coefficient image of the
     upsampled Y_l: X0 = up(Y_l) E^T (E E^T)^{-1}.

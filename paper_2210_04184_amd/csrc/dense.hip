@@ -131,104 +131,113 @@ __global__ void fused_tables_kernel(int p, int q, int d, const float* blur, int 
     }
 }
 
-// G = (ratio I + R^T R)^{-1}, L_h x L_h, ratio = rho / lambda1, by Gauss-Jordan elimination
-// with partial pivoting in FP64 (one thread; L_h <= 16).
-__global__ void g_kernel(const float* R, int L, int Lh, double ratio, float* G) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double A[kMaxLh][2 * kMaxLh];
-  for (int a = 0; a < Lh; ++a) {
-    for (int b = 0; b < Lh; ++b) {
-      double s = 0.0;
-      for (int c = 0; c < L; ++c) s += (double)R[c * Lh + a] * (double)R[c * Lh + b];
-      A[a][b] = s + (a == b ? ratio : 0.0);
-      A[a][Lh + b] = (a == b) ? 1.0 : 0.0;
+// Gauss-Jordan inversion with partial pivoting in FP64, by one workgroup: A is n x 2n in LDS
+// (row stride 2 NM), [matrix | I] on entry and [I | inverse] on return.  One thread picks
+// the pivot (largest magnitude, first on ties); every element then takes the same sequence
+// of operations as in the textbook serial loop.
+template <int NM>
+__device__ void gauss_jordan_block(double* A, int n) {
+  constexpr int RS = 2 * NM;
+  __shared__ int piv_s;
+  __shared__ double f[NM];
+  const int n2 = 2 * n;
+  for (int col = 0; col < n; ++col) {
+    if (threadIdx.x == 0) {
+      int piv = col;
+      for (int r = col + 1; r < n; ++r)
+        if (fabs(A[r * RS + col]) > fabs(A[piv * RS + col])) piv = r;
+      piv_s = piv;
     }
-  }
-  for (int col = 0; col < Lh; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < Lh; ++r)
-      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    __syncthreads();
+    const int piv = piv_s;
     if (piv != col)
-      for (int j = 0; j < 2 * Lh; ++j) {
-        const double t = A[col][j];
-        A[col][j] = A[piv][j];
-        A[piv][j] = t;
+      for (int j = threadIdx.x; j < n2; j += blockDim.x) {
+        const double t = A[col * RS + j];
+        A[col * RS + j] = A[piv * RS + j];
+        A[piv * RS + j] = t;
       }
-    const double inv = 1.0 / A[col][col];
-    for (int j = 0; j < 2 * Lh; ++j) A[col][j] *= inv;
-    for (int r = 0; r < Lh; ++r) {
-      if (r == col) continue;
-      const double f = A[r][col];
-      if (f != 0.0)
-        for (int j = 0; j < 2 * Lh; ++j) A[r][j] -= f * A[col][j];
+    __syncthreads();
+    const double inv = 1.0 / A[col * RS + col];
+    __syncthreads();                       // every thread has read the pivot
+    for (int j = threadIdx.x; j < n2; j += blockDim.x) A[col * RS + j] *= inv;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) f[r] = 0.0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+      if (r != col) f[r] = A[r * RS + col];  // factors before any row changes
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n2; e += blockDim.x) {
+      const int r = e / n2, j = e - (e / n2) * n2;
+      if (f[r] != 0.0) A[r * RS + j] -= f[r] * A[col * RS + j];
     }
+    __syncthreads();
   }
-  for (int a = 0; a < Lh; ++a)
-    for (int b = 0; b < Lh; ++b) G[a * Lh + b] = (float)A[a][Lh + b];
 }
 
-// With a subspace basis E (Ls x L), in FP64 (one thread; Ls <= 32):
+// G = (ratio I + R^T R)^{-1}, L_h x L_h, ratio = rho / lambda1, in FP64 (one workgroup).
+__global__ void __launch_bounds__(256) g_kernel(const float* R, int L, int Lh, double ratio,
+                                                float* G) {
+  __shared__ double A[kMaxLh * 2 * kMaxLh];
+  for (int e = threadIdx.x; e < Lh * Lh; e += blockDim.x) {
+    const int a = e / Lh, b = e - (e / Lh) * Lh;
+    double s = 0.0;
+    for (int c = 0; c < L; ++c) s += (double)R[c * Lh + a] * (double)R[c * Lh + b];
+    A[a * 2 * kMaxLh + b] = s + (a == b ? ratio : 0.0);
+    A[a * 2 * kMaxLh + Lh + b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  gauss_jordan_block<kMaxLh>(A, Lh);
+  for (int e = threadIdx.x; e < Lh * Lh; e += blockDim.x) {
+    const int a = e / Lh, b = e - (e / Lh) * Lh;
+    G[a * Lh + b] = (float)A[a * 2 * kMaxLh + Lh + b];
+  }
+}
+
+// With a subspace basis E (Ls x L), in FP64 (one workgroup; Ls <= 32):
 //   M  = (E E^T + rho I)^{-1}            Ls x Ls   (P1-update, eq. (Qh_update))
 //   Ep = E^T (E E^T)^{-1}                L x Ls    (default start X0 = up(Y_l) Ep)
 //   Rt = E R                             Ls x Lh   (P2-update with E R in place of R)
-__device__ void gauss_jordan(double (*A)[2 * kMaxLs], int n) {
-  for (int col = 0; col < n; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < n; ++r)
-      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
-    if (piv != col)
-      for (int j = 0; j < 2 * n; ++j) {
-        const double t = A[col][j];
-        A[col][j] = A[piv][j];
-        A[piv][j] = t;
-      }
-    const double inv = 1.0 / A[col][col];
-    for (int j = 0; j < 2 * n; ++j) A[col][j] *= inv;
-    for (int r = 0; r < n; ++r) {
-      if (r == col) continue;
-      const double f = A[r][col];
-      if (f != 0.0)
-        for (int j = 0; j < 2 * n; ++j) A[r][j] -= f * A[col][j];
-    }
+__global__ void __launch_bounds__(256) subspace_kernel(const float* E, const float* R, int L,
+                                                       int Ls, int Lh, double rho, float* M,
+                                                       float* Ep, float* Rt) {
+  constexpr int RS = 2 * kMaxLs;
+  __shared__ double A[kMaxLs * RS];
+  __shared__ double EEt[kMaxLs * kMaxLs];
+  for (int e = threadIdx.x; e < Ls * Ls; e += blockDim.x) {
+    const int a = e / Ls, b = e - (e / Ls) * Ls;
+    double s = 0.0;
+    for (int c = 0; c < L; ++c) s += (double)E[a * L + c] * (double)E[b * L + c];
+    EEt[a * kMaxLs + b] = s;
   }
-}
-
-__global__ void subspace_kernel(const float* E, const float* R, int L, int Ls, int Lh, double rho,
-                                float* M, float* Ep, float* Rt) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double A[kMaxLs][2 * kMaxLs];
-  double EEt[kMaxLs][kMaxLs];
-  for (int a = 0; a < Ls; ++a)
-    for (int b = 0; b < Ls; ++b) {
-      double s = 0.0;
-      for (int c = 0; c < L; ++c) s += (double)E[a * L + c] * (double)E[b * L + c];
-      EEt[a][b] = s;
-    }
+  __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {      // pass 0: (E E^T + rho I)^{-1}; 1: (E E^T)^{-1}
-    for (int a = 0; a < Ls; ++a)
-      for (int b = 0; b < Ls; ++b) {
-        A[a][b] = EEt[a][b] + (pass == 0 && a == b ? rho : 0.0);
-        A[a][Ls + b] = (a == b) ? 1.0 : 0.0;
-      }
-    gauss_jordan(A, Ls);
+    for (int e = threadIdx.x; e < Ls * Ls; e += blockDim.x) {
+      const int a = e / Ls, b = e - (e / Ls) * Ls;
+      A[a * RS + b] = EEt[a * kMaxLs + b] + (pass == 0 && a == b ? rho : 0.0);
+      A[a * RS + Ls + b] = (a == b) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    gauss_jordan_block<kMaxLs>(A, Ls);
     if (pass == 0) {
-      for (int a = 0; a < Ls; ++a)
-        for (int b = 0; b < Ls; ++b) M[a * Ls + b] = (float)A[a][Ls + b];
+      for (int e = threadIdx.x; e < Ls * Ls; e += blockDim.x) {
+        const int a = e / Ls, b = e - (e / Ls) * Ls;
+        M[a * Ls + b] = (float)A[a * RS + Ls + b];
+      }
     } else {
-      for (int c = 0; c < L; ++c)
-        for (int b = 0; b < Ls; ++b) {
-          double s = 0.0;
-          for (int a = 0; a < Ls; ++a) s += (double)E[a * L + c] * A[a][Ls + b];
-          Ep[c * Ls + b] = (float)s;
-        }
+      for (int e = threadIdx.x; e < L * Ls; e += blockDim.x) {
+        const int c = e / Ls, b = e - (e / Ls) * Ls;
+        double s = 0.0;
+        for (int a = 0; a < Ls; ++a) s += (double)E[a * L + c] * A[a * RS + Ls + b];
+        Ep[c * Ls + b] = (float)s;
+      }
     }
+    __syncthreads();
   }
-  for (int a = 0; a < Ls; ++a)
-    for (int h = 0; h < Lh; ++h) {
-      double s = 0.0;
-      for (int c = 0; c < L; ++c) s += (double)E[a * L + c] * (double)R[c * Lh + h];
-      Rt[a * Lh + h] = (float)s;
-    }
+  for (int e = threadIdx.x; e < Ls * Lh; e += blockDim.x) {
+    const int a = e / Lh, h = e - (e / Lh) * Lh;
+    double s = 0.0;
+    for (int c = 0; c < L; ++c) s += (double)E[a * L + c] * (double)R[c * Lh + h];
+    Rt[a * Lh + h] = (float)s;
+  }
 }
 
 // Y_l E^T and Y_l E^+ at every low-resolution pixel m: [Ls][p/d][q/d] each.
@@ -815,7 +824,7 @@ int launch_precompute(Plan& P) {
                      q, P.d_blur, P.prm.blur_radius, P.d_taus, P.npairs, P.npatch);
   NLPR_LAUNCH_CHECK("den_kernel");
   if (P.d_E) {
-    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(1), 0, nullptr, P.d_E, P.d_R, P.prm.L, P.Lx,
+    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(256), 0, nullptr, P.d_E, P.d_R, P.prm.L, P.Lx,
                        P.prm.Lh, P.prm.rho, P.d_M, P.d_Ep, P.d_Rt);
     NLPR_LAUNCH_CHECK("subspace_kernel");
   }
@@ -826,7 +835,7 @@ int launch_precompute(Plan& P) {
                        P.prm.rho, P.d_fia, P.d_fu, P.d_fv);
     NLPR_LAUNCH_CHECK("fused_tables_kernel");
   }
-  hipLaunchKernelGGL(g_kernel, dim3(1), dim3(1), 0, nullptr, P.d_E ? P.d_Rt : P.d_R, P.Lx,
+  hipLaunchKernelGGL(g_kernel, dim3(1), dim3(256), 0, nullptr, P.d_E ? P.d_Rt : P.d_R, P.Lx,
                      P.prm.Lh, P.prm.rho / P.prm.lambda1, P.d_G);
   NLPR_LAUNCH_CHECK("g_kernel");
   return NLPR_OK;

@@ -4,7 +4,7 @@ Inputs are the seeded synthetic scenes (rounded once to float32); the oracle rea
 float32 values as float64.  Shapes cover radix 2/3/4/8 transforms, several sweep tiles with
 a ragged last tile, a tile shorter than the halo, odd band counts and 1..4 guide bands.
 
-Tolerances.  The spec bar for the solve is a relative RMSE of 1e-4 on Z.  Single
+Tolerances.  The bar for the solve is a relative RMSE of 1e-4 on Z.  Single
 steps are held to what FP32 arithmetic gives: a few ulps times the depth of the sums.
 """
 import numpy as np
