@@ -73,15 +73,19 @@ def measured_traffic(config: str):
 
 
 def hbm_reference(gib: float):
-    """Plain torch copy and in-place negation over `gib` GiB buffers, event-timed: the
-    practical HBM ceiling for a streaming read+write, and the copy kernel of known size whose
-    FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures."""
+    """Plain torch copy and in-place negation, and the library's reference stream (in-place,
+    one 16-byte non-temporal load and store per thread, the sweep's access pattern), over
+    `gib` GiB buffers, event-timed on the current stream: the practical HBM ceilings for a
+    streaming read+write, and the copy kernel of known size whose FETCH_SIZE / WRITE_SIZE
+    counters calibrate the traffic figures."""
     import torch
     n = int(gib * 1024 ** 3) // 4
     x = torch.ones(n, device="cuda")
     y = torch.empty_like(x)
     out = {}
-    for name, fn in (("copy", lambda: y.copy_(x)), ("inplace_rmw", lambda: x.neg_())):
+    from paper_2210_04184_amd import nlpr
+    for name, fn in (("copy", lambda: y.copy_(x)), ("inplace_rmw", lambda: x.neg_()),
+                     ("inplace_rmw_nt16", lambda: nlpr.stream_rmw(x))):
         fn()
         torch.cuda.synchronize()
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

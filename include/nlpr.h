@@ -77,7 +77,8 @@ enum {
                                    aliasing group of d^2 frequencies (Sherman-Morrison, tables in
                                    FP64).  Same minimiser as the paper's splitting of eq.
                                    (fusionoptim), different iterates.  Requires Ls == 0 and
-                                   8 * d * p <= 65536 (a column group fits one FFT workgroup).  */
+                                   8 * (d + 1) * p <= 65536 (a column group and the twiddles fit
+                                   one FFT workgroup).  */
 };
 
 /*
@@ -349,6 +350,16 @@ int nlpr_batch_stage_time(nlpr_batch* batch, int stage, double* ms_total, int64_
 int nlpr_batch_monitor(const nlpr_batch* batch, int32_t scene, double* trace, int32_t cap,
                        int32_t* n);
 int nlpr_batch_destroy(nlpr_batch* batch);
+
+/*
+ * Reference stream for the HBM roofline, not part of the method: negates the `bytes / 4`
+ * floats at `buf` in place with one 16-byte non-temporal load and store per thread, the
+ * access pattern of the dual sweep, so that its rate is the practical ceiling the sweep is
+ * held against.  buf: device memory, 16-byte aligned; bytes: a multiple of 16, at most
+ * 2^31 * 4096.  Asynchronous on `stream`.  NLPR_ERR_INVALID_ARG for a null, host or
+ * misaligned buffer or a bad size.
+ */
+int nlpr_stream_rmw(void* buf, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

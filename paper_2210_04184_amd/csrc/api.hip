@@ -87,7 +87,8 @@ int validate(const nlpr_params& q) {
   if ((q.flags & NLPR_LOCAL_WINDOW) && q.Sw != 1) return bad("NLPR_LOCAL_WINDOW needs Sw == 1");
   if (q.flags & NLPR_FUSED_S) {
     if (q.Ls != 0) return bad("NLPR_FUSED_S takes no subspace basis (Ls must be 0)");
-    if ((size_t)8 * q.d * q.p > 65536) return bad("NLPR_FUSED_S needs 8 * d * p <= 65536");
+    // the column pass holds d columns of p points and a line of twiddles in 64 KiB of LDS
+    if ((size_t)8 * (q.d + 1) * q.p > 65536) return bad("NLPR_FUSED_S needs 8 * (d + 1) * p <= 65536");
   }
   if (q.iters < 0) return fail(NLPR_ERR_INVALID_ARG, "iters must be >= 0");
   if (!(q.lambda >= 0.0) || !std::isfinite(q.lambda)) return fail(NLPR_ERR_INVALID_ARG, "lambda must be >= 0");
@@ -1223,6 +1224,19 @@ int nlpr_batch_destroy(nlpr_batch* batch) {
   batch_release(batch->B);
   delete batch;
   return NLPR_OK;
+}
+
+int nlpr_stream_rmw(void* buf, size_t bytes, void* stream) {
+  int rc = check_device_ptr(buf, "buf");
+  if (rc) return rc;
+  if (reinterpret_cast<uintptr_t>(buf) % 16 || bytes % 16)
+    return fail(NLPR_ERR_INVALID_ARG, "buf must be 16-byte aligned and bytes a multiple of 16");
+  if (bytes / 16 > (size_t)0x7fffffff * 256)
+    return fail(NLPR_ERR_INVALID_ARG, "bytes exceeds 2^31 * 4096");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, buf) != hipSuccess) return fail(NLPR_ERR_HIP, "hipPointerGetAttributes failed");
+  DeviceGuard g(attr.device);
+  return launch_stream_rmw(static_cast<float*>(buf), bytes / 16, static_cast<hipStream_t>(stream));
 }
 
 int nlpr_batch_workspace_size(const nlpr_batch* batch, size_t* bytes) {

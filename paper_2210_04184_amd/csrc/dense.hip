@@ -795,6 +795,15 @@ int launch_groups(const Batch& B, Kind kind, const char* name, Kern kern, hipStr
 int weights_blocks(const Plan& P) {
   return ceil_div(P.prm.q, WT_X) * ceil_div(P.prm.p, WT_Y) * P.npairs;
 }
+// Reference stream: one 16-byte non-temporal load and store per thread, in place.
+__global__ void __launch_bounds__(256) stream_rmw_kernel(float* buf, size_t n4) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n4) return;
+  gv4f* p = reinterpret_cast<gv4f*>(as_global(buf)) + i;
+  const v4f_t v = __builtin_nontemporal_load(p);
+  __builtin_nontemporal_store(-v, p);
+}
+
 size_t weights_lds(const Plan& P) {
   const int K = P.prm.K;
   return (size_t)((WT_Y + 2 * K) * (WT_X + 2 * K) + (WT_Y + 2 * K) * WT_X) * sizeof(float);
@@ -851,6 +860,14 @@ int launch_init(const Batch& B, int yl, int ylp, int x0, int l1, int l2, int w2,
 
 int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s) {
   return launch_groups(B, KD_PLANE, "upsample_zero_kernel", upsample_zero_kernel, s, yl, t);
+}
+
+int launch_stream_rmw(float* buf, size_t n4, hipStream_t s) {
+  if (!n4) return NLPR_OK;
+  hipLaunchKernelGGL(stream_rmw_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, buf,
+                     n4);
+  NLPR_LAUNCH_CHECK("stream_rmw_kernel");
+  return NLPR_OK;
 }
 
 int launch_fill(const Batch& B, int slot_, hipStream_t s) {

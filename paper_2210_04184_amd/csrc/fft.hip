@@ -96,11 +96,12 @@ template <bool INV> struct Dft<3, INV> {
 };
 
 // One Stockham stage of radix R on a line of n points in LDS.  Ns is the product of the
-// radices of the earlier stages.  Threads t < tpl of the line take part; tpl >= ceil(n/8)
-// keeps every thread at <= ceil(8/R) butterflies.  All threads of the block must call it.
+// radices of the earlier stages; tw holds the line's n twiddles, staged in LDS.  Threads
+// t < tpl of the line take part; tpl >= ceil(n/8) keeps every thread at <= ceil(8/R)
+// butterflies.  All threads of the block must call it.
 template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(float2* buf, int n, int Ns, const gfloat* __restrict__ tw, int t,
-                          int tpl) {
+__device__ __forceinline__ void fft_stage(float2* buf, int n, int Ns, const float2* tw, int t,
+                                          int tpl) {
   constexpr int MAXB = (8 + R - 1) / R;
   const int nb = n / R;
   float2 v[MAXB][R];
@@ -121,7 +122,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int Ns, const gflo
       const int k = j % Ns;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = ldg2(tw + 2 * (r * k * step));
+        float2 w = tw[r * k * step];
         if (INV) w.y = -w.y;
         v[u][r] = cmul(v[u][r], w);
       }
@@ -134,12 +135,19 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int Ns, const gflo
   __syncthreads();
 }
 
+// Twiddles of a line length, copied from the FP64-computed table to LDS (before the
+// barrier that follows the data load) so the stages read them without global latency.
+__device__ __forceinline__ void stage_twiddles(float2* twl, const LineFFT& f) {
+  const gfloat* tw = (const gfloat*)f.tw;
+  for (int e = threadIdx.x; e < f.n; e += blockDim.x) twl[e] = ldg2(tw + 2 * e);
+}
+
 template <bool INV>
-__device__ __forceinline__ void fft_line(float2* buf, const LineFFT& f, int t, int tpl) {
+__device__ __forceinline__ void fft_line(float2* buf, const LineFFT& f, int t, int tpl,
+                                         const float2* tw) {
   int Ns = 1;
   for (int s = 0; s < f.nfac; ++s) {
     const int R = f.fac[s];
-    const gfloat* tw = (const gfloat*)f.tw;
     if (R == 8) fft_stage<8, INV>(buf, f.n, Ns, tw, t, tpl);
     else if (R == 4) fft_stage<4, INV>(buf, f.n, Ns, tw, t, tpl);
     else if (R == 2) fft_stage<2, INV>(buf, f.n, Ns, tw, t, tpl);
@@ -159,6 +167,8 @@ __global__ void fft_rows_fwd(const SceneDesc* __restrict__ sd, const int2* __res
   const int m = it.y / nrb, row0 = (it.y - m * nrb) * lpb;
   const size_t plane = (size_t)p * q;
   const gfloat* C = gslot<const gfloat>(S, c_s);
+  float2* twl = sh + lpb * q;
+  stage_twiddles(twl, S.fq);
   const gfloat* Ca = C + (size_t)(2 * m) * plane;
   const gfloat* Cb = (2 * m + 1 < L) ? C + (size_t)(2 * m + 1) * plane : nullptr;
   // 16-byte loads (4 points of a row; q % 4 == 0) when the buffer allows, else 4-byte ones
@@ -191,7 +201,7 @@ __global__ void fft_rows_fwd(const SceneDesc* __restrict__ sd, const int2* __res
   __syncthreads();
   const int g = threadIdx.x / tpl;
   const int t = (g < lpb) ? threadIdx.x - g * tpl : tpl;
-  fft_line<false>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl);
+  fft_line<false>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl, twl);
   gfloat* Fm = gslot<gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex, interleaved
   const int q2 = q >> 1;                // two complex points per 16-byte store
   for (int e = threadIdx.x; e < lpb * q2; e += blockDim.x) {
@@ -221,6 +231,8 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
   const int m = it.y / ncb, cblk = it.y - m * ncb;
   const size_t plane = (size_t)p * q;
   gfloat* Fm = gslot<gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex, interleaved
+  float2* twl = sh + cb * p;
+  stage_twiddles(twl, S.fp);
   const int d = S.d, cbb = S.fused ? cb / d : cb, qd = q / d;
   // column of LDS line l (-1: past the image)
   auto column = [&](int l) -> int {
@@ -265,7 +277,7 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
       const bool act = (g < G) && (l < cb);
       const int t = act ? tl : tpl;
       float2* line = sh + (act ? l : 0) * p;
-      fft_line<false>(line, S.fp, t, tpl);
+      fft_line<false>(line, S.fp, t, tpl, twl);
       const int col = act ? column(l) : -1;
       if (col >= 0) {
         for (int i = tl; i < p; i += tpl) {
@@ -274,13 +286,13 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
         }
       }
       __syncthreads();
-      fft_line<true>(line, S.fp, t, tpl);
+      fft_line<true>(line, S.fp, t, tpl, twl);
     }
   } else {
     for (int base = 0; base < cb; base += G) {
       const int l = base + g;
       const bool act = (g < G) && (l < cb);
-      fft_line<false>(sh + (act ? l : 0) * p, S.fp, act ? tl : tpl, tpl);
+      fft_line<false>(sh + (act ? l : 0) * p, S.fp, act ? tl : tpl, tpl, twl);
     }
     // group solves: (i1, base column) pairs, i1 fastest (tables are column-major)
     const int pd = p / d;
@@ -317,7 +329,7 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
     for (int base = 0; base < cb; base += G) {
       const int l = base + g;
       const bool act = (g < G) && (l < cb);
-      fft_line<true>(sh + (act ? l : 0) * p, S.fp, act ? tl : tpl, tpl);
+      fft_line<true>(sh + (act ? l : 0) * p, S.fp, act ? tl : tpl, tpl, twl);
     }
   }
   if (pairs) {
@@ -349,6 +361,8 @@ __global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __res
   const int m = it.y / nrb, row0 = (it.y - m * nrb) * lpb;
   const size_t plane = (size_t)p * q;
   const gfloat* Fm = gslot<const gfloat>(S, f_s) + 2 * (size_t)m * plane;   // complex
+  float2* twl = sh + lpb * q;
+  stage_twiddles(twl, S.fq);
   const int q2 = q >> 1;                // two complex points per 16-byte load
   for (int e = threadIdx.x; e < lpb * q2; e += blockDim.x) {
     const int l = e / q2, i2 = e - l * q2, r = row0 + l;
@@ -360,7 +374,7 @@ __global__ void fft_rows_inv(const SceneDesc* __restrict__ sd, const int2* __res
   __syncthreads();
   const int g = threadIdx.x / tpl;
   const int t = (g < lpb) ? threadIdx.x - g * tpl : tpl;
-  fft_line<true>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl);
+  fft_line<true>(sh + (g < lpb ? g : 0) * q, S.fq, t, tpl, twl);
   gfloat* X = gslot<gfloat>(S, x_s);
   gfloat* Xa = X + (size_t)(2 * m) * plane;
   gfloat* Xb = (2 * m + 1 < L) ? X + (size_t)(2 * m + 1) * plane : nullptr;
@@ -444,8 +458,9 @@ int rows_blocks(const Plan& P) {
 int cols_blocks(const Plan& P) {
   return ceil_div(P.prm.q, P.fft.p_cb) * ((P.Lx + 1) / 2);
 }
-size_t rows_lds(const Plan& P) { return (size_t)P.fft.q_lpb * P.prm.q * sizeof(float2); }
-size_t cols_lds(const Plan& P) { return (size_t)P.fft.p_cb * P.prm.p * sizeof(float2); }
+// data lines plus one line of twiddles
+size_t rows_lds(const Plan& P) { return (size_t)(P.fft.q_lpb + 1) * P.prm.q * sizeof(float2); }
+size_t cols_lds(const Plan& P) { return (size_t)(P.fft.p_cb + 1) * P.prm.p * sizeof(float2); }
 
 // d_fused > 0: the columns per block must be a multiple of d (a base column and its aliases)
 FftShape default_fft_shape(int p, int q, int d_fused) {
@@ -453,10 +468,11 @@ FftShape default_fft_shape(int p, int q, int d_fused) {
   f.q_tpl = ceil_div(q, 8);
   f.p_tpl = ceil_div(p, 8);
   f.q_lpb = fft_block(f.q_tpl) / f.q_tpl;
-  while (f.q_lpb > 1 && (size_t)f.q_lpb * q * sizeof(float2) > kFftLds) --f.q_lpb;
+  while (f.q_lpb > 1 && (size_t)(f.q_lpb + 1) * q * sizeof(float2) > kFftLds) --f.q_lpb;
   const int unit = d_fused > 0 ? d_fused : 1;
   f.p_cb = unit;
-  while (f.p_cb * 2 <= std::max(16, unit) && (size_t)f.p_cb * 2 * p * sizeof(float2) <= kFftLds)
+  while (f.p_cb * 2 <= std::max(16, unit) &&
+         (size_t)(f.p_cb * 2 + 1) * p * sizeof(float2) <= kFftLds)
     f.p_cb *= 2;
   return f;
 }
@@ -549,12 +565,12 @@ int autotune_fft(Plan& P) {
     const int tpl = best.q_tpl, bs = fft_block(tpl);
     float tbest = 1e30f;
     for (int lpb = 1; lpb <= bs / tpl; lpb *= 2) {
-      if ((size_t)lpb * q * sizeof(float2) > kFftLds) break;
+      if ((size_t)(lpb + 1) * q * sizeof(float2) > kFftLds) break;
       h.fq_tpl = tpl;
       h.fq_lpb = lpb;
       hipMemcpy(d_sd, &h, sizeof(SceneDesc), hipMemcpyHostToDevice);
       const int nb = ceil_div(p, lpb) * tp;
-      const size_t lds = (size_t)lpb * q * sizeof(float2);
+      const size_t lds = (size_t)(lpb + 1) * q * sizeof(float2);
       const float ms = time_it([&]() {
         hipLaunchKernelGGL(fft_rows_fwd, dim3(nb), dim3(bs), lds, nullptr, d_sd, d_items, (int)B_C,
                            (int)B_F);
@@ -570,12 +586,12 @@ int autotune_fft(Plan& P) {
     const int tpl = best.p_tpl, bs = fft_block(tpl);
     float tbest = 1e30f;
     for (int cb = std::max(dfu, 1); cb <= std::max(32, dfu); cb *= 2) {
-      if ((size_t)cb * p * sizeof(float2) > kFftLds) break;
+      if ((size_t)(cb + 1) * p * sizeof(float2) > kFftLds) break;
       h.fp_tpl = tpl;
       h.fp_cb = cb;
       hipMemcpy(d_sd, &h, sizeof(SceneDesc), hipMemcpyHostToDevice);
       const int nb = ceil_div(q, cb) * tp;
-      const size_t lds = (size_t)cb * p * sizeof(float2);
+      const size_t lds = (size_t)(cb + 1) * p * sizeof(float2);
       const float ms = time_it([&]() {
         hipLaunchKernelGGL(fft_cols_solve, dim3(nb), dim3(bs), lds, nullptr, d_sd, d_items,
                            (int)B_F);

@@ -282,6 +282,8 @@ int lh_class(int Lh);                // pupdate template class of a guide-band c
 // 131072, where one thread per pixel would leave most of the GPU idle, else 1
 inline int pixel_split(size_t pixels) { return pixels < 131072 ? 4 : 1; }
 int lowres_blocks(const Plan& P);
+// in-place negation of n4 float4 values with non-temporal 16-byte accesses (reference stream)
+int launch_stream_rmw(float* buf, size_t n4, hipStream_t s);
 // with a subspace basis: Y_l E^T and Y_l E^+ (once per solve), the P1-update on sampled
 // pixels, and Z = X E
 int launch_project(const Batch& B, int yl, int yle, int ylp, hipStream_t s);

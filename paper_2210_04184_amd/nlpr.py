@@ -64,7 +64,7 @@ EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlp
                    "nlpr_plan_get_info", "nlpr_batch_create", "nlpr_batch_workspace_size",
                    "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
                    "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor",
-                   "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward"])
+                   "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward", "nlpr_stream_rmw"])
 
 
 class NlprError(RuntimeError):
@@ -130,6 +130,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_grad_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.nlpr_forward.argtypes = [vp, vp, vp, vp, vp, sz, vp, sz, vp]
     lib.nlpr_backward.argtypes = [vp, vp, vp, vp, vp, sz, vp, sz, vp, sz, vp, vp, vp, vp]
+    lib.nlpr_stream_rmw.argtypes = [vp, sz, vp]
     for name in EXPORTED:
         if name not in ("nlpr_status_string", "nlpr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -159,6 +160,15 @@ def _stream_handle(stream) -> Optional[int]:
     if stream is None:
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
+
+
+def stream_rmw(buf, stream=None) -> None:
+    """Negate a float32 device tensor in place with the library's reference stream (one
+    16-byte non-temporal load and store per thread, the dual sweep's access pattern)."""
+    import torch
+    if buf.dtype != torch.float32:
+        raise TypeError("stream_rmw takes a float32 tensor")
+    _check(load().nlpr_stream_rmw(_ptr(buf), buf.numel() * 4, _stream_handle(stream)))
 
 
 class Plan:

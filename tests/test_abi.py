@@ -86,7 +86,8 @@ def _create(**over):
     (dict(Ls=9), nlpr.ERR_UNSUPPORTED_SHAPE),                         # more basis rows than bands
     (dict(Ls=2), nlpr.ERR_INVALID_ARG),                               # Ls without a basis
     (dict(monitor_every=-1), nlpr.ERR_INVALID_ARG),
-    (dict(flags=nlpr.FUSED_S, p=4096, q=64, d=4), nlpr.ERR_UNSUPPORTED_SHAPE),   # 8 d p > 64 KiB
+    (dict(flags=nlpr.FUSED_S, p=4096, q=64, d=4), nlpr.ERR_UNSUPPORTED_SHAPE),   # 8 (d+1) p > 64 KiB
+    (dict(flags=nlpr.FUSED_S, p=1024, q=64, d=8), nlpr.ERR_UNSUPPORTED_SHAPE),   # 73728 B: just over
 ])
 def test_invalid_parameters_are_rejected_on_the_host(over, code):
     rc, h, msg = _create(**over)

@@ -83,3 +83,23 @@ def test_largest_image_is_a_periodic_tiling_of_half_the_size():
     want = np.tile(host(Zs), (1, 2, 2))
     del small, Zs
     assert rel(host(Zb), want) <= 1e-5
+
+
+def test_reference_stream_negates_in_place_and_checks_its_arguments():
+    x = torch.randn(4 * 100003, device="cuda")
+    want = -x
+    nlpr.stream_rmw(x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, want)
+    import ctypes
+    lib = nlpr.load()
+    for bad in (torch.randn(10, device="cuda"),          # 40 bytes: not a multiple of 16
+                torch.randn(17, device="cuda")[1:]):     # 4 bytes past an aligned start
+        with pytest.raises(nlpr.NlprError) as e:
+            nlpr.stream_rmw(bad)
+        assert e.value.status == nlpr.ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        nlpr.stream_rmw(torch.zeros(16))
+    host = np.zeros(16, dtype=np.float32)
+    assert lib.nlpr_stream_rmw(host.ctypes.data_as(ctypes.c_void_p), 64, None) == nlpr.ERR_INVALID_ARG
+    assert lib.nlpr_stream_rmw(None, 64, None) == nlpr.ERR_INVALID_ARG
