@@ -289,6 +289,9 @@ def main():
     ap.add_argument("--subspace", type=int, default=0,
                     help="Ls > 0: solve for Z = X E with E the Ls leading right singular "
                          "vectors of Y_l")
+    ap.add_argument("--graph", action="store_true",
+                    help="solve through one captured HIP graph (stage timers off): the form "
+                         "for small, launch-bound scenes")
     ap.add_argument("--fused", action="store_true",
                     help="the splitting with S inside the X-update (no P1)")
     ap.add_argument("--monitor", type=int, default=0,
@@ -330,7 +333,7 @@ def main():
         M = sc.Yl.reshape(spec.L, -1).T.astype(np.float64)
         E = np.ascontiguousarray(np.linalg.svd(M, full_matrices=False)[2][:args.subspace],
                                  dtype=np.float32)
-    flags = nlpr.TIMING | (nlpr.FUSED_S if args.fused else 0)
+    flags = (nlpr.GRAPH if args.graph else nlpr.TIMING) | (nlpr.FUSED_S if args.fused else 0)
     plan = nlpr.Plan.from_scene(sc, flags=flags, E=E, monitor_every=args.monitor)
     npairs = len(plan.half_window())
     ws = plan.alloc_workspace()
@@ -340,8 +343,9 @@ def main():
         plan.solve(Yl, Yh, Z=Z, ws=ws)
         torch.cuda.synchronize()
         log(f"[bench] warmup {i + 1} done")
-    for st in nlpr.STAGE_NAMES:
-        plan.stage_time(st, reset=True)
+    if not args.graph:
+        for st in nlpr.STAGE_NAMES:
+            plan.stage_time(st, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step_s = []
@@ -354,7 +358,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stages = {}
-    for st, name in nlpr.STAGE_NAMES.items():
+    for st, name in ([] if args.graph else nlpr.STAGE_NAMES.items()):
         ms, n = plan.stage_time(st)
         if n:
             stages[name] = {"ms_total": round(ms, 3), "launches": n, "ms_avg": round(ms / n, 4)}
@@ -394,7 +398,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name(spec) + (f", subspace Ls={args.subspace}"
                                                       if args.subspace else "")
-                   + (", fused-S X-update" if args.fused else ""),
+                   + (", fused-S X-update" if args.fused else "")
+                   + (", one HIP graph" if args.graph else ""),
                    "p": spec.p, "q": spec.q, "L": spec.L, "Ls": args.subspace or spec.L,
                    "Lh": spec.Lh, "d": spec.d, "blur": 2 * spec.blur_radius + 1,
                    "patch": 2 * spec.K + 1, "window": 2 * spec.Sw + 1, "iters": spec.iters,
