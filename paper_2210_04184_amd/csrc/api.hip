@@ -761,6 +761,9 @@ int grad_check(const Batch& B) {
   if (P.npairs && (P.sweep.items != 1 || sweep_bwd_lds(P) > kMaxSweepLds))
     return fail(NLPR_ERR_UNSUPPORTED_SHAPE,
                 "the sweep adjoint needs q <= 1024 and its LDS tile within 160 KiB");
+  // the sweep adjoint gives each of its 256 threads one float4 of the tile
+  if (P.npairs && (size_t)P.sweep.rows * (P.prm.q / 4) > 256)
+    return fail(NLPR_ERR_UNSUPPORTED_SHAPE, "the sweep tile is larger than the adjoint's workgroup");
   return NLPR_OK;
 }
 
