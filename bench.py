@@ -255,6 +255,17 @@ def run_grad(args):
     t_solve = timed(lambda: plan.solve(Yl, Yh, Z=Z, ws=ws), args.steps)
     dYl, dYh, ds = grad_step()
     torch.cuda.synchronize()
+    # untimed check of the scalar gradients: central differences of the loss over plain
+    # solves at a relative step of 1e-3 (the loss is piecewise smooth; 1e-2 agreement)
+    def loss_at(**over):
+        Zs, _ = nlpr.Plan.from_scene(sc, **over).solve(Yl, Yh)
+        return float(torch.mean((Zs.double() - Zt) ** 2))
+    fd = {}
+    for i, (name, val) in enumerate((("lam", spec.lam), ("rho", spec.rho))):
+        h = 1e-3 * val
+        d = (loss_at(**{name: val + h}) - loss_at(**{name: val - h})) / (2 * h)
+        fd[name] = {"reverse": float(ds[i]), "central_difference": d,
+                    "rel_err": abs(float(ds[i]) - d) / max(abs(d), 1e-300)}
     pbi = spec.p * spec.q * spec.L * spec.iters
     out = {
         "metric": "ADMM pixel*band*iter/s (+ % HBM roofline) at <=1e-4 rel. RMSE vs FP64 oracle",
@@ -274,6 +285,7 @@ def run_grad(args):
         "checkpoint_bytes": ckb, "gradient_workspace_bytes": gwsb,
         "grads_finite": bool(torch.isfinite(dYl).all() and torch.isfinite(dYh).all()),
         "dlambda_drho": [float(x) for x in ds.cpu()],
+        "fd_check": fd,
     }
     print(json.dumps(out), flush=True)
 
