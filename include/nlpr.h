@@ -300,13 +300,14 @@ int nlpr_monitor(const nlpr_plan* plan, double* trace, int32_t cap, int32_t* n);
  * with the sweep adjoint's LDS tile within 160 KiB; else NLPR_ERR_UNSUPPORTED_SHAPE or
  * NLPR_ERR_INVALID_ARG.
  *
- * nlpr_grad_sizes: bytes of the checkpoint buffer (for t = 0 .. iters-1 the state entering
- *   iteration t+1: C, Lambda1, Lambda2 and, for t >= 1, Sigma') and of the gradient
- *   workspace.  Checkpoints take about iters * (3 + 2 Npairs |P|) * 4 * L * p * q bytes.
+ * nlpr_grad_sizes: bytes of the checkpoint buffer (for t = 1 .. iters-1: X^t, B X^t, the
+ *   Lambda1 and Lambda2 entering iteration t, and Sigma' after its sweep) and of the
+ *   gradient workspace.  Checkpoints take (iters - 1) * (4 + Npairs |P|) * 4 * L * p * q
+ *   bytes (at least 256).
  * nlpr_forward: like nlpr_solve (Z equal bit for bit) and also writes the checkpoints to ck
  *   (device, 256-byte aligned).  ws as for nlpr_solve.
- * nlpr_backward: given dZ = dloss/dZ (device, [L][p][q]), recomputes each iteration's X and
- *   B X from its checkpoint and carries the adjoints back; writes dYl ([L][p/d][q/d]),
+ * nlpr_backward: given dZ = dloss/dZ (device, [L][p][q]), reloads each iteration's X, B X
+ *   and Lambda from its checkpoint and carries the adjoints back; writes dYl ([L][p/d][q/d]),
  *   dYh ([Lh][p][q]) and dscal (device, 2 doubles: dloss/dlambda_2, dloss/drho).  ws, ck
  *   from the matching nlpr_forward (same Yl, Yh); gws: gradient workspace (device,
  *   256-byte aligned).  Never allocates; asynchronous on `stream`; sums run in a fixed

@@ -747,7 +747,8 @@ GradLayout grad_layout(const Plan& P) {
   const int T = P.prm.iters;
   G.plane_al = align256(pl);
   G.sig_al = P.npairs ? align256(P.sz[B_SIGMA]) : 0;
-  G.ck_bytes = (size_t)T * 3 * G.plane_al + (size_t)std::max(T - 1, 0) * G.sig_al;
+  // for t = 1 .. T-1: X^t, B X^t and the Lambda1, Lambda2 entering iteration t, then Sigma'
+  G.ck_bytes = std::max<size_t>(256, (size_t)std::max(T - 1, 0) * (4 * G.plane_al + G.sig_al));
   return G;
 }
 
@@ -767,34 +768,34 @@ int grad_check(const Batch& B) {
   return NLPR_OK;
 }
 
+// Checkpoint t (1 .. T-1) holds what the reverse step of iteration t reads: plane k = 0 X^t,
+// 1 B X^t, 2 Lambda1^{t-1}, 3 Lambda2^{t-1}; then Sigma' after the sweep of iteration t.
 char* ck_plane(void* ck, const GradLayout& G, int t, int k) {
-  return static_cast<char*>(ck) + ((size_t)t * 3 + k) * G.plane_al;
+  return static_cast<char*>(ck) + ((size_t)(t - 1) * 4 + k) * G.plane_al;
 }
 float* ck_sig(void* ck, const GradLayout& G, int T, int t) {
-  return reinterpret_cast<float*>(static_cast<char*>(ck) + (size_t)T * 3 * G.plane_al +
+  return reinterpret_cast<float*>(static_cast<char*>(ck) + (size_t)(T - 1) * 4 * G.plane_al +
                                   (size_t)(t - 1) * G.sig_al);
 }
 
-int save_state(const Plan& P, const GradLayout& G, char* ws, void* ck, int t, hipStream_t s) {
+// Copy the four planes of checkpoint t between the checkpoint buffer and their places in the
+// solve: X (the Z buffer of the pass), B X, Lambda1, Lambda2.
+int ck_copy(const Plan& P, const GradLayout& G, char* ws, const float* X, void* ck, int t,
+            bool save, hipStream_t s) {
   const size_t pl = (size_t)P.Lx * P.prm.p * P.prm.q * sizeof(float);
-  const int slots[3] = {B_C, B_L1, B_L2};
-  for (int k = 0; k < 3; ++k)
-    NLPR_HIP_TRY(hipMemcpyAsync(ck_plane(ck, G, t, k), ws + P.off[slots[k]], pl,
+  char* place[4] = {reinterpret_cast<char*>(const_cast<float*>(X)), ws + P.off[B_BX],
+                    ws + P.off[B_L1], ws + P.off[B_L2]};
+  for (int k = 0; k < 4; ++k) {
+    char* c = ck_plane(ck, G, t, k);
+    NLPR_HIP_TRY(hipMemcpyAsync(save ? c : place[k], save ? place[k] : c, pl,
                                 hipMemcpyDeviceToDevice, s));
-  return NLPR_OK;
-}
-
-int load_state(const Plan& P, const GradLayout& G, char* ws, void* ck, int t, hipStream_t s) {
-  const size_t pl = (size_t)P.Lx * P.prm.p * P.prm.q * sizeof(float);
-  const int slots[3] = {B_C, B_L1, B_L2};
-  for (int k = 0; k < 3; ++k)
-    NLPR_HIP_TRY(hipMemcpyAsync(ws + P.off[slots[k]], ck_plane(ck, G, t, k), pl,
-                                hipMemcpyDeviceToDevice, s));
+  }
   return NLPR_OK;
 }
 
 // Forward solve that keeps the checkpoints.  Z = X^T equals nlpr_solve's output bit for bit;
-// the last iteration stops after its X-update, the only part of it that reaches Z.
+// the last iteration stops after its X-update, the only part of it that reaches Z.  X^t and
+// B X^t are saved before the P-update of iteration t, together with the Lambda it reads.
 int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws, size_t ws_bytes,
                  void* ck, size_t ck_bytes, hipStream_t s) {
   int rc;
@@ -819,25 +820,24 @@ int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws,
   if ((rc = launch_init(B, B_YL, B_YLP, B_Z, B_L1, B_L2, B_W2, s))) return rc;
   if ((rc = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return rc;
   if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s))) return rc;
-  if ((rc = save_state(P, G, base, ck, 0, s))) return rc;
   for (int t = 1; t <= T; ++t) {
     if ((rc = launch_xsolve(B, B_C, B_Z, B_F, -1, s))) return rc;
     if (t == T) break;
     if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
+    if ((rc = ck_copy(P, G, base, Z, ck, t, true, s))) return rc;
     if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
     if (reg && (rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, t == 1, s,
                                   t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
                                   ck_sig(ck, G, T, t))))
       return rc;
     if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
-    if ((rc = save_state(P, G, base, ck, t, s))) return rc;
   }
   NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
   return NLPR_OK;
 }
 
-// Reverse pass: from Z' back through the T iterations (recomputing X and B X of each from
-// its checkpoint), the start and the weights.
+// Reverse pass: from Z' back through the T iterations (X, B X and the entering Lambda of
+// each from its checkpoint), the start and the weights.
 int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, void* ws,
                   size_t ws_bytes, void* ck, size_t ck_bytes, void* gws, size_t gws_bytes,
                   float* dYl, float* dYh, double* dscal, hipStream_t s) {
@@ -856,8 +856,9 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
     return fail(NLPR_ERR_WORKSPACE_TOO_SMALL, "workspace, checkpoint or gradient buffer too small");
   char* base = static_cast<char*>(ws);
   char* gb = static_cast<char*>(gws);
-  // X of each iteration is recomputed into the W2 region (W2 is not needed backwards)
-  SceneDesc d = solve_desc(P, base, Yl, Yh, reinterpret_cast<float*>(base + P.off[B_W2]));
+  // X of each iteration is reloaded into the W2 region (W2 is not needed backwards)
+  float* xb = reinterpret_cast<float*>(base + P.off[B_W2]);
+  SceneDesc d = solve_desc(P, base, Yl, Yh, xb);
   for (int k : {B_GC, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR, B_GSIG, B_GHALO, B_GMUP,
                 B_GMU, B_GE, B_GPART})
     d.buf[k] = gb + G.off[k];
@@ -883,9 +884,7 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
   // Z = X^T = solve(C^{T-1})
   if ((rc = launch_xsolve(B, B_GZ, B_GC, B_F, -1, s))) return rc;
   for (int t = T - 1; t >= 1; --t) {
-    if ((rc = load_state(P, G, base, ck, t - 1, s))) return rc;
-    if ((rc = launch_xsolve(B, B_C, B_Z, B_F, -1, s))) return rc;
-    if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
+    if ((rc = ck_copy(P, G, base, xb, ck, t, false, s))) return rc;   // X^t, B X^t, Lambda^{t-1}
     if ((rc = launch_conv(B, B_GC, B_GW1, false, -1, -1, -1, 0, s))) return rc;   // W1' = B C'
     if (reg && (rc = launch_sweep_bwd(B, B_Z, B_MU, B_GC, t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
                                       B_GSIG, B_GXR, B_GHALO, B_GMUP, t == 1, s)))
