@@ -604,7 +604,8 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     }
     {
       StageTimer tm(B, s, NLPR_STAGE_PUPDATE);
-      if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
+      if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, B_L1, B_L2, s)))
+        return rc;
       if (sub && (rc = launch_p1_subspace(B, B_BX, B_YLE, B_L1, B_W1, s))) return rc;
     }
     if (mon) {
@@ -633,6 +634,8 @@ SceneDesc solve_desc(const Plan& P, char* base, const float* Yl, const float* Yh
   SceneDesc d = static_desc(P);
   for (int k : {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO})
     d.buf[k] = base + P.off[k];
+  d.buf[B_L1O] = d.buf[B_L1];
+  d.buf[B_L2O] = d.buf[B_L2];
   d.buf[B_YL] = const_cast<float*>(Yl);
   d.buf[B_YH] = const_cast<float*>(Yh);
   if (P.d_E) {                       // X lives in the workspace; Z = X E at the end
@@ -778,24 +781,11 @@ float* ck_sig(void* ck, const GradLayout& G, int T, int t) {
                                   (size_t)(t - 1) * G.sig_al);
 }
 
-// Copy the four planes of checkpoint t between the checkpoint buffer and their places in the
-// solve: X (the Z buffer of the pass), B X, Lambda1, Lambda2.
-int ck_copy(const Plan& P, const GradLayout& G, char* ws, const float* X, void* ck, int t,
-            bool save, hipStream_t s) {
-  const size_t pl = (size_t)P.Lx * P.prm.p * P.prm.q * sizeof(float);
-  char* place[4] = {reinterpret_cast<char*>(const_cast<float*>(X)), ws + P.off[B_BX],
-                    ws + P.off[B_L1], ws + P.off[B_L2]};
-  for (int k = 0; k < 4; ++k) {
-    char* c = ck_plane(ck, G, t, k);
-    NLPR_HIP_TRY(hipMemcpyAsync(save ? c : place[k], save ? place[k] : c, pl,
-                                hipMemcpyDeviceToDevice, s));
-  }
-  return NLPR_OK;
-}
-
 // Forward solve that keeps the checkpoints.  Z = X^T equals nlpr_solve's output bit for bit;
-// the last iteration stops after its X-update, the only part of it that reaches Z.  X^t and
-// B X^t are saved before the P-update of iteration t, together with the Lambda it reads.
+// the last iteration stops after its X-update, the only part of it that reaches Z.  Nothing
+// is copied: before each iteration the descriptor's slots are re-pointed so that the X-update
+// and the blur write X^t and B X^t into checkpoint t, and the P-update reads the Lambda of
+// checkpoint t and writes the new Lambda into checkpoint t+1 (the workspace after the last).
 int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws, size_t ws_bytes,
                  void* ck, size_t ck_bytes, hipStream_t s) {
   int rc;
@@ -816,16 +806,38 @@ int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws,
   if ((rc = upload_desc(B, descs, s))) return rc;
   const int T = B.iters;
   const bool reg = P.npairs > 0;
+  B.desc_valid = false;          // the slots below change the device copy
+  auto plane = [&](int t, int k) -> void* { return ck_plane(ck, G, t, k); };
+  void* wl1 = base + P.off[B_L1];
+  void* wl2 = base + P.off[B_L2];
   if ((rc = launch_weights(B, B_YH, B_MU, s))) return rc;
+  if (T > 1) {                   // the start's Lambda (zeros) goes into checkpoint 1
+    SlotSet st;
+    st.add(B_L1, plane(1, 2));
+    st.add(B_L2, plane(1, 3));
+    if ((rc = launch_set_slots(B, st, s))) return rc;
+  }
   if ((rc = launch_init(B, B_YL, B_YLP, B_Z, B_L1, B_L2, B_W2, s))) return rc;
   if ((rc = launch_conv(B, B_Z, B_W1, false, -1, -1, -1, 0, s))) return rc;
   if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, -1, -1, 0, s))) return rc;
   for (int t = 1; t <= T; ++t) {
+    if (T > 1) {
+      SlotSet st;
+      st.add(B_Z, t < T ? plane(t, 0) : static_cast<void*>(Z));
+      if (t < T) {
+        st.add(B_BX, plane(t, 1));
+        st.add(B_L1, plane(t, 2));
+        st.add(B_L2, plane(t, 3));
+        st.add(B_L1O, t + 1 < T ? plane(t + 1, 2) : wl1);
+        st.add(B_L2O, t + 1 < T ? plane(t + 1, 3) : wl2);
+      }
+      if ((rc = launch_set_slots(B, st, s))) return rc;
+    }
     if ((rc = launch_xsolve(B, B_C, B_Z, B_F, -1, s))) return rc;
     if (t == T) break;
     if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
-    if ((rc = ck_copy(P, G, base, Z, ck, t, true, s))) return rc;
-    if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s))) return rc;
+    if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, B_L1O, B_L2O, s)))
+      return rc;
     if (reg && (rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, t == 1, s,
                                   t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
                                   ck_sig(ck, G, T, t))))
@@ -856,9 +868,8 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
     return fail(NLPR_ERR_WORKSPACE_TOO_SMALL, "workspace, checkpoint or gradient buffer too small");
   char* base = static_cast<char*>(ws);
   char* gb = static_cast<char*>(gws);
-  // X of each iteration is reloaded into the W2 region (W2 is not needed backwards)
-  float* xb = reinterpret_cast<float*>(base + P.off[B_W2]);
-  SceneDesc d = solve_desc(P, base, Yl, Yh, xb);
+  // X, B X and Lambda of each iteration are read from its checkpoint (slots re-pointed)
+  SceneDesc d = solve_desc(P, base, Yl, Yh, reinterpret_cast<float*>(base + P.off[B_W2]));
   for (int k : {B_GC, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR, B_GSIG, B_GHALO, B_GMUP,
                 B_GMU, B_GE, B_GPART})
     d.buf[k] = gb + G.off[k];
@@ -868,6 +879,7 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
   std::vector<SceneDesc> descs{d};
   DeviceGuard dg(B.device);
   if ((rc = upload_desc(B, descs, s))) return rc;
+  B.desc_valid = false;          // the checkpoint slots below change the device copy
   const int T = B.iters;
   const bool reg = P.npairs > 0;
   const int p = P.prm.p, q = P.prm.q, d_ = P.prm.d;
@@ -884,7 +896,10 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
   // Z = X^T = solve(C^{T-1})
   if ((rc = launch_xsolve(B, B_GZ, B_GC, B_F, -1, s))) return rc;
   for (int t = T - 1; t >= 1; --t) {
-    if ((rc = ck_copy(P, G, base, xb, ck, t, false, s))) return rc;   // X^t, B X^t, Lambda^{t-1}
+    SlotSet st;                  // X^t, B X^t and the Lambda entering iteration t
+    for (int k = 0; k < 4; ++k) st.add(k == 0 ? B_Z : k == 1 ? B_BX : k == 2 ? B_L1 : B_L2,
+                                       ck_plane(ck, G, t, k));
+    if ((rc = launch_set_slots(B, st, s))) return rc;
     if ((rc = launch_conv(B, B_GC, B_GW1, false, -1, -1, -1, 0, s))) return rc;   // W1' = B C'
     if (reg && (rc = launch_sweep_bwd(B, B_Z, B_MU, B_GC, t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
                                       B_GSIG, B_GXR, B_GHALO, B_GMUP, t == 1, s)))
@@ -1158,7 +1173,9 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
     case NLPR_STAGE_PUPDATE:
       put(B_Z, 0); put(B_BX, 1); put(B_YL, 2); put(B_YH, 3); put(B_L1, 4); put(B_L2, 5);
       put(B_W1, 6); put(B_W2, 7);
-      return run([&] { return launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, s); });
+      return run([&] {
+        return launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, B_L1, B_L2, s);
+      });
     case NLPR_STAGE_SWEEP:
     case NLPR_STAGE_SWEEP_FIRST:
       // Creg = the sweep's own-tile part (scratch TMP) + the folded halo rows, assembled by

@@ -667,13 +667,15 @@ __device__ __forceinline__ void pupdate_share(const gfloat* __restrict__ X,
   }
 }
 
-// Bands [c0, c1) of one pixel: P2, Lambda2, W2 and (per p1mode) P1, Lambda1, W1.  The
-// pointers arrive as restrict parameters so that the compiler may read R with scalar loads
-// across the stores (restrict on local pointer variables is not used for that).
+// Bands [c0, c1) of one pixel: P2, Lambda2, W2 and (per p1mode) P1, Lambda1, W1.  Lambda is
+// read through L1, L2 and written through L1o, L2o, which may be the same buffers (no
+// restrict on those four).  R arrives as a restrict parameter so that the compiler may read
+// it with scalar loads across the stores (restrict on local pointer variables is not used
+// for that).
 template <int LHM>
 __device__ __forceinline__ void pupdate_write(
     const gfloat* __restrict__ X, const gfloat* __restrict__ BX, const gfloat* __restrict__ Yl,
-    gfloat* __restrict__ L1, gfloat* __restrict__ L2, gfloat* __restrict__ W1,
+    const gfloat* L1, const gfloat* L2, gfloat* L1o, gfloat* L2o, gfloat* __restrict__ W1,
     gfloat* __restrict__ W2, const gfloat* __restrict__ R, const float (&u)[LHM], size_t plane,
     size_t lplane, size_t lj, bool sampled, int p1mode, int Lh, float rho, float inv_1prho,
     int c0, int c1, int j) {
@@ -686,13 +688,13 @@ __device__ __forceinline__ void pupdate_write(
     const float x = X[o], l2 = L2[o];
     const float p2 = (x - l2) + corr;
     const float l2n = l2 - (x - p2);
-    L2[o] = l2n;
+    L2o[o] = l2n;
     W2[o] = p2 + l2n;
     if (p1mode == 2 || (sampled && p1mode == 1)) continue;
     const float bx = BX[o], l1 = L1[o];
     const float p1 = sampled ? (rho * bx + Yl[c * lplane + lj] - rho * l1) * inv_1prho : bx - l1;
     const float l1n = l1 - (bx - p1);
-    L1[o] = l1n;
+    L1o[o] = l1n;
     W1[o] = p1 + l1n;
   }
 }
@@ -700,7 +702,8 @@ __device__ __forceinline__ void pupdate_write(
 template <int LHM, int PU_NC>
 __global__ void __launch_bounds__(256 * PU_NC)
 pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
-               int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1_s, int w2_s) {
+               int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1_s, int w2_s, int l1o_s,
+               int l2o_s) {
   __shared__ float part[PU_NC > 1 ? PU_NC : 1][PU_NC > 1 ? LHM : 1][PU_NC > 1 ? 256 : 1];
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
@@ -714,7 +717,7 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
   const bool act = j < (int)plane;
   const int c0 = (L * ch) / PU_NC, c1 = (L * (ch + 1)) / PU_NC;   // this thread's bands
   const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
-  gfloat* __restrict__ L2 = gslot<gfloat>(S, l2_s);
+  const gfloat* L2 = gslot<const gfloat>(S, l2_s);
   const gfloat* __restrict__ R = as_global(S.R);
   const gfloat* __restrict__ G = as_global(S.G);
   const gfloat* __restrict__ Yh = gslot<const gfloat>(S, yh_s);
@@ -771,7 +774,8 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
   // p1mode 1: a basis couples the sampled pixels across bands (p1_subspace_kernel);
   // p1mode 2: fused-S splitting, no P1
   pupdate_write<LHM>(X, gslot<const gfloat>(S, bx_s), gslot<const gfloat>(S, yl_s),
-                     gslot<gfloat>(S, l1_s), L2, gslot<gfloat>(S, w1_s), gslot<gfloat>(S, w2_s),
+                     gslot<const gfloat>(S, l1_s), L2, gslot<gfloat>(S, l1o_s),
+                     gslot<gfloat>(S, l2o_s), gslot<gfloat>(S, w1_s), gslot<gfloat>(S, w2_s),
                      R, u, plane, (size_t)(p / d) * (q / d),
                      (size_t)(i1 / d) * (q / d) + i2 / d, (i1 % d == 0) && (i2 % d == 0),
                      S.fused ? 2 : (S.subspace ? 1 : 0), Lh, S.rho, S.inv_1prho, c0, c1, j);
@@ -795,6 +799,12 @@ int launch_groups(const Batch& B, Kind kind, const char* name, Kern kern, hipStr
 int weights_blocks(const Plan& P) {
   return ceil_div(P.prm.q, WT_X) * ceil_div(P.prm.p, WT_Y) * P.npairs;
 }
+// Buffer slots of descriptor 0 re-pointed on the stream (one thread per slot).
+__global__ void set_slots_kernel(SceneDesc* sd, SlotSet set) {
+  const int i = threadIdx.x;
+  if (i < set.n) sd->buf[set.slot[i]] = set.ptr[i];
+}
+
 // Reference stream: one 16-byte non-temporal load and store per thread, in place.
 __global__ void __launch_bounds__(256) stream_rmw_kernel(float* buf, size_t n4) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -862,6 +872,13 @@ int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s) {
   return launch_groups(B, KD_PLANE, "upsample_zero_kernel", upsample_zero_kernel, s, yl, t);
 }
 
+int launch_set_slots(const Batch& B, const SlotSet& set, hipStream_t s) {
+  if (set.n <= 0) return NLPR_OK;
+  hipLaunchKernelGGL(set_slots_kernel, dim3(1), dim3(64), 0, s, B.d_desc, set);
+  NLPR_LAUNCH_CHECK("set_slots_kernel");
+  return NLPR_OK;
+}
+
 int launch_stream_rmw(float* buf, size_t n4, hipStream_t s) {
   if (!n4) return NLPR_OK;
   hipLaunchKernelGGL(stream_rmw_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, buf,
@@ -916,27 +933,27 @@ int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int a
 
 template <int LHM, int NC>
 void launch_pu(const Batch& B, const Group& g, int x, int bx, int yl, int yh, int l1, int l2,
-               int w1, int w2, hipStream_t s) {
+               int w1, int w2, int l1o, int l2o, hipStream_t s) {
   hipLaunchKernelGGL((pupdate_kernel<LHM, NC>), dim3(g.nitems), dim3(256 * NC), 0, s, B.d_desc,
-                     g.d_items, x, bx, yl, yh, l1, l2, w1, w2);
+                     g.d_items, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o);
 }
 
 int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,
-                   hipStream_t s) {
+                   int l1o, int l2o, hipStream_t s) {
   // one launch per guide-band class (key0 = 1, 4 or 16 register slots) and threads per
   // pixel (key1 = 1 or 4)
   for (const Group& g : B.groups[KD_PIXEL]) {
     if (!g.nitems) continue;
     const bool split = g.key1 == 4;
     if (g.key0 == 1) {
-      if (split) launch_pu<1, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
-      else launch_pu<1, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+      if (split) launch_pu<1, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o, s);
+      else launch_pu<1, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o, s);
     } else if (g.key0 == 4) {
-      if (split) launch_pu<4, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
-      else launch_pu<4, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+      if (split) launch_pu<4, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o, s);
+      else launch_pu<4, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o, s);
     } else {
-      if (split) launch_pu<kMaxLh, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
-      else launch_pu<kMaxLh, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, s);
+      if (split) launch_pu<kMaxLh, 4>(B, g, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o, s);
+      else launch_pu<kMaxLh, 1>(B, g, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o, s);
     }
     NLPR_LAUNCH_CHECK("pupdate_kernel");
   }

@@ -44,6 +44,7 @@ enum Slot {
   B_OUT,     // Z = X E when a subspace basis is used (B_Z is then the X iterate)
   B_YLE,     // Y_l E^T, [Ls][p/d][q/d]
   B_YLP,     // Y_l E^+, [Ls][p/d][q/d]
+  B_L1O, B_L2O,   // where the P-update writes Lambda1, Lambda2 when not in place (checkpoints)
   // reverse mode (single scene): adjoints of the iteration's variables and the outputs
   B_GZ,      // Z' (input)
   B_GC,      // C'
@@ -275,8 +276,19 @@ int launch_init(const Batch& B, int yl, int ylp, int x0, int l1, int l2, int w2,
 // scenes without a search window)
 int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int add2, int halo,
                 int reg_mask, hipStream_t s);
+// Lambda1, Lambda2 are read from slots l1, l2 and written to l1o, l2o (the same slots for an
+// update in place)
 int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,
-                   hipStream_t s);
+                   int l1o, int l2o, hipStream_t s);
+// Re-point buffer slots of the descriptor of scene 0 on the stream: kernels enqueued after it
+// see the new buffers.  The reverse-mode passes move through their checkpoints this way.
+struct SlotSet {
+  int n = 0;
+  int slot[6];
+  void* ptr[6];
+  void add(int sl, void* p) { slot[n] = sl; ptr[n] = p; ++n; }
+};
+int launch_set_slots(const Batch& B, const SlotSet& set, hipStream_t s);
 int lh_class(int Lh);                // pupdate template class of a guide-band count: 1, 4 or 16
 // threads per pixel of a P-update launch over `pixels` pixels in all: 4 (bands split) below
 // 131072, where one thread per pixel would leave most of the GPU idle, else 1
