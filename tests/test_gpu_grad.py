@@ -122,6 +122,26 @@ def test_forward_equals_solve_and_backward_repeats_bit_for_bit():
         assert torch.equal(x, y)
 
 
+def test_plain_solve_on_the_same_plan_after_reverse_mode():
+    """The reverse-mode passes re-point the plan's buffer slots at the checkpoints; a plain
+    solve on the same plan afterwards, with the very same workspace and output buffers (so
+    the host-side descriptor is unchanged), must use those buffers again."""
+    sc = scene(48, 36, 3, 3, 2, 1, 1, 1, iters=5)
+    plan = nlpr.Plan.from_scene(sc)
+    Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+    Zf, ws, ck = plan.forward(Yl, Yh)
+    dZ = torch.full_like(Zf, 1e-3)
+    first = [g.clone() for g in plan.backward(Yl, Yh, dZ, ws, ck)]
+    want = Zf.clone()
+    Zf.zero_()
+    plan.solve(Yl, Yh, Z=Zf, ws=ws)
+    assert torch.equal(Zf, want)
+    plan.forward(Yl, Yh, Z=Zf, ws=ws, ck=ck)
+    assert torch.equal(Zf, want)
+    for x, y in zip(first, plan.backward(Yl, Yh, dZ, ws, ck)):
+        assert torch.equal(x, y)
+
+
 def test_autograd_function_matches_the_plan_calls():
     sc = scene(32, 32, 4, 1, 4, 2, 1, 2, iters=5)
     Yl = dev(sc.Yl).requires_grad_()
