@@ -793,12 +793,6 @@ int launch_groups(const Batch& B, Kind kind, const char* name, Kern kern, hipStr
   return NLPR_OK;
 }
 
-}  // namespace
-
-// --------------------------------------------------------------------- work-item counts
-int weights_blocks(const Plan& P) {
-  return ceil_div(P.prm.q, WT_X) * ceil_div(P.prm.p, WT_Y) * P.npairs;
-}
 // Buffer slots of descriptor 0 re-pointed on the stream (one thread per slot).
 __global__ void set_slots_kernel(SceneDesc* sd, SlotSet set) {
   const int i = threadIdx.x;
@@ -814,6 +808,12 @@ __global__ void __launch_bounds__(256) stream_rmw_kernel(float* buf, size_t n4) 
   __builtin_nontemporal_store(-v, p);
 }
 
+}  // namespace
+
+// --------------------------------------------------------------------- work-item counts
+int weights_blocks(const Plan& P) {
+  return ceil_div(P.prm.q, WT_X) * ceil_div(P.prm.p, WT_Y) * P.npairs;
+}
 size_t weights_lds(const Plan& P) {
   const int K = P.prm.K;
   return (size_t)((WT_Y + 2 * K) * (WT_X + 2 * K) + (WT_Y + 2 * K) * WT_X) * sizeof(float);
