@@ -480,6 +480,9 @@ __global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
 // halo and the taps are zero-padded to (2 RM + 1)^2, so each thread keeps the 4 + 2 RM input
 // values of a tap row in registers and the tap loop is unrolled.  Padded taps add exact
 // zeros, so the sum equals the (2r+1)^2 one.
+// The tile comes in with 16-byte loads when RM is a multiple of 4 (its columns then start
+// on a multiple of 4 and q % 4 == 0, so no access straddles the wrap), else column by
+// column; tap rows are read from LDS as float4 when RM is even (rows of 64 + 2 RM floats).
 // A rank-one blur b = u v^T (S.bsep) runs as a pass along rows over the tile and its halo
 // rows, h = v * in, kept in LDS, then one along columns, out = u * h: 2 (2 RM + 1) instead of
 // (2 RM + 1)^2 multiply-adds per output.
@@ -526,15 +529,24 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
     }
     // tile with a circular RM halo: thread = column (coalesced), rows strided by 2; one wrap
     // of the column per thread, rows wrapped incrementally (TX <= 96 <= 128 columns)
-    const int lane = threadIdx.x & 127;
-    if (lane < TX) {
-      const int gxx = wrapi(x0 - RM + lane, q);
-      int yy = threadIdx.x >> 7;
-      int gyy = wrapi(y0 - RM + yy, p);
-      for (; yy < TY; yy += 2) {
-        tile[yy * TX + lane] = inc[(size_t)gyy * q + gxx];
-        gyy += 2;
-        if (gyy >= p) gyy -= p;   // p >= 8
+    if (RM % 4 == 0 && (reinterpret_cast<uintptr_t>(inc) & 15) == 0) {
+      constexpr int TX4 = TX / 4;
+      for (int e = threadIdx.x; e < TY * TX4; e += blockDim.x) {
+        const int yy = e / TX4, c4 = e - yy * TX4;
+        const int gyy = wrapi(y0 - RM + yy, p), gxx = wrapi(x0 - RM + 4 * c4, q);
+        *reinterpret_cast<float4*>(tile + yy * TX + 4 * c4) = ldg4(inc + (size_t)gyy * q + gxx);
+      }
+    } else {
+      const int lane = threadIdx.x & 127;
+      if (lane < TX) {
+        const int gxx = wrapi(x0 - RM + lane, q);
+        int yy = threadIdx.x >> 7;
+        int gyy = wrapi(y0 - RM + yy, p);
+        for (; yy < TY; yy += 2) {
+          tile[yy * TX + lane] = inc[(size_t)gyy * q + gxx];
+          gyy += 2;
+          if (gyy >= p) gyy -= p;   // p >= 8
+        }
       }
     }
     __syncthreads();
@@ -543,8 +555,16 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
       for (int yy = y; yy < TY; yy += CV_Y) {   // rows of the tile and of its halo
         const float* trow = tile + yy * TX + xb;
         float rv[4 + 2 * RM];
+        if constexpr (RM % 2 == 0) {
 #pragma unroll
-        for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+          for (int i4 = 0; i4 < (4 + 2 * RM) / 4; ++i4) {
+            const float4 v = reinterpret_cast<const float4*>(trow)[i4];
+            rv[4 * i4] = v.x; rv[4 * i4 + 1] = v.y; rv[4 * i4 + 2] = v.z; rv[4 * i4 + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+        }
         float hs[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int m2 = -RM; m2 <= RM; ++m2) {
@@ -571,8 +591,16 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
         const float* trow = tile + (TR ? (y + RM + m1) : (y + RM - m1)) * TX + xb;
         const float* tap = tp + (m1 + RM) * W2;
         float rv[4 + 2 * RM];
+        if constexpr (RM % 2 == 0) {
 #pragma unroll
-        for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+          for (int i4 = 0; i4 < (4 + 2 * RM) / 4; ++i4) {
+            const float4 v = reinterpret_cast<const float4*>(trow)[i4];
+            rv[4 * i4] = v.x; rv[4 * i4 + 1] = v.y; rv[4 * i4 + 2] = v.z; rv[4 * i4 + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4 + 2 * RM; ++i) rv[i] = trow[i];
+        }
 #pragma unroll
         for (int m2 = -RM; m2 <= RM; ++m2) {
           const float b = tap[m2 + RM];

@@ -286,7 +286,9 @@ struct SlotSet {
   int n = 0;
   int slot[6];
   void* ptr[6];
-  void add(int sl, void* p) { slot[n] = sl; ptr[n] = p; ++n; }
+  void add(int sl, void* p) {      // at most 6 (the callers add 2, 4 or 6)
+    if (n < 6) { slot[n] = sl; ptr[n] = p; ++n; }
+  }
 };
 int launch_set_slots(const Batch& B, const SlotSet& set, hipStream_t s);
 int lh_class(int Lh);                // pupdate template class of a guide-band count: 1, 4 or 16
