@@ -3,11 +3,12 @@ through T unrolled iterations, against the FP64 reference gradient (torch autogr
 the literal iteration, ``oracle.nlpr_grad``) and against central finite differences.
 
 Tolerances.  Against the FP64 reference: 1e-3 relative (L2 norm for the images), the bar
-the differentiated workload sets.  The FP32 finite differences are held to 1e-2.  For
-lambda_2 and rho they use a relative step of 1e-3.  For the images they use 1e-4: the loss
-is only piecewise smooth (every soft-threshold decision is a kink, and moving Y_h moves
-the thresholds), and at this workload a step of 1e-3 along Y_h already crosses enough
-kinks to move the quotient by about 3 % (0.3 % at 1e-4, measured).
+the differentiated workload sets.  Central differences of the FP32 loss at a relative step
+of 1e-3 are held to that bar for lambda_2 and rho (measured 1.5e-5 and 3.4e-4).  Along
+Y_l and Y_h they use a step of 1e-4 and a bar of 1e-2: the loss is only piecewise smooth
+(every soft-threshold decision is a kink, and moving Y_h moves the thresholds), and at
+this workload a step of 1e-3 along Y_h already crosses enough kinks to move the quotient
+by about 3 % (0.3 % at 1e-4, measured).
 """
 import numpy as np
 import pytest
@@ -165,7 +166,8 @@ def test_autograd_function_matches_the_plan_calls():
 def test_differentiated_workload_against_finite_differences():
     """256 x 256 x 31 bands, 3-band guide, 7x7 blur, d = 4, 3x3 patch and window, 20
     unrolled iterations: central differences at a relative step of 1e-3 for lambda_2 and
-    rho, and of 1e-4 along one random direction for Y_l and for Y_h."""
+    rho (held to 1e-3), and of 1e-4 along one random direction for Y_l and for Y_h (held
+    to 1e-2)."""
     sc = synth.make_scene(synth.config("c5"))
     loss, gYl, gYh, glam, grho, _ = gpu_grad(sc)
     assert np.isfinite(gYl).all() and np.isfinite(gYh).all()
@@ -178,7 +180,7 @@ def test_differentiated_workload_against_finite_differences():
     for name, val, g in (("lam", sc.spec.lam, glam), ("rho", sc.spec.rho, grho)):
         h = 1e-3 * val
         fd = (loss_at(**{name: val + h}) - loss_at(**{name: val - h})) / (2 * h)
-        assert g == pytest.approx(fd, rel=1e-2), name
+        assert g == pytest.approx(fd, rel=1e-3), name
     rng = np.random.default_rng(4)
     for name, arr, g in (("Yl", sc.Yl, gYl), ("Yh", sc.Yh, gYh)):
         v = rng.standard_normal(arr.shape)
