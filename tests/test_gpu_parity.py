@@ -244,6 +244,22 @@ def solve_oracle(sc, init="upsample", **kw):
     return o.solve(f32(sc.Yl), f32(sc.Yh), pr, sc.spec.iters, init=init).X
 
 
+def test_solve_matches_stored_oracle_anchor():
+    """The 12 x 12 x 3 regression anchor of tests/golden (inputs and the FP64 oracle's Z after
+    6 iterations stored together), solved without running the oracle."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_12x12x3.json")
+    with open(path) as f:
+        g = json.load(f)
+    plan = nlpr.Plan(g["p"], g["q"], g["L"], g["Lh"], g["d"], np.asarray(g["blur"]),
+                     np.asarray(g["R"]), g["K"], g["Sw"], g["iters"], g["lam"], g["rho"], g["h"],
+                     lam1=g["lam1"])
+    Z, _ = plan.solve(dev(np.asarray(g["Yl"])), dev(np.asarray(g["Yh"])))
+    assert rel_rmse(host(Z), np.asarray(g["Z"])) <= 1e-4
+
+
 def test_solve_c1_matches_oracle():
     """The small pansharpening workload: 64x64x8, 7x7 blur, d = 4, patch 3x3, window 5x5,
     50 iterations."""
