@@ -297,6 +297,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--iters", type=int, default=None, help="override the iteration count")
+    ap.add_argument("--bands", type=int, default=None,
+                    help="override the band count (e.g. 16: one GPU's share of the 128-band "
+                         "scene split over 8 GPUs by bands)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--subspace", type=int, default=0,
                     help="Ls > 0: solve for Z = X E with E the Ls leading right singular "
@@ -332,6 +335,8 @@ def main():
     spec = synth.config(args.config)
     if args.iters is not None:
         spec = spec.replace(iters=args.iters)
+    if args.bands is not None:
+        spec = spec.replace(L=args.bands)
     ref = hbm_reference(args.calib_gib) if args.calib_gib > 0 else None
     if ref:
         log(f"[bench] reference streams: {ref}")
@@ -385,7 +390,8 @@ def main():
         achieved = bytes_launch / (sw["ms_avg"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": "sweep_kernel", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if args.subspace else measured_traffic(args.config),
+                "traffic": None if (args.subspace or args.bands)
+                else measured_traffic(args.config),
                 "bytes_per_launch": bytes_launch,
                 "ms_per_launch": sw["ms_avg"]}
     # the iterations alone (HIP events around every stage launch, weights and start excluded)

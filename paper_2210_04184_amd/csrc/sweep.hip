@@ -31,7 +31,6 @@
 namespace nlpr {
 namespace {
 
-constexpr int PADW = 4;  // mu rows in LDS are padded by one float4 on each side (K <= 4)
 
 // Sigma' is touched once per iteration: stream it with non-temporal loads and stores so it
 // does not evict X and mu from the caches.
@@ -77,9 +76,8 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int q4 = q >> 2;
-  const int ms = q + 2 * PADW;          // row stride of the mu tile
-  float* Ms = lds;                      // (R + 2K) x ms       mu(., tau), rows r0-K .. r0+R+K-1
-  float* Xs = Ms + (R + 2 * K) * ms;    // (R + H) x q         X rows r0-H .. r0+R-1
+  float* Ms = lds;                      // (R + 2K) x q        mu(., tau), rows r0-K .. r0+R+K-1
+  float* Xs = Ms + (R + 2 * K) * q;     // (R + H) x q         X rows r0-H .. r0+R-1
   float* Cs = Xs + (R + H) * q;         // (R + H) x q         adjoint accumulator
 
   const int tile = it_.y / L;
@@ -123,14 +121,11 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
     __syncthreads();  // the previous shift's reads of Ms and updates of Cs are done
     {
       const gfloat* mun = mu + (size_t)n * plane;
-      const int ms4 = ms >> 2;
-      for (int e = threadIdx.x; e < (R + 2 * K) * ms4; e += NT) {
-        const int rr = e / ms4, c4 = e - rr * ms4 - 1;  // c4 in [-1, q4]
+      for (int e = threadIdx.x; e < (R + 2 * K) * q4; e += NT) {
+        const int rr = e / q4, c4 = e - rr * q4;
         int gr = (r0 - K + rr) % p;
         if (gr < 0) gr += p;
-        const int gc4 = c4 < 0 ? c4 + q4 : (c4 >= q4 ? c4 - q4 : c4);
-        reinterpret_cast<float4*>(Ms)[e] =
-            ldg4(mun + (size_t)gr * q + 4 * gc4);
+        reinterpret_cast<float4*>(Ms)[e] = ldg4(mun + (size_t)gr * q + 4 * c4);
       }
     }
     __syncthreads();
@@ -153,12 +148,16 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
     const size_t n_off = tile_off + (size_t)n * tstride;
 #pragma unroll
     for (int k1 = -K; k1 <= K; ++k1) {
-      // thresholds mu(j + k, tau) for k2 in [-K, K]: columns col-4 .. col+7 of row + k1
+      // thresholds mu(j + k, tau) for k2 in [-K, K]: columns col-4 .. col+7 of row + k1, the
+      // float4 before and after wrapped around the full-width row (no padding columns, so
+      // four workgroups fit a CU's LDS at q = 512)
       float mw[ITEMS][12];
 #pragma unroll
       for (int m = 0; m < ITEMS; ++m) {
-        const float4* mr = reinterpret_cast<const float4*>(Ms + (row[m] + K + k1) * ms + col[m]);
-        const float4 a = mr[0], b = mr[1], d = mr[2];  // padded: column index col - 4 + 4*s
+        const float4* mr = reinterpret_cast<const float4*>(Ms + (row[m] + K + k1) * q);
+        const int c4 = col[m] >> 2;
+        const float4 a = mr[c4 == 0 ? q4 - 1 : c4 - 1], b = mr[c4],
+                     d = mr[c4 + 1 == q4 ? 0 : c4 + 1];
         mw[m][0] = a.x; mw[m][1] = a.y; mw[m][2] = a.z; mw[m][3] = a.w;
         mw[m][4] = b.x; mw[m][5] = b.y; mw[m][6] = b.z; mw[m][7] = b.w;
         mw[m][8] = d.x; mw[m][9] = d.y; mw[m][10] = d.z; mw[m][11] = d.w;
@@ -301,7 +300,7 @@ SweepShape choose_sweep_shape(int p, int q, int K, int halo) {
   sh.rows = std::max(1, std::min(p, per_block / q));
   sh.ntiles = ceil_div(p, sh.rows);
   sh.halo = halo;
-  sh.lds = (size_t)((sh.rows + 2 * K) * (q + 2 * PADW) + 2 * (sh.rows + halo) * q) * sizeof(float);
+  sh.lds = (size_t)((sh.rows + 2 * K) * q + 2 * (sh.rows + halo) * q) * sizeof(float);
   return sh;
 }
 
