@@ -93,7 +93,7 @@ enum {
  *   Sw         : search radius, W = [-Sw, Sw]^2, 0 <= Sw <= 8, Sw < p and Sw < q.
  *   The sweep keeps full image rows in LDS: with R = max(1, 1024 * items / q) rows per tile
  *   (items = 1, 2 or 4, the smallest with 1024 * items >= q),
- *   4 * ((R + 2K)(q + 8) + 2 (R + Sw) q) must not exceed 160 KiB (e.g. q <= 2048 for
+ *   4 * ((R + 2K) q + 2 (R + Sw) q) must not exceed 160 KiB (e.g. q <= 2048 for
  *   K = 2, Sw = 5).
  *   iters      : ADMM iterations, >= 0.
  *   Ls         : 0 = no subspace (Z is the ADMM variable X).  1 <= Ls <= min(L, 32): Z = X E
@@ -134,7 +134,11 @@ typedef struct nlpr_plan nlpr_plan;
  * matrix G = (rho/lambda1 I + R^T R)^{-1} (FP64) with which the P2-update of
  * eq. (Qm_update) applies F = (I + lambda1/rho R R^T)^{-1} = I - R G R^T.
  *   blur_host : host, (2r+1)^2 floats, row-major, tap b(m1, m2) at [(m1 + r)(2r+1) + m2 + r];
- *               B X (i) = sum_m b(m) X(i - m), circular.
+ *               B X (i) = sum_m b(m) X(i - m), circular.  When b has rank one up to FP32
+ *               rounding (no tap off by more than 1e-6 of the largest; a Gaussian, for
+ *               one), the plan also stores its row and column factors (derived in FP64)
+ *               and applies B as a row and a column pass; nlpr_plan_info.blur_separable
+ *               reports it.
  *   R_host    : host, L x Lh floats, row-major (R[c][h] at [c * Lh + h]).
  *   With NLPR_FUSED_S the plan also holds, per frequency, the FP64-derived factors of the
  *   aliasing-group solve (1/a, b^/a and gamma conj(b^)/a, with a the denominator of
