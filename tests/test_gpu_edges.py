@@ -53,6 +53,13 @@ def test_smallest_image_one_band_identity_blur():
                                           iters=6, seed=4, tile=8))
 
 
+def test_narrowest_image_with_patch_and_window():
+    # q = 8: two float4 per row, so the sweep's wrapped threshold reads take the same float4
+    # on both sides of a thread's columns; 3 x 3 patch, 5 x 5 window
+    check_against_oracle(synth.small_spec(p=16, q=8, L=3, Lh=2, d=2, blur_radius=1, K=1, Sw=2,
+                                          iters=6, seed=9, tile=4))
+
+
 def test_no_decimation():
     check_against_oracle(synth.small_spec(p=32, q=48, L=3, Lh=2, d=1, blur_radius=2, K=1,
                                           Sw=2, iters=6, seed=5, tile=8))
