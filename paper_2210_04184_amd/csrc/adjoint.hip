@@ -308,12 +308,15 @@ __device__ __forceinline__ double pupdate_bwd_write(
 #pragma unroll
     for (int h = 0; h < LHM; ++h)
       if (h < Lh) corr += v[h] * R[c * Lh + h];
-    const float w2b = W2b[o], l2b = L2b[o];
-    const float a0b = (2.f * w2b + l2b) - corr;           // A0' = P2' - P2' R G R^T
-    Xp[o] = -w2b - l2b + a0b;
-    L2b[o] = w2b + l2b - a0b;
-    const float w1b = W1b[o], l1b = L1b[o];
+    // with P2' = 2 W2' + Lambda2'' and A0' = P2' - P2' R G R^T = P2' - corr:
+    // X' = A0' - W2' - Lambda2'' = W2' - corr and Lambda2''(new) = W2' + Lambda2'' - A0'
+    // = corr - W2', so Lambda2'' is not read again here
+    const float xp = W2b[o] - corr;
+    Xp[o] = xp;
+    L2b[o] = -xp;
+    const float w1b = W1b[o];
     if (sampled) {
+      const float l1b = L1b[o];            // read only where the P1 step keeps it
       const float p1b = 2.f * w1b + l1b;
       const float y = Yl[c * lplane + lj];
       BXb[o] = -w1b - l1b + p1b * rr;
