@@ -367,3 +367,42 @@ def test_module_level_solve_wrapper():
     Z = nlpr.solve(dev(sc.Yl), dev(sc.Yh), sc.blur, s.d, sc.R, s.lam, s.K, s.Sw, s.rho,
                    s.iters, sc.h)
     assert rel_rmse(host(Z), solve_oracle(sc)) <= 1e-4
+
+
+def random_configuration(i):
+    """Seeded random small problem within the documented limits: sides of the form 2^a 3^b
+    (q a multiple of 4), d dividing both, any band and guide-band counts, blur radius,
+    patch and window radii; every other case with a full-rank asymmetric blur."""
+    rng = np.random.default_rng(1000 + i)
+    while True:
+        p = int(rng.choice([8, 12, 16, 18, 24, 32, 36, 48]))
+        q = int(rng.choice([8, 12, 16, 24, 32, 36, 48]))
+        d = int(rng.choice([1, 2, 3, 4]))
+        if p % d == 0 and q % d == 0:
+            break
+    L = int(rng.integers(1, 7))
+    Lh = int(rng.integers(1, 5))
+    r = int(rng.integers(0, min(4, (min(p, q) - 1) // 2) + 1))
+    K = int(rng.integers(0, 3))
+    Sw = int(rng.integers(0, min(3, min(p, q) - 1) + 1))
+    iters = int(rng.integers(2, 6))
+    spec = synth.small_spec(p=p, q=q, L=L, Lh=Lh, d=d, blur_radius=r, K=K, Sw=Sw, iters=iters,
+                            seed=200 + i, tile=4)
+    b = None
+    if i % 2:
+        b = rng.uniform(0.0, 1.0, (2 * r + 1, 2 * r + 1))
+        b = np.asarray(b / b.sum(), dtype=np.float32)
+    return spec, b
+
+
+@pytest.mark.parametrize("i", range(40))
+def test_random_configurations_match_oracle(i):
+    spec, b = random_configuration(i)
+    sc = synth.make_scene(spec)
+    print(f"[random {i}] p={spec.p} q={spec.q} L={spec.L} Lh={spec.Lh} d={spec.d} "
+          f"r={spec.blur_radius} K={spec.K} Sw={spec.Sw} T={spec.iters} "
+          f"blur={'general' if b is not None else 'gaussian'}", flush=True)
+    over = {} if b is None else dict(blur=b)
+    okw = {} if b is None else dict(b=b.astype(np.float64))
+    z, _, _ = solve_gpu(sc, **over)
+    assert rel_rmse(z, solve_oracle(sc, **okw)) <= 1e-4
