@@ -57,7 +57,7 @@ def optimum(name):
 def gpu_solve(pr, Yl, Yh, iters, flags=0):
     plan = nlpr.Plan(p=pr.p, q=pr.q, L=pr.L, Lh=pr.R.shape[1], d=pr.d, blur=pr.b, R=pr.R,
                      K=pr.K, Sw=pr.S, iters=iters, lam=pr.lam, rho=pr.rho, h=pr.h,
-                     lam1=pr.lam1, flags=flags)
+                     lam1=pr.lam1, E=pr.E, flags=flags)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     Z, _ = plan.solve(dev(Yl), dev(Yh))
     torch.cuda.synchronize()
@@ -93,3 +93,29 @@ def test_long_run_stays_within_the_bar_of_the_fp64_oracle():
     X = gpu_solve(pr, Yl, Yh, 1000)
     ref = o.solve(Yl, Yh, pr, 1000).X
     assert np.linalg.norm(X - ref) / np.linalg.norm(ref) <= 1e-4
+
+
+# the other regularisers and the subspace form, each with part of the differences zero at the
+# optimum (68 %, 52 %, 66 %); the dense solve is converged to 1e-10 at 16 000 iterations
+VARIANTS = {
+    "subspace": (dict(L=3, Lh=1, lam=0.02, h=0.7, Ls=2, seed=0), 0),
+    "unweighted": (dict(L=2, Lh=1, lam=0.002, h=0.7, unweighted=True, seed=0), nlpr.UNWEIGHTED),
+    "local": (dict(L=2, Lh=1, lam=0.05, h=0.7, local=True, seed=1), nlpr.LOCAL_WINDOW),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_variants_reach_the_optimum_of_an_independent_solver(name):
+    kw, flags = VARIANTS[name]
+    pr, Yl, Yh = tiny_problem(p=8, q=8, d=2, K=1, S=1, rho=0.3, **kw)
+    pr.b, pr.R, Yl, Yh = f32(pr.b), f32(pr.R), f32(Yl), f32(Yh)
+    if pr.E is not None:
+        pr.E = f32(pr.E)
+    H, bb, c0, G, w = _dense_problem(pr, Yl, Yh)
+    f_opt = _dense_objective(_pdhg(H, bb, G, w, 16000), H, bb, c0, G, w)
+    Z = gpu_solve(pr, Yl, Yh, 20000, flags=flags)
+    # the objective is a function of the coefficient image X (Z = X E, E of full row rank)
+    X = vec(Z) if pr.E is None else vec(Z) @ np.linalg.pinv(pr.E)
+    f = _dense_objective(X.T.ravel(), H, bb, c0, G, w)
+    print(f"[optimum {name}] rel={(f - f_opt) / f_opt:.2e}", flush=True)
+    assert f == pytest.approx(f_opt, rel=1e-5)
