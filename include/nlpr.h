@@ -304,12 +304,15 @@ int nlpr_monitor(const nlpr_plan* plan, double* trace, int32_t cap, int32_t* n);
  * with the sweep adjoint's LDS tile within 160 KiB; else NLPR_ERR_UNSUPPORTED_SHAPE or
  * NLPR_ERR_INVALID_ARG.
  *
- * nlpr_grad_sizes: bytes of the checkpoint buffer (for t = 1 .. iters-1: X^t, B X^t, the
- *   Lambda1 and Lambda2 entering iteration t, and Sigma' after its sweep) and of the
- *   gradient workspace.  Checkpoints take (iters - 1) * (4 + Npairs |P|) * 4 * L * p * q
- *   bytes (at least 256).
+ * nlpr_grad_sizes: bytes of the checkpoint buffer and of the gradient workspace.  For
+ *   t = 1 .. iters-1 the checkpoints hold X^t, B X^t, the Lambda1 and Lambda2 entering
+ *   iteration t, and which branch of the threshold every dual element of its sweep took
+ *   (2 bits each: |V| < mu, V >= mu or V <= -mu; the adjoint needs nothing else of Sigma).
+ *   They take (iters - 1) * (16 + Npairs |P| / 4) * L * p * q bytes, each part rounded up to
+ *   a multiple of 256 (at least 256 in all).
  * nlpr_forward: like nlpr_solve (Z equal bit for bit) and also writes the checkpoints to ck
- *   (device, 256-byte aligned).  ws as for nlpr_solve.
+ *   (device, 256-byte aligned).  ws as for nlpr_solve; the dual state is updated in it in
+ *   place, as by nlpr_solve.
  * nlpr_backward: given dZ = dloss/dZ (device, [L][p][q]), reloads each iteration's X, B X
  *   and Lambda from its checkpoint and carries the adjoints back; writes dYl ([L][p/d][q/d]),
  *   dYh ([Lh][p][q]) and dscal (device, 2 doubles: dloss/dlambda_2, dloss/drho).  ws, ck

@@ -16,7 +16,7 @@
 namespace nlpr {
 namespace {
 
-constexpr int PADW = 4;   // LDS column padding of the mu tiles (K <= 4), as in the sweep
+constexpr int PADW = 4;   // LDS column padding of the mu' accumulator (K <= 4)
 
 __device__ __forceinline__ int wrapg(int a, int m) {
   a %= m;
@@ -71,24 +71,24 @@ __device__ __forceinline__ void block_sum256(double (&v)[N]) {
 }
 
 // ------------------------------------------------------------------------ sweep adjoint
-// Per workgroup (tile, band) as the forward sweep, one float4 item per thread.  Inputs: X,
-// mu, Sigma' before the forward sweep (sig_in, tile-major; absent for the first sweep,
-// where it is 0), C' (adjoint of the right-hand side the sweep fed), Sigma'' (adjoint of
-// the sweep's Sigma' output, updated in place to the adjoint of its input).  Outputs: X'
-// of the sweep (xr, plus the rows above the tile in the halo buffer, folded like the
-// forward's), and mu' accumulated into per-(band, tile) partial tiles covering the rows
+// Per workgroup (tile, band) as the forward sweep, one float4 item per thread.  Inputs: the
+// threshold branch of every dual element in the forward sweep (codes, 2 bits each, one byte
+// per float4 of Sigma', written by the forward's branch-recording variant), C' (adjoint of
+// the right-hand side the sweep fed) and Sigma'' (adjoint of the sweep's Sigma' output,
+// updated in place to the adjoint of its input).  The branch is all the adjoint needs of
+// the forward values: inside the threshold Sigma+ = -V, outside it Sigma+ = -mu sign(V).
+// Outputs: X' of the sweep (xr, plus the rows above the tile in the halo buffer, folded like
+// the forward's), and mu' accumulated into per-(band, tile) partial tiles covering the rows
 // r0 - K .. r0 + R + K - 1 (mup), reduced over bands and tiles by mubar_reduce_kernel.
 //   A'(j) = 2 (C'(j) - C'(j - tau));  per k: c' = -Sigma''(j) - 2 A'(j);
-//   V' = A'(j) + [|V| < mu] c';  mu'(j + k) += [|V| >= mu] sign(V) c';  Sigma''(j) := -V';
-//   g'(j) = sum_k V';  X'(j) += g'(j),  X'(j - tau) -= g'(j).
-// With K <= 1 the kernel is held to 128 VGPRs (four waves per SIMD, so four workgroups per
-// CU instead of three; one register spills): at 256 x 256 x 31 its 1984 workgroups then take
-// two rounds instead of three, and the reverse pass runs 3.5 % faster.
-template <int K, bool FIRST>
-__global__ void __launch_bounds__(256, K <= 1 ? 4 : 1)
-sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
-                 int mu_s, int cb_s, const float* sig_in, int sb_s, int xr_s, int halo_s,
-                 int mup_s) {
+//   V' = A'(j) + [|V| < mu] c';  mu'(j + k) += [V >= mu] c' - [V <= -mu] c';
+//   Sigma''(j) := -V';  g'(j) = sum_k V';  X'(j) += g'(j),  X'(j - tau) -= g'(j).
+// Without X, mu and Sigma' the kernel needs 96 VGPRs at K = 1 (five workgroups per CU);
+// holding it to 80 or 64 (six or eight per CU, with spills) made the reverse pass slower.
+template <int K>
+__global__ void __launch_bounds__(256)
+sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int cb_s,
+                 const uint8_t* codes, int sb_s, int xr_s, int halo_s, int mup_s) {
   constexpr int NT = 256;
   constexpr int KW = 2 * K + 1;
   constexpr int NP = KW * KW;
@@ -96,47 +96,39 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
   const SceneDesc& S = sd[it_.x];
   const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
             H = S.halo;
-  const gfloat* X = gslot<const gfloat>(S, x_s);
-  const gfloat* mu = gslot<const gfloat>(S, mu_s);
   const gfloat* Cb = gslot<const gfloat>(S, cb_s);
-  const gfloat* sgin = FIRST ? nullptr : as_global(sig_in);
+  const gu8* cod = (const gu8*)codes;
   gfloat* sb = gslot<gfloat>(S, sb_s);
   gfloat* mup = gslot<gfloat>(S, mup_s);
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int q4 = q >> 2;
   const int ms = q + 2 * PADW;
-  const int ER = R + 2 * K;               // extended rows of the mu tiles
-  float* Ms = lds;                        // ER x ms   mu(., tau)
-  float* Mb = Ms + ER * ms;               // ER x ms   mu' accumulator
-  float* Xs = Mb + ER * ms;               // (R + H) x q
-  float* Cs = Xs + (R + H) * q;           // (R + H) x q   C'
+  const int ER = R + 2 * K;               // extended rows of the mu' tile
+  float* Mb = lds;                        // ER x ms   mu' accumulator
+  float* Cs = Mb + ER * ms;               // (R + H) x q   C'
   float* As = Cs + (R + H) * q;           // (R + H) x q   X' accumulator
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
 
   const int tile = it_.y / L;
   const int c = it_.y - tile * L;
   const int r0 = tile * R;
   const int rows = min(R, p - r0);
   const size_t plane = (size_t)p * q;
-  const gfloat* Xc = X + (size_t)c * plane;
   const gfloat* Cc = Cb + (size_t)c * plane;
   for (int e = threadIdx.x; e < (R + H) * q4; e += NT) {
     const int rr = e / q4, c4 = e - rr * q4;
     const int gr = wrapg(r0 - H + rr, p);
-    reinterpret_cast<float4*>(Xs)[e] = ldg4(Xc + (size_t)gr * q + 4 * c4);
     reinterpret_cast<float4*>(Cs)[e] = ldg4(Cc + (size_t)gr * q + 4 * c4);
-    reinterpret_cast<float4*>(As)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    reinterpret_cast<float4*>(As)[e] = zero4;
   }
   __syncthreads();
 
   const int row = threadIdx.x / q4;
   const int col = (threadIdx.x - row * q4) * 4;
   const bool ok = row < rows;
-  const float4 xv = ok ? *reinterpret_cast<const float4*>(Xs + (row + H) * q + col)
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 cv = ok ? *reinterpret_cast<const float4*>(Cs + (row + H) * q + col)
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 cp = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 cv = ok ? *reinterpret_cast<const float4*>(Cs + (row + H) * q + col) : zero4;
+  float4 cp = zero4;
 
   const size_t kstride = (size_t)R * q;
   const size_t tstride = (size_t)NP * kstride;
@@ -146,65 +138,42 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
   for (int n = 0; n < npairs; ++n) {
     const int2 t = tau_at(S, n);
     __syncthreads();
-    {
-      const gfloat* mun = mu + (size_t)n * plane;
-      const int ms4 = ms >> 2;
-      for (int e = threadIdx.x; e < ER * ms4; e += NT) {
-        const int rr = e / ms4, c4 = e - rr * ms4 - 1;
-        const int gr = wrapg(r0 - K + rr, p);
-        const int gc4 = c4 < 0 ? c4 + q4 : (c4 >= q4 ? c4 - q4 : c4);
-        reinterpret_cast<float4*>(Ms)[e] = ldg4(mun + (size_t)gr * q + 4 * gc4);
-        reinterpret_cast<float4*>(Mb)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
+    for (int e = threadIdx.x; e < ER * (ms >> 2); e += NT) reinterpret_cast<float4*>(Mb)[e] = zero4;
     __syncthreads();
-    // g and A' at the item's four pixels
-    float gg[4], ab[4], gb[4] = {0.f, 0.f, 0.f, 0.f};
+    // A' at the item's four pixels
+    float ab[4], gb[4] = {0.f, 0.f, 0.f, 0.f};
     {
-      const float* xr = Xs + (row + H - t.x) * q;
       const float* cr = Cs + (row + H - t.x) * q;
-      const float xa[4] = {xv.x, xv.y, xv.z, xv.w};
       const float ca[4] = {cv.x, cv.y, cv.z, cv.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         int cc = col + e - t.y;
         cc = cc < 0 ? cc + q : (cc >= q ? cc - q : cc);
-        gg[e] = ok ? xa[e] - xr[cc] : 0.f;
         ab[e] = ok ? 2.f * (ca[e] - cr[cc]) : 0.f;
       }
     }
     const size_t n_off = tile_off + (size_t)n * tstride;
 #pragma unroll
     for (int k1 = -K; k1 <= K; ++k1) {
-      float mw[12];
-      {
-        const float4* mr = reinterpret_cast<const float4*>(Ms + (row + K + k1) * ms + col);
-        const float4 a = mr[0], b = mr[1], d = mr[2];
-        mw[0] = a.x; mw[1] = a.y; mw[2] = a.z; mw[3] = a.w;
-        mw[4] = b.x; mw[5] = b.y; mw[6] = b.z; mw[7] = b.w;
-        mw[8] = d.x; mw[9] = d.y; mw[10] = d.z; mw[11] = d.w;
-      }
-      float4 sv[KW], sbv[KW];
+      unsigned cw[KW];
+      float4 sbv[KW];
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
         const size_t off = n_off + (size_t)((k1 + K) * KW + k2) * kstride + (size_t)row * q + col;
-        sv[k2] = (FIRST || !ok) ? make_float4(0.f, 0.f, 0.f, 0.f) : ld4_nt(sgin + off);
-        sbv[k2] = ok ? ld4_nt(sb + off) : make_float4(0.f, 0.f, 0.f, 0.f);
+        cw[k2] = ok ? (unsigned)cod[off >> 2] : 0u;
+        sbv[k2] = ok ? ld4_nt(sb + off) : zero4;
       }
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
         const int o = 4 + (k2 - K);
-        const float s4[4] = {sv[k2].x, sv[k2].y, sv[k2].z, sv[k2].w};
         const float b4[4] = {sbv[k2].x, sbv[k2].y, sbv[k2].z, sbv[k2].w};
         float vb[4], mb[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float V = gg[e] - s4[e];
-          const float m = mw[o + e];
+          const unsigned code = (cw[k2] >> (2 * e)) & 3u;
           const float cbar = -b4[e] - 2.f * ab[e];
-          const bool inside = fabsf(V) < m;
-          vb[e] = ab[e] + (inside ? cbar : 0.f);
-          mb[e] = inside ? 0.f : (V > 0.f ? cbar : (V < 0.f ? -cbar : 0.f));
+          vb[e] = ab[e] + (code == 0u ? cbar : 0.f);
+          mb[e] = code == 1u ? cbar : (code == 2u ? -cbar : 0.f);
           gb[e] += vb[e];
         }
         if (ok) {
@@ -633,21 +602,19 @@ int launch_kind(const Batch& B, Kind kind, const char* name, Kern kern, hipStrea
   return NLPR_OK;
 }
 
-template <int K, bool FIRST>
-int launch_sbwd(const Batch& B, const Group& g, size_t lds, int x, int mu, int cb,
-                const float* sig_in, int sb, int xr, int halo, int mup, hipStream_t s) {
-  auto kern = sweep_bwd_kernel<K, FIRST>;
-  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(256), lds, s, B.d_desc, g.d_items, x, mu, cb,
-                     sig_in, sb, xr, halo, mup);
+template <int K>
+int launch_sbwd(const Batch& B, const Group& g, size_t lds, int cb, const uint8_t* codes, int sb,
+                int xr, int halo, int mup, hipStream_t s) {
+  auto kern = sweep_bwd_kernel<K>;
+  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(256), lds, s, B.d_desc, g.d_items, cb, codes, sb,
+                     xr, halo, mup);
   NLPR_LAUNCH_CHECK("sweep_bwd_kernel");
   return NLPR_OK;
 }
 
 template <int K>
 int sbwd_attr() {
-  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K, true>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
-  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K, false>),
+  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
   return NLPR_OK;
 }
@@ -656,7 +623,7 @@ int sbwd_attr() {
 
 size_t sweep_bwd_lds(const Plan& P) {
   const int R = P.sweep.rows, H = P.sweep.halo, K = P.prm.K, q = P.prm.q;
-  return (size_t)(2 * (R + 2 * K) * (q + 2 * PADW) + 3 * (R + H) * q) * sizeof(float);
+  return (size_t)((R + 2 * K) * (q + 2 * PADW) + 2 * (R + H) * q) * sizeof(float);
 }
 size_t weights_bwd_lds(const Plan& P) {
   const int K = P.prm.K;
@@ -682,25 +649,19 @@ int sweep_bwd_prepare(int K) {
   }
 }
 
-int launch_sweep_bwd(const Batch& B, int x, int mu, int cb, const float* sig_in, int sb, int xr,
-                     int halo, int mup, bool first, hipStream_t s) {
+int launch_sweep_bwd(const Batch& B, int cb, const uint8_t* codes, int sb, int xr, int halo,
+                     int mup, hipStream_t s) {
   const Plan& P = *B.scenes[0];
   const size_t lds = sweep_bwd_lds(P);
   for (const Group& g : B.groups[KD_SWEEP]) {
     if (!g.nitems) continue;
     int rc;
     switch (g.key0) {
-#define NLPR_SB(KK)                                                                           \
-  case KK:                                                                                    \
-    rc = first ? launch_sbwd<KK, true>(B, g, lds, x, mu, cb, sig_in, sb, xr, halo, mup, s)   \
-               : launch_sbwd<KK, false>(B, g, lds, x, mu, cb, sig_in, sb, xr, halo, mup, s); \
-    break;
-      NLPR_SB(0)
-      NLPR_SB(1)
-      NLPR_SB(2)
-      NLPR_SB(3)
-      NLPR_SB(4)
-#undef NLPR_SB
+      case 0: rc = launch_sbwd<0>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
+      case 1: rc = launch_sbwd<1>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
+      case 2: rc = launch_sbwd<2>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
+      case 3: rc = launch_sbwd<3>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
+      case 4: rc = launch_sbwd<4>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
       default:
         set_error("sweep adjoint: unsupported patch radius");
         return NLPR_ERR_UNSUPPORTED_SHAPE;

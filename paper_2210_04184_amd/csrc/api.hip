@@ -718,13 +718,14 @@ int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float*
 }
 
 // ---------------------------------------------------------------------- reverse mode
-// Checkpoints: for t = 0 .. T-1 the state at the start of iteration t + 1, i.e. C^t,
-// Lambda1^t, Lambda2^t (planes) and, for t >= 1, Sigma'^t.  Layout: the 3 T planes first
-// ([t][C, Lambda1, Lambda2]), then the T - 1 Sigma' blocks.
+// Checkpoints, for t = 1 .. T-1: X^t, B X^t and the Lambda1, Lambda2 entering iteration t
+// (planes), then the threshold branches of iteration t's sweep (2 bits per dual element).
+// Layout: the 4 (T - 1) planes first ([t][X, BX, Lambda1, Lambda2]), then the T - 1 blocks
+// of branch codes.
 struct GradLayout {
   size_t off[B_COUNT] = {};
   size_t gws_bytes = 0;
-  size_t plane_al = 0, sig_al = 0, ck_bytes = 0;
+  size_t plane_al = 0, code_al = 0, ck_bytes = 0;
   int npix = 0, nw = 0;
 };
 
@@ -749,9 +750,8 @@ GradLayout grad_layout(const Plan& P) {
   G.gws_bytes = off;
   const int T = P.prm.iters;
   G.plane_al = align256(pl);
-  G.sig_al = P.npairs ? align256(P.sz[B_SIGMA]) : 0;
-  // for t = 1 .. T-1: X^t, B X^t and the Lambda1, Lambda2 entering iteration t, then Sigma'
-  G.ck_bytes = std::max<size_t>(256, (size_t)std::max(T - 1, 0) * (4 * G.plane_al + G.sig_al));
+  G.code_al = P.npairs ? align256(P.sz[B_SIGMA] / 16) : 0;   // one byte per float4 of Sigma'
+  G.ck_bytes = std::max<size_t>(256, (size_t)std::max(T - 1, 0) * (4 * G.plane_al + G.code_al));
   return G;
 }
 
@@ -772,13 +772,13 @@ int grad_check(const Batch& B) {
 }
 
 // Checkpoint t (1 .. T-1) holds what the reverse step of iteration t reads: plane k = 0 X^t,
-// 1 B X^t, 2 Lambda1^{t-1}, 3 Lambda2^{t-1}; then Sigma' after the sweep of iteration t.
+// 1 B X^t, 2 Lambda1^{t-1}, 3 Lambda2^{t-1}; then the branch codes of iteration t's sweep.
 char* ck_plane(void* ck, const GradLayout& G, int t, int k) {
   return static_cast<char*>(ck) + ((size_t)(t - 1) * 4 + k) * G.plane_al;
 }
-float* ck_sig(void* ck, const GradLayout& G, int T, int t) {
-  return reinterpret_cast<float*>(static_cast<char*>(ck) + (size_t)(T - 1) * 4 * G.plane_al +
-                                  (size_t)(t - 1) * G.sig_al);
+uint8_t* ck_codes(void* ck, const GradLayout& G, int T, int t) {
+  return reinterpret_cast<uint8_t*>(ck) + (size_t)(T - 1) * 4 * G.plane_al +
+         (size_t)(t - 1) * G.code_al;
 }
 
 // Forward solve that keeps the checkpoints.  Z = X^T equals nlpr_solve's output bit for bit;
@@ -786,6 +786,8 @@ float* ck_sig(void* ck, const GradLayout& G, int T, int t) {
 // is copied: before each iteration the descriptor's slots are re-pointed so that the X-update
 // and the blur write X^t and B X^t into checkpoint t, and the P-update reads the Lambda of
 // checkpoint t and writes the new Lambda into checkpoint t+1 (the workspace after the last).
+// The sweep updates Sigma' in place in the workspace, as in the solve, and writes the branch
+// codes of checkpoint t.
 int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws, size_t ws_bytes,
                  void* ck, size_t ck_bytes, hipStream_t s) {
   int rc;
@@ -839,8 +841,7 @@ int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws,
     if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, B_L1O, B_L2O, s)))
       return rc;
     if (reg && (rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, t == 1, s,
-                                  t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
-                                  ck_sig(ck, G, T, t))))
+                                  ck_codes(ck, G, T, t))))
       return rc;
     if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
   }
@@ -901,8 +902,8 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
                                        ck_plane(ck, G, t, k));
     if ((rc = launch_set_slots(B, st, s))) return rc;
     if ((rc = launch_conv(B, B_GC, B_GW1, false, -1, -1, -1, 0, s))) return rc;   // W1' = B C'
-    if (reg && (rc = launch_sweep_bwd(B, B_Z, B_MU, B_GC, t >= 2 ? ck_sig(ck, G, T, t - 1) : nullptr,
-                                      B_GSIG, B_GXR, B_GHALO, B_GMUP, t == 1, s)))
+    if (reg && (rc = launch_sweep_bwd(B, B_GC, ck_codes(ck, G, T, t), B_GSIG, B_GXR, B_GHALO,
+                                      B_GMUP, s)))
       return rc;
     if ((rc = launch_pupdate_bwd(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_GW1, B_GC, B_GL1, B_GL2,
                                  B_GBX, B_GXP, B_GYL, B_GYH, B_GPART, s)))

@@ -218,6 +218,7 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // Vector elements move through clang ext-vector types (HIP's vector structs cannot be
 // copied out of an address-space-qualified object).
 typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) uint8_t gu8;
 typedef __attribute__((address_space(1))) double gdouble;
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
@@ -315,8 +316,9 @@ size_t weights_bwd_lds(const Plan& P);
 int weights_bwd_blocks(const Plan& P);
 size_t mubar_partial_elems(const Plan& P);
 int sweep_bwd_prepare(int K);
-int launch_sweep_bwd(const Batch& B, int x, int mu, int cb, const float* sig_in, int sb, int xr,
-                     int halo, int mup, bool first, hipStream_t s);
+// codes: the forward sweep's threshold branches of the iteration (launch_sweep's codes)
+int launch_sweep_bwd(const Batch& B, int cb, const uint8_t* codes, int sb, int xr, int halo,
+                     int mup, hipStream_t s);
 int launch_mubar_reduce(const Batch& B, int mup, int mub, hipStream_t s);
 int launch_pupdate_bwd(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1b,
                        int w2b, int l1b, int l2b, int bxb, int xp, int gyl, int gyh, int part,
@@ -330,10 +332,10 @@ int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] 
 int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s);   // S^T Y_l / rho
 // X = solve(C) (+ add, a [L][p][q] slot, when add >= 0); the fused-S system for fused scenes
 int launch_xsolve(const Batch& B, int c, int x, int f, int add, hipStream_t s);
-// sig_in / sig_out: read Sigma' from / write it to other buffers than the slot (a single
-// scene: the checkpoints of the differentiated solve); null = in place in the slot
+// Sigma' is updated in place.  codes (differentiated form, one item per thread): also
+// write each dual element's 2-bit threshold branch there, one byte per float4 of Sigma'
 int launch_sweep(const Batch& B, int x, int mu, int sigma, int creg, int halo, bool first,
-                 hipStream_t s, const float* sig_in = nullptr, float* sig_out = nullptr);
+                 hipStream_t s, uint8_t* codes = nullptr);
 int sweep_prepare(int K, int items);   // kernel attributes; call before launches or capture
 
 // ---- shapes and tuning

@@ -56,19 +56,21 @@ __device__ __forceinline__ void st_nt(gfloat* p, float4 v) {
 __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v, -m), m); }
 
 // ---- sweep kernel begin (the traffic record of the benchmark is keyed to this text)
-template <int K, int ITEMS, int NT, bool FIRST>
+// CODES (differentiated form): also record, per dual element, which branch of the
+// threshold it took, which is all the sweep's adjoint needs of this iteration: 2 bits, 0 for
+// |V| < mu, 1 for V >= mu, 2 for V <= -mu, 3 for V = 0 with mu = 0 (or V not a number).  The
+// four elements of a float4 item share one byte, at the item's float offset / 4.
+template <int K, int ITEMS, int NT, bool FIRST, bool CODES>
 __global__ void __launch_bounds__(NT)
 sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s, int mu_s,
-             int sig_s, int creg_s, int halo_s, const float* sig_in, float* sig_out) {
+             int sig_s, int creg_s, int halo_s, uint8_t* codes) {
   const int2 it_ = items[blockIdx.x];
   const SceneDesc& S = sd[it_.x];
   const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
             H = S.halo;
   const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
   const gfloat* __restrict__ mu = gslot<const gfloat>(S, mu_s);
-  // Sigma' is updated in place unless sig_in / sig_out name other buffers (checkpoints)
-  gfloat* sig_w = sig_out ? as_global(sig_out) : gslot<gfloat>(S, sig_s);
-  const gfloat* sig_r = sig_in ? as_global(sig_in) : sig_w;
+  gfloat* sig = gslot<gfloat>(S, sig_s);   // updated in place
   gfloat* __restrict__ creg = gslot<gfloat>(S, creg_s);
   gfloat* __restrict__ halo = gslot<gfloat>(S, halo_s);
   constexpr int KW = 2 * K + 1;
@@ -166,7 +168,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       if (!FIRST) {
 #pragma unroll
         for (int k2 = 0; k2 < KW; ++k2) {
-          const gfloat* base = sig_r + n_off + (size_t)((k1 + K) * KW + k2) * kstride;
+          const gfloat* base = sig + n_off + (size_t)((k1 + K) * KW + k2) * kstride;
 #pragma unroll
           for (int m = 0; m < ITEMS; ++m)
             s[k2][m] = ok[m] ? ld_nt(base + (size_t)row[m] * q + col[m])
@@ -175,7 +177,8 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       }
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
-        gfloat* base = sig_w + n_off + (size_t)((k1 + K) * KW + k2) * kstride;
+        const size_t pl_off = n_off + (size_t)((k1 + K) * KW + k2) * kstride;
+        gfloat* base = sig + pl_off;
 #pragma unroll
         for (int m = 0; m < ITEMS; ++m) {
           if (!ok[m]) continue;
@@ -191,6 +194,18 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
           A[m].z += v.z - 2.f * cl.z;
           A[m].w += v.w - 2.f * cl.w;
           st_nt(base + (size_t)row[m] * q + col[m], make_float4(-cl.x, -cl.y, -cl.z, -cl.w));
+          if (CODES) {
+            const float va[4] = {v.x, v.y, v.z, v.w};
+            unsigned byte = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const unsigned code = fabsf(va[e]) < mw[m][o + e] ? 0u
+                                    : (va[e] > 0.f ? 1u : (va[e] < 0.f ? 2u : 3u));
+              byte |= code << (2 * e);
+            }
+            ((gu8*)codes)[(pl_off + (size_t)row[m] * q + col[m]) >> 2] =
+                (uint8_t)byte;
+          }
         }
       }
     }
@@ -244,24 +259,28 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
 constexpr int kThreads = NLPR_SWEEP_THREADS;
 constexpr int kMinItems = NLPR_SWEEP_MIN_ITEMS;
 
-template <int K, int ITEMS, bool FIRST>
+template <int K, int ITEMS, bool FIRST, bool CODES>
 int launch_k(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
-             const float* sig_in, float* sig_out, hipStream_t s) {
-  auto kern = sweep_kernel<K, ITEMS, kThreads, FIRST>;
+             uint8_t* codes, hipStream_t s) {
+  auto kern = sweep_kernel<K, ITEMS, kThreads, FIRST, CODES>;
   hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(kThreads), g.lds, s, B.d_desc, g.d_items, x, mu,
-                     sig, creg, halo, sig_in, sig_out);
+                     sig, creg, halo, codes);
   NLPR_LAUNCH_CHECK("sweep_kernel");
   return NLPR_OK;
 }
 
 // Allow the sweep's dynamic LDS beyond the default limit (done when a batch is built, not
-// during graph capture).
+// during graph capture).  The branch-recording variant exists for one item per thread only.
 template <int K, int ITEMS>
 int set_lds_limit() {
-  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, true>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
-  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, false>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
+  const void* kern[4] = {
+      reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, true, false>),
+      reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, false, false>),
+      ITEMS == 1 ? reinterpret_cast<const void*>(sweep_kernel<K, 1, kThreads, true, true>) : nullptr,
+      ITEMS == 1 ? reinterpret_cast<const void*>(sweep_kernel<K, 1, kThreads, false, true>) : nullptr};
+  for (const void* k : kern)
+    if (k) NLPR_HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)kMaxSweepLds));
   return NLPR_OK;
 }
 
@@ -276,15 +295,22 @@ int set_lds_limit_items(int items) {
 
 template <int K, bool FIRST>
 int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
-                 const float* sig_in, float* sig_out, hipStream_t s) {
+                 uint8_t* codes, hipStream_t s) {
+  if (codes) {
+    if (g.key1 != 1 || kMinItems != 1) {
+      set_error("sweep: branch codes need one item per thread");
+      return NLPR_ERR_UNSUPPORTED_SHAPE;
+    }
+    return launch_k<K, 1, FIRST, true>(B, g, x, mu, sig, creg, halo, codes, s);
+  }
   switch (g.key1) {
     case 1:
-      return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST>(B, g, x, mu, sig, creg, halo,
-                                                                  sig_in, sig_out, s);
+      return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST, false>(B, g, x, mu, sig, creg,
+                                                                         halo, nullptr, s);
     case 2:
-      return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST>(B, g, x, mu, sig, creg, halo,
-                                                                  sig_in, sig_out, s);
-    default: return launch_k<K, 4, FIRST>(B, g, x, mu, sig, creg, halo, sig_in, sig_out, s);
+      return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST, false>(B, g, x, mu, sig, creg,
+                                                                         halo, nullptr, s);
+    default: return launch_k<K, 4, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, s);
   }
 }
 
@@ -322,15 +348,15 @@ int sweep_prepare(int K, int items) {
 }
 
 int launch_sweep(const Batch& B, int x, int mu, int sig, int creg, int halo, bool first,
-                 hipStream_t s, const float* sig_in, float* sig_out) {
+                 hipStream_t s, uint8_t* codes) {
   for (const Group& g : B.groups[KD_SWEEP]) {
     if (!g.nitems) continue;
     int rc;
     switch (g.key0) {
 #define NLPR_SW(KK)                                                                            \
   case KK:                                                                                     \
-    rc = first ? launch_items<KK, true>(B, g, x, mu, sig, creg, halo, sig_in, sig_out, s)      \
-               : launch_items<KK, false>(B, g, x, mu, sig, creg, halo, sig_in, sig_out, s);    \
+    rc = first ? launch_items<KK, true>(B, g, x, mu, sig, creg, halo, codes, s)               \
+               : launch_items<KK, false>(B, g, x, mu, sig, creg, halo, codes, s);             \
     break;
       NLPR_SW(0)
       NLPR_SW(1)
