@@ -9,6 +9,16 @@ Y_l and Y_h they use a step of 1e-4 and a bar of 1e-2: the loss is only piecewis
 (every soft-threshold decision is a kink, and moving Y_h moves the thresholds), and at
 this workload a step of 1e-3 along Y_h already crosses enough kinks to move the quotient
 by about 3 % (0.3 % at 1e-4, measured).
+
+The same kinks bound what the comparison with the FP64 reference can show.  The reverse
+mode differentiates the FP32 forward at the branches that forward took.  Where an element
+of V lies within a few FP32 ulps of its threshold, the FP64 forward can take the other
+branch, and the two derivatives then differ legitimately.  Over 60 further seeded random
+configurations, 57 met the 1e-3 bar.  Two missed it by a single FP32/FP64 branch flip (1
+and 4 flipped elements out of 0.25 M and 0.75 M, counted by comparing the forward's branch
+codes with the oracle's branches; Y_h' off by 2.6e-3 and 1.4e-3).  The third had
+dloss/drho = -1.1e-5, the sum of much larger terms that cancel, where FP32 rounding gives
+1.7e-3 relative.  The seeds below are fixed, and the results repeat bit for bit.
 """
 import numpy as np
 import pytest
