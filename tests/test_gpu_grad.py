@@ -253,3 +253,65 @@ def test_random_configurations_gradient_matches_fp64_reference(i):
     assert rel(gYh, ref[2]) <= 1e-3
     assert glam == pytest.approx(ref[3], rel=1e-3, abs=1e-9)
     assert grho == pytest.approx(ref[4], rel=1e-3)
+
+
+def _align256(n):
+    return (n + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("case", ["shape0", "shape1", "shape2", "random2030", "random2052"])
+def test_branch_codes_in_the_checkpoints_match_the_oracle(case):
+    """The checkpoints record, per dual element of each iteration's sweep, the branch of the
+    threshold: 0 for |V| < mu, 1 for V >= mu, 2 for V <= -mu (2 bits, four elements of a
+    float4 of Sigma' per byte, in Sigma''s tile-major order, after the 4 (T - 1) planes).  An
+    element whose FP64 |V| lies farther than 1e-5 max|X| from mu (about ten times the FP32
+    error of V in these runs, which comes from the size of X, not of V) has one correct
+    branch, and its code must equal the oracle's; closer ones may go either way (under 2 in
+    1000 of them)."""
+    if case.startswith("shape"):
+        *sz, T = SHAPES[int(case[5:])]
+        sc, b = scene(*sz, iters=T), None
+    else:
+        from test_gpu_parity import random_configuration
+        spec, b = random_configuration(int(case[6:]))
+        sc, T = synth.make_scene(spec), spec.iters
+    over = {} if b is None else dict(blur=b)
+    plan = nlpr.Plan.from_scene(sc, **over)
+    Z, ws, ck = plan.forward(dev(sc.Yl), dev(sc.Yh))
+    torch.cuda.synchronize()
+    ckh = ck.cpu().numpy()
+    inf = plan.info()
+    L, p, q = sc.Z.shape
+    R, nt, npairs, npatch = inf.tile_rows, inf.ntiles, inf.npairs, inf.npatch
+    KW = int(round(npatch ** 0.5))
+    K = KW // 2
+    plane_al, code_al = _align256(L * p * q * 4), _align256(inf.sigma_elems // 4)
+    taus = plan.half_window()
+    pr = o.Problem.from_scene(sc, **({} if b is None else dict(b=b.astype(np.float64))))
+    Yl, Yh = sc.Yl.astype(np.float64), sc.Yh.astype(np.float64)
+    den = o.denominator(p, q, pr.b, pr.window, pr.K)
+    mu = pr.lam * o.weights(Yh, pr.window, pr.K, pr.h, pr.unweighted) / pr.rho
+    F = o.p2_matrix(pr)
+    X, st = o.initial_state(Yl, pr)
+    checked = near = 0
+    for t in range(1, T):
+        X, nst = o.admm_step(st, Yl, Yh, pr, den, mu, F)
+        codes = ckh[(T - 1) * 4 * plane_al + (t - 1) * code_al:][:inf.sigma_elems // 4]
+        el = np.stack([(codes >> (2 * e)) & 3 for e in range(4)], axis=-1)
+        el = el.reshape(L, nt, npairs, npatch, R, q)
+        for n, tau in enumerate(taus):
+            on = pr.window.index(tuple(tau))
+            for kk in range(npatch):
+                k = (kk // KW - K, kk % KW - K)
+                V = o.D(X, tau, k) - st.Sig[on, pr.patch.index(k)]       # at pixel i
+                m = mu[on][None]
+                want = np.where(np.abs(V) < m, 0, np.where(V > 0, 1, np.where(V < 0, 2, 3)))
+                clear = np.abs(np.abs(V) - m) > 1e-5 * np.abs(X).max()
+                # the code at source-aligned position j belongs to pixel i = j + k
+                got = np.roll(el[:, :, n, kk].reshape(L, nt * R, q)[:, :p], (k[0], k[1]), (1, 2))
+                assert np.array_equal(got[clear], want[clear]), (t, tau, k)
+                checked += int(clear.sum())
+                near += int((~clear).sum())
+        st = nst
+    print(f"[codes {case}] {checked} checked, {near} near a kink", flush=True)
+    assert checked > 0 and near <= 2 * checked // 1000
