@@ -47,6 +47,34 @@ def sweep_bytes_per_launch(spec, npairs: int) -> int:
     return (8 * npairs * npatch + 8) * n * spec.L + 4 * npairs * n
 
 
+def sweep_shape_stream(plan, ws, spec, lx: int, reps: int = 3):
+    """GB/s of the library's sweep-shaped reference stream (nlpr_stream_chunks) over the
+    solve's own dual-state region, run after the timed solves (it overwrites Sigma'): one
+    chunk per (tile, band) workgroup of the sweep, holding the Sigma' that workgroup streams,
+    a step of the 2K+1 planes of one patch row, and the sweep's LDS per workgroup.  The rate
+    is the ceiling of the sweep's access pattern on the same footprint."""
+    import torch
+    from paper_2210_04184_amd import nlpr
+    inf = plan.info()
+    off, nbytes = plan.region(nlpr.REGION_SIGMA)
+    nchunks = lx * inf.ntiles
+    chunk, kw = nbytes // nchunks, 2 * spec.K + 1
+    if chunk == 0 or chunk % (4096 * kw):
+        return None
+    rows, q = inf.tile_rows, spec.q
+    lds = 4 * ((rows + 2 * spec.K) * q + 2 * (rows + inf.halo_rows) * q)
+    run = lambda: nlpr.stream_chunks(ws, chunk, nchunks, lx, kw, lds, offset=off)
+    run()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        run()
+    e.record()
+    torch.cuda.synchronize()
+    return round(2 * chunk * nchunks * reps / (s.elapsed_time(e) * 1e-3) / 1e9, 1)
+
+
 def sweep_kernel_sha() -> str:
     """sha256 of the sweep kernel's source text (between its begin / end markers)."""
     import hashlib
@@ -380,6 +408,9 @@ def main():
         if n:
             stages[name] = {"ms_total": round(ms, 3), "launches": n, "ms_avg": round(ms / n, 4)}
     finite = bool(torch.isfinite(Z).all().item())
+    shape_gbs = sweep_shape_stream(plan, ws, spec, args.subspace or spec.L) if (ref and npairs) else None
+    if shape_gbs:
+        ref["sweep_shape_stream_GBs"] = shape_gbs
 
     pbi = spec.p * spec.q * spec.L * spec.iters * args.steps
     value = pbi / elapsed
@@ -393,7 +424,8 @@ def main():
                 "traffic": None if (args.subspace or args.bands)
                 else measured_traffic(args.config),
                 "bytes_per_launch": bytes_launch,
-                "ms_per_launch": sw["ms_avg"]}
+                "ms_per_launch": sw["ms_avg"],
+                "frac_of_sweep_shape_stream": round(achieved / shape_gbs, 4) if shape_gbs else None}
     # the iterations alone (HIP events around every stage launch, weights and start excluded)
     # against the algorithmic bytes of an iteration: Sigma' read + write plus 16 dense FP32
     # touches (X, BX, C, Lambda1, Lambda2, W1, W2, FFT in/out) per pixel, band and iteration

@@ -369,6 +369,23 @@ int nlpr_batch_destroy(nlpr_batch* batch);
  */
 int nlpr_stream_rmw(void* buf, size_t bytes, void* stream);
 
+/*
+ * A second reference stream, with the sweep's own access shape and none of its arithmetic,
+ * for the ceiling that pattern reaches on a given footprint.  nchunks workgroups of 256
+ * threads; workgroup b owns chunk (b mod bands) * (nchunks / bands) + b / bands of
+ * chunk_bytes contiguous bytes (bands fastest, the order in which the sweep visits its
+ * tile-major dual state).  It negates that chunk in place in steps of `planes` 4 KB planes:
+ * all 16-byte non-temporal loads of a step, then its stores.  lds_bytes of dynamic LDS per
+ * workgroup (not used) limits the workgroups per CU as the sweep's tile does.
+ *   buf: device memory, 16-byte aligned, buf_bytes long; nchunks * chunk_bytes <= buf_bytes.
+ *   chunk_bytes: a positive multiple of 4096 * planes; planes in [1, 8]; nchunks a positive
+ *   multiple of bands; lds_bytes <= 160 KiB.
+ * Asynchronous on `stream`.  NLPR_ERR_INVALID_ARG for a null, host or misaligned buffer or
+ * a bad size.
+ */
+int nlpr_stream_chunks(void* buf, size_t buf_bytes, size_t chunk_bytes, int32_t nchunks,
+                       int32_t bands, int32_t planes, size_t lds_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1259,6 +1259,26 @@ int nlpr_stream_rmw(void* buf, size_t bytes, void* stream) {
   return launch_stream_rmw(static_cast<float*>(buf), bytes / 16, static_cast<hipStream_t>(stream));
 }
 
+int nlpr_stream_chunks(void* buf, size_t buf_bytes, size_t chunk_bytes, int32_t nchunks,
+                       int32_t bands, int32_t planes, size_t lds_bytes, void* stream) {
+  int rc = check_device_ptr(buf, "buf");
+  if (rc) return rc;
+  if (reinterpret_cast<uintptr_t>(buf) % 16) return fail(NLPR_ERR_INVALID_ARG, "buf must be 16-byte aligned");
+  if (planes < 1 || planes > 8) return fail(NLPR_ERR_INVALID_ARG, "planes must lie in [1, 8]");
+  if (chunk_bytes == 0 || chunk_bytes % ((size_t)4096 * planes))
+    return fail(NLPR_ERR_INVALID_ARG, "chunk_bytes must be a positive multiple of 4096 * planes");
+  if (bands < 1 || nchunks < 1 || nchunks % bands)
+    return fail(NLPR_ERR_INVALID_ARG, "nchunks must be a positive multiple of bands");
+  if (chunk_bytes > buf_bytes / (size_t)nchunks)
+    return fail(NLPR_ERR_INVALID_ARG, "nchunks * chunk_bytes exceeds buf_bytes");
+  if (lds_bytes > kMaxSweepLds) return fail(NLPR_ERR_INVALID_ARG, "lds_bytes exceeds 160 KiB");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, buf) != hipSuccess) return fail(NLPR_ERR_HIP, "hipPointerGetAttributes failed");
+  DeviceGuard g(attr.device);
+  return launch_stream_chunks(static_cast<float*>(buf), chunk_bytes / 16, nchunks, bands, planes,
+                              lds_bytes, static_cast<hipStream_t>(stream));
+}
+
 int nlpr_batch_workspace_size(const nlpr_batch* batch, size_t* bytes) {
   if (!batch || !bytes) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
   *bytes = batch->B.ws_bytes;

@@ -828,6 +828,28 @@ __global__ void set_slots_kernel(SceneDesc* sd, SlotSet set) {
 }
 
 // Reference stream: one 16-byte non-temporal load and store per thread, in place.
+// The sweep's access shape without its arithmetic: workgroup b owns chunk
+// (b mod bands) * per_band + b / bands of chunk4 float4s and negates it in place, P planes of
+// 256 float4 (4 KB) at a time, all loads of a step before its stores.  The dynamic LDS the
+// launch asks for is reserved per workgroup but not used: it limits the workgroups per CU as
+// the sweep's tile does.
+template <int P>
+__global__ void __launch_bounds__(256) stream_chunks_kernel(float* buf, size_t chunk4,
+                                                            int per_band, int bands) {
+  const int b = blockIdx.x;
+  const size_t c = (size_t)(b % bands) * per_band + b / bands;
+  gv4f* base = reinterpret_cast<gv4f*>(as_global(buf)) + c * chunk4 + threadIdx.x;
+  const size_t steps = chunk4 / (256 * P);
+  for (size_t st = 0; st < steps; ++st) {
+    gv4f* p = base + st * (256 * P);
+    v4f_t v[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j] = __builtin_nontemporal_load(p + j * 256);
+#pragma unroll
+    for (int j = 0; j < P; ++j) __builtin_nontemporal_store(-v[j], p + j * 256);
+  }
+}
+
 __global__ void __launch_bounds__(256) stream_rmw_kernel(float* buf, size_t n4) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n4) return;
@@ -913,6 +935,35 @@ int launch_stream_rmw(float* buf, size_t n4, hipStream_t s) {
                      n4);
   NLPR_LAUNCH_CHECK("stream_rmw_kernel");
   return NLPR_OK;
+}
+
+template <int P>
+int launch_chunks_p(float* buf, size_t chunk4, int nchunks, int bands, size_t lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(stream_chunks_kernel<P>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kMaxSweepLds));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(stream_chunks_kernel<P>, dim3((unsigned)nchunks), dim3(256), lds, s, buf,
+                     chunk4, nchunks / bands, bands);
+  NLPR_LAUNCH_CHECK("stream_chunks_kernel");
+  return NLPR_OK;
+}
+
+int launch_stream_chunks(float* buf, size_t chunk4, int nchunks, int bands, int planes,
+                         size_t lds, hipStream_t s) {
+  switch (planes) {
+    case 1: return launch_chunks_p<1>(buf, chunk4, nchunks, bands, lds, s);
+    case 2: return launch_chunks_p<2>(buf, chunk4, nchunks, bands, lds, s);
+    case 3: return launch_chunks_p<3>(buf, chunk4, nchunks, bands, lds, s);
+    case 4: return launch_chunks_p<4>(buf, chunk4, nchunks, bands, lds, s);
+    case 5: return launch_chunks_p<5>(buf, chunk4, nchunks, bands, lds, s);
+    case 6: return launch_chunks_p<6>(buf, chunk4, nchunks, bands, lds, s);
+    case 7: return launch_chunks_p<7>(buf, chunk4, nchunks, bands, lds, s);
+    default: return launch_chunks_p<8>(buf, chunk4, nchunks, bands, lds, s);
+  }
 }
 
 int launch_fill(const Batch& B, int slot_, hipStream_t s) {

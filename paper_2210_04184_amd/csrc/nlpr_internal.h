@@ -299,6 +299,8 @@ inline int pixel_split(size_t pixels) { return pixels < 131072 ? 4 : 1; }
 int lowres_blocks(const Plan& P);
 // in-place negation of n4 float4 values with non-temporal 16-byte accesses (reference stream)
 int launch_stream_rmw(float* buf, size_t n4, hipStream_t s);
+int launch_stream_chunks(float* buf, size_t chunk4, int nchunks, int bands, int planes,
+                         size_t lds, hipStream_t s);
 // with a subspace basis: Y_l E^T and Y_l E^+ (once per solve), the P1-update on sampled
 // pixels, and Z = X E
 int launch_project(const Batch& B, int yl, int yle, int ylp, hipStream_t s);

@@ -64,7 +64,8 @@ EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlp
                    "nlpr_plan_get_info", "nlpr_batch_create", "nlpr_batch_workspace_size",
                    "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
                    "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor",
-                   "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward", "nlpr_stream_rmw"])
+                   "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward", "nlpr_stream_rmw",
+                   "nlpr_stream_chunks"])
 
 
 class NlprError(RuntimeError):
@@ -131,6 +132,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_forward.argtypes = [vp, vp, vp, vp, vp, sz, vp, sz, vp]
     lib.nlpr_backward.argtypes = [vp, vp, vp, vp, vp, sz, vp, sz, vp, sz, vp, vp, vp, vp]
     lib.nlpr_stream_rmw.argtypes = [vp, sz, vp]
+    lib.nlpr_stream_chunks.argtypes = [vp, sz, sz, i32, i32, i32, sz, vp]
     for name in EXPORTED:
         if name not in ("nlpr_status_string", "nlpr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -169,6 +171,19 @@ def stream_rmw(buf, stream=None) -> None:
     if buf.dtype != torch.float32:
         raise TypeError("stream_rmw takes a float32 tensor")
     _check(load().nlpr_stream_rmw(_ptr(buf), buf.numel() * 4, _stream_handle(stream)))
+
+
+def stream_chunks(buf, chunk_bytes: int, nchunks: int, bands: int, planes: int,
+                  lds_bytes: int = 0, offset: int = 0, stream=None) -> None:
+    """The sweep-shaped reference stream (nlpr_stream_chunks) on the bytes of the device
+    tensor ``buf`` from ``offset`` on: nchunks chunks of chunk_bytes, negated in place."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous device tensor")
+    nbytes = buf.numel() * buf.element_size()
+    if not 0 <= offset <= nbytes:
+        raise ValueError("offset outside buf")
+    _check(load().nlpr_stream_chunks(_ptr(buf) + offset, nbytes - offset, chunk_bytes, nchunks,
+                                     bands, planes, lds_bytes, _stream_handle(stream)))
 
 
 class Plan:

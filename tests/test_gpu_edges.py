@@ -110,3 +110,33 @@ def test_reference_stream_negates_in_place_and_checks_its_arguments():
     host = np.zeros(16, dtype=np.float32)
     assert lib.nlpr_stream_rmw(host.ctypes.data_as(ctypes.c_void_p), 64, None) == nlpr.ERR_INVALID_ARG
     assert lib.nlpr_stream_rmw(None, 64, None) == nlpr.ERR_INVALID_ARG
+
+
+def test_sweep_shaped_stream_negates_each_chunk_once_and_checks_its_arguments():
+    # 12 chunks of two steps of three 4 KB planes, 4 bands: every chunk is negated exactly
+    # once (a chunk visited twice would come back unchanged), the bytes after them stay
+    import ctypes
+    planes, chunk, nchunks, bands = 3, 2 * 3 * 4096, 12, 4
+    n = nchunks * chunk // 4
+    x = torch.randn(n + 1000, device="cuda")
+    want = torch.cat([-x[:n], x[n:]])
+    nlpr.stream_chunks(x, chunk, nchunks, bands, planes, lds_bytes=40960)
+    torch.cuda.synchronize()
+    assert torch.equal(x, want)
+    # from an offset into a byte buffer (as on a workspace region)
+    w = torch.zeros(4096 + chunk * 2, dtype=torch.uint8, device="cuda")
+    w[4096:].view(torch.float32).fill_(1.0)
+    nlpr.stream_chunks(w, chunk, 2, 2, planes, offset=4096)
+    torch.cuda.synchronize()
+    assert bool((w[4096:].view(torch.float32) == -1.0).all()) and not w[:4096].any()
+    for kw in (dict(planes=0), dict(planes=9), dict(chunk_bytes=chunk + 16),
+               dict(nchunks=10), dict(nchunks=16), dict(lds_bytes=160 * 1024 + 1)):
+        args = dict(chunk_bytes=chunk, nchunks=nchunks, bands=bands, planes=planes, lds_bytes=0)
+        args.update(kw)
+        with pytest.raises(nlpr.NlprError) as e:
+            nlpr.stream_chunks(x, **args)
+        assert e.value.status == nlpr.ERR_INVALID_ARG, kw
+    host = np.zeros(4096, dtype=np.float32)
+    lib = nlpr.load()
+    assert lib.nlpr_stream_chunks(host.ctypes.data_as(ctypes.c_void_p), host.nbytes, 4096, 1, 1,
+                                  1, 0, None) == nlpr.ERR_INVALID_ARG
