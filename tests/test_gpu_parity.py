@@ -395,7 +395,7 @@ def random_configuration(i):
     return spec, b
 
 
-@pytest.mark.parametrize("i", range(40))
+@pytest.mark.parametrize("i", range(100))
 def test_random_configurations_match_oracle(i):
     spec, b = random_configuration(i)
     sc = synth.make_scene(spec)
