@@ -198,6 +198,8 @@ typedef struct nlpr_plan_info {
   int32_t ntiles;       /* ceil(p / R)                                                      */
   int32_t halo_rows;    /* largest tau1 in W+ (rows the adjoint scatter reaches above a tile) */
   int32_t blur_separable; /* 1: the blur has rank one and runs as a row and a column pass  */
+  int32_t sweep_split;  /* workgroups per (tile, band) in the sweep, each over a contiguous
+                           part of W+ (more than 1 for scenes with few tiles x bands)        */
   size_t sigma_elems;   /* floats in the Sigma' region (= L * ntiles * npairs * npatch * R * q) */
 } nlpr_plan_info;
 int nlpr_plan_get_info(const nlpr_plan* plan, nlpr_plan_info* info);

@@ -110,8 +110,12 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
   float* As = Cs + (R + H) * q;           // (R + H) x q   X' accumulator
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
 
-  const int tile = it_.y / L;
-  const int c = it_.y - tile * L;
+  // the forward sweep's work items, y = (tile * psplit + part) * L + band; the adjoint covers
+  // all shifts of a tile in one workgroup, so the items of parts 1 .. psplit-1 have no work
+  const int tp = it_.y / L;
+  const int c = it_.y - tp * L;
+  const int tile = tp / S.psplit;
+  if (tp - tile * S.psplit != 0) return;
   const int r0 = tile * R;
   const int rows = min(R, p - r0);
   const size_t plane = (size_t)p * q;

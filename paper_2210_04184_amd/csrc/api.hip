@@ -185,6 +185,7 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
   factor_23(p, P->fp);
   factor_23(q, P->fq);
   P->sweep = choose_sweep_shape(p, q, prm.K, hrows);
+  P->sweep.split = choose_pair_split(P->sweep.ntiles * Lx, P->npairs);
   auto cleanup = [&](int code) {
     scene_free(P);
     return code;
@@ -270,7 +271,8 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
   take(B_W1, pl);
   take(B_W2, pl);
   take(B_F, (size_t)((Lx + 1) / 2) * plane * sizeof(float2));
-  take(B_HALO, (size_t)Lx * P->sweep.ntiles * P->sweep.halo * q * sizeof(float));
+  take(B_HALO, (size_t)P->sweep.split * Lx * P->sweep.ntiles * P->sweep.halo * q * sizeof(float));
+  take(B_CSPLIT, (size_t)(P->sweep.split - 1) * pl);
   if (E_host) {                            // the X iterate and the projected Y_l
     const size_t lowres = (size_t)(p / prm.d) * (q / prm.d) * Lx * sizeof(float);
     take(B_Z, pl);
@@ -303,6 +305,7 @@ SceneDesc static_desc(const Plan& P) {
   d.rows = P.sweep.rows;
   d.ntiles = P.sweep.ntiles;
   d.halo = P.sweep.halo;
+  d.psplit = P.sweep.split;
   d.fq_tpl = P.fft.q_tpl;
   d.fq_lpb = P.fft.q_lpb;
   d.fp_tpl = P.fft.p_tpl;
@@ -619,7 +622,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     }
     {
       StageTimer tm(B, s, NLPR_STAGE_ASSEMBLE);
-      if ((rc = launch_conv(B, fused ? -1 : B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
+      if ((rc = launch_conv(B, fused ? -1 : B_W1, B_C, true, B_W2, B_C, B_HALO, 2 | 4, s))) return rc;
     }
   }
   if (sub) {
@@ -632,7 +635,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
 // Descriptor of one scene for a solve: workspace regions, observations and output.
 SceneDesc solve_desc(const Plan& P, char* base, const float* Yl, const float* Yh, float* Z) {
   SceneDesc d = static_desc(P);
-  for (int k : {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO})
+  for (int k : {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO, B_CSPLIT})
     d.buf[k] = base + P.off[k];
   d.buf[B_L1O] = d.buf[B_L1];
   d.buf[B_L2O] = d.buf[B_L2];
@@ -843,7 +846,7 @@ int grad_forward(Batch& B, const float* Yl, const float* Yh, float* Z, void* ws,
     if (reg && (rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, t == 1, s,
                                   ck_codes(ck, G, T, t))))
       return rc;
-    if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2, s))) return rc;
+    if ((rc = launch_conv(B, B_W1, B_C, true, B_W2, B_C, B_HALO, 2 | 4, s))) return rc;
   }
   NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
   return NLPR_OK;
@@ -1085,6 +1088,7 @@ int nlpr_plan_get_info(const nlpr_plan* plan, nlpr_plan_info* info) {
   info->ntiles = P.sweep.ntiles;
   info->halo_rows = P.sweep.halo;
   info->blur_separable = P.blur_separable ? 1 : 0;
+  info->sweep_split = P.sweep.split;
   info->sigma_elems = P.sz[B_SIGMA] / sizeof(float);
   return NLPR_OK;
 }
@@ -1183,6 +1187,7 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
       // the B^T kernel over a zero image
       put(B_Z, 0); put(B_MU, 1); put(B_SIGMA, 2); put(B_C, 3);
       scratch(B_HALO, 4, B_HALO);
+      scratch(B_CSPLIT, 4, B_CSPLIT);
       scratch(B_W1, 4, B_W1);
       scratch(B_TMP, 4, B_BX);
       return run([&] {
@@ -1192,7 +1197,7 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
                                stage == NLPR_STAGE_SWEEP_FIRST, s)))
           return r2;
         if ((r2 = launch_fill(B, B_W1, s))) return r2;
-        return launch_conv(B, B_W1, B_C, true, B_TMP, -1, B_HALO, 1, s);
+        return launch_conv(B, B_W1, B_C, true, B_TMP, -1, B_HALO, 1 | 4, s);
       });
     case NLPR_STAGE_ASSEMBLE:
       put(B_W1, 0); put(B_W2, 1); put(B_TMP, 2); put(B_C, 3);

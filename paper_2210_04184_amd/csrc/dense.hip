@@ -473,7 +473,8 @@ __global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
 // regulariser term that the sweep scattered above its tile: halo row h of tile t belongs
 // to image row (t * rows - halo + h) mod p.  Bit 0 / bit 1 of reg_mask mark add1 / add2 as
 // regulariser terms; they and the halo are skipped for scenes without a search window,
-// whose sweep never runs.  Local block = (band, tile row, tile col), tile
+// whose sweep never runs.  Bit 2 adds the planes and halo rows of the sweep's other parts
+// when it splits the shifts of a tile over several workgroups.  Local block = (band, tile row, tile col), tile
 // 16 x 64; each thread produces 4 consecutive outputs of one row, reusing the LDS row it
 // reads for all 4.
 // The blur radius is a template bound RM >= r (1, 2, 4, 8 or 16): the tile carries an RM
@@ -623,8 +624,15 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   // halo rows folded into image row gy2: halo row h of the tile starting at row
   // gy2 + H - h (when that is a tile start); the same for the four columns
   const int H = hb ? S.halo : 0, R = S.rows;
+  // bit 2: the regulariser term comes from a sweep split into psplit parts; parts 1 ..
+  // psplit-1 left their planes in slot B_CSPLIT and every part its own halo rows
+  const int ns = (reg && (reg_mask & 4)) ? S.psplit : 1;
+  const gfloat* cs = ns > 1 ? gslot<const gfloat>(S, B_CSPLIT) : nullptr;
+  const size_t cs_stride = (size_t)S.L * plane;
+  const size_t hb_stride = (size_t)S.L * S.ntiles * H * q;
   const uintptr_t align = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(a1) |
-                          reinterpret_cast<uintptr_t>(a2) | reinterpret_cast<uintptr_t>(hb);
+                          reinterpret_cast<uintptr_t>(a2) | reinterpret_cast<uintptr_t>(hb) |
+                          reinterpret_cast<uintptr_t>(cs);
   if (gx0 + 3 < q && (align & 15) == 0) {
     float4 v = make_float4(acc[0], acc[1], acc[2], acc[3]);
     if (a1) {
@@ -635,11 +643,18 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
       const float4 t = ldg4(a2 + o0);
       v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
     }
+    for (int j = 1; j < ns; ++j) {
+      const float4 t = ldg4(cs + (size_t)(j - 1) * cs_stride + o0);
+      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+    }
     for (int h = 0; h < H; ++h) {
       const int r0 = wrapi(gy2 + H - h, p);
       if (r0 % R) continue;
-      const float4 t = ldg4(hb + (((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx0);
-      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+      const size_t ho = (((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx0;
+      for (int j = 0; j < ns; ++j) {
+        const float4 t = ldg4(hb + (size_t)j * hb_stride + ho);
+        v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+      }
     }
     stg4(out + o0, v);
     return;
@@ -652,9 +667,12 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
     float v = acc[e];
     if (a1) v += a1[o];
     if (a2) v += a2[o];
+    for (int j = 1; j < ns; ++j) v += cs[(size_t)(j - 1) * cs_stride + o];
     for (int h = 0; h < H; ++h) {
       const int r0 = wrapi(gy2 + H - h, p);
-      if (r0 % R == 0) v += hb[(((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx2];
+      if (r0 % R) continue;
+      const size_t ho = (((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx2;
+      for (int j = 0; j < ns; ++j) v += hb[(size_t)j * hb_stride + ho];
     }
     out[o] = v;
   }

@@ -45,6 +45,7 @@ enum Slot {
   B_YLE,     // Y_l E^T, [Ls][p/d][q/d]
   B_YLP,     // Y_l E^+, [Ls][p/d][q/d]
   B_L1O, B_L2O,   // where the P-update writes Lambda1, Lambda2 when not in place (checkpoints)
+  B_CSPLIT,  // regulariser planes of sweep parts 1 .. psplit-1, [psplit-1][L][p][q]
   // reverse mode (single scene): adjoints of the iteration's variables and the outputs
   B_GZ,      // Z' (input)
   B_GC,      // C'
@@ -68,6 +69,7 @@ enum Slot {
 struct SceneDesc {
   int p, q, L, Lh, d, r, K, npairs, npatch;
   int rows, ntiles, halo;          // sweep tiling
+  int psplit;                      // sweep workgroups per (tile, band), each over a part of W+
   int fq_tpl, fq_lpb;              // row FFT: threads per line, lines per block
   int fp_tpl, fp_cb;               // column FFT: threads per line, columns per block
   int init_zero, unweighted;
@@ -102,6 +104,7 @@ struct SweepShape {
   int threads;   // workgroup size
   int ntiles;    // ceil(p / R)
   int halo;      // rows above the tile reached by the adjoint scatter (max tau1)
+  int split;     // workgroups per (tile, band), each over a contiguous part of W+
   size_t lds;    // dynamic LDS bytes
 };
 
@@ -274,7 +277,8 @@ size_t cols_lds(const Plan& P);
 int launch_weights(const Batch& B, int yh, int mu, hipStream_t s);
 int launch_init(const Batch& B, int yl, int ylp, int x0, int l1, int l2, int w2, hipStream_t s);
 // reg_mask: bit 0 / 1 mark add1 / add2 as regulariser terms (skipped, like the halo, for
-// scenes without a search window)
+// scenes without a search window); bit 2 marks them as the forward sweep's output, whose
+// parts 1 .. psplit-1 (slot B_CSPLIT) and halo parts are then added as well
 int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int add2, int halo,
                 int reg_mask, hipStream_t s);
 // Lambda1, Lambda2 are read from slots l1, l2 and written to l1o, l2o (the same slots for an
@@ -342,6 +346,7 @@ int sweep_prepare(int K, int items);   // kernel attributes; call before launche
 
 // ---- shapes and tuning
 SweepShape choose_sweep_shape(int p, int q, int K, int halo);
+int choose_pair_split(int blocks, int npairs);   // SweepShape.split for `blocks` (tile, band) pairs
 size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npatch);
 int fft_block(int tpl);             // workgroup size of a line FFT with tpl threads per line
 int autotune_fft(Plan& P);          // picks P.fft by timing candidates (cached per (p, q, d if fused))

@@ -26,6 +26,12 @@
 // it; since j -> j - tau is one-to-one, the LDS updates of one tau never collide.  The rows
 // above the tile go to a small halo buffer that the right-hand-side assembly folds in, so
 // the result is deterministic (no atomics).
+//
+// Split.  A scene with fewer (tile, band) pairs than the GPU has CUs would leave most of it
+// idle, so each pair is then served by `psplit` workgroups, part j taking the contiguous
+// shifts [j Npairs / psplit, (j+1) Npairs / psplit) of W+.  Part 0 writes the regulariser
+// plane and its halo rows as above, part j > 0 its own plane (slot B_CSPLIT) and halo rows;
+// the assembly adds the parts in a fixed order, so results stay bit-for-bit repeatable.
 #include "nlpr_internal.h"
 
 namespace nlpr {
@@ -67,12 +73,10 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const int2 it_ = items[blockIdx.x];
   const SceneDesc& S = sd[it_.x];
   const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
-            H = S.halo;
+            H = S.halo, split = S.psplit;
   const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
   const gfloat* __restrict__ mu = gslot<const gfloat>(S, mu_s);
   gfloat* sig = gslot<gfloat>(S, sig_s);   // updated in place
-  gfloat* __restrict__ creg = gslot<gfloat>(S, creg_s);
-  gfloat* __restrict__ halo = gslot<gfloat>(S, halo_s);
   constexpr int KW = 2 * K + 1;
   constexpr int NP = KW * KW;
   extern __shared__ float4 lds4[];
@@ -82,11 +86,19 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   float* Xs = Ms + (R + 2 * K) * q;     // (R + H) x q         X rows r0-H .. r0+R-1
   float* Cs = Xs + (R + H) * q;         // (R + H) x q         adjoint accumulator
 
-  const int tile = it_.y / L;
-  const int c = it_.y - tile * L;
+  // work item y = (tile * split + part) * L + band: bands fastest, so that the workgroups
+  // resident together share the tile's thresholds in L2
+  const int tp = it_.y / L;
+  const int c = it_.y - tp * L;
+  const int tile = tp / split;
+  const int part = tp - tile * split;
+  const int n_begin = part * npairs / split, n_end = (part + 1) * npairs / split;
   const int r0 = tile * R;
   const int rows = min(R, p - r0);
   const size_t plane = (size_t)p * q;
+  gfloat* creg = part == 0 ? gslot<gfloat>(S, creg_s)
+                           : gslot<gfloat>(S, B_CSPLIT) + (size_t)(part - 1) * L * plane;
+  gfloat* halo = gslot<gfloat>(S, halo_s) + (size_t)part * L * ntiles * H * q;
   const gfloat* Xc = X + (size_t)c * plane;
 
   for (int e = threadIdx.x; e < (R + H) * q4; e += NT) {
@@ -118,7 +130,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const size_t tstride = (size_t)NP * kstride;      // between shifts
   const size_t tile_off = ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
 
-  for (int n = 0; n < npairs; ++n) {
+  for (int n = n_begin; n < n_end; ++n) {
     const int2 t = tau_at(S, n);
     __syncthreads();  // the previous shift's reads of Ms and updates of Cs are done
     {
@@ -334,7 +346,15 @@ size_t sweep_sigma_bytes(const SweepShape& sh, int q, int L, int npairs, int npa
   return (size_t)L * sh.ntiles * npairs * npatch * sh.rows * q * sizeof(float);
 }
 
-int sweep_blocks(const Plan& P) { return P.sweep.ntiles * P.Lx; }
+// Workgroups per (tile, band): 1 unless the scene has fewer (tile, band) pairs than the GPU
+// has CUs, then enough parts of W+ (at most one shift each) for about one workgroup per CU.
+int choose_pair_split(int blocks, int npairs) {
+  constexpr int kCus = 256;
+  if (blocks <= 0 || blocks >= kCus || npairs <= 1) return 1;
+  return std::min(npairs, (kCus + blocks - 1) / blocks);
+}
+
+int sweep_blocks(const Plan& P) { return P.sweep.ntiles * P.Lx * P.sweep.split; }
 
 int sweep_prepare(int K, int items) {
   switch (K) {

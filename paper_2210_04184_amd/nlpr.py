@@ -88,7 +88,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("npairs", ctypes.c_int32), ("npatch", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("ntiles", ctypes.c_int32),
                 ("halo_rows", ctypes.c_int32), ("blur_separable", ctypes.c_int32),
-                ("sigma_elems", ctypes.c_size_t)]
+                ("sweep_split", ctypes.c_int32), ("sigma_elems", ctypes.c_size_t)]
 
 
 _lib = None

@@ -262,11 +262,31 @@ def test_solve_matches_stored_oracle_anchor():
 
 def test_solve_c1_matches_oracle():
     """The small pansharpening workload: 64x64x8, 7x7 blur, d = 4, patch 3x3, window 5x5,
-    50 iterations."""
+    50 iterations.  Its 4 tiles x 8 bands are far fewer than the GPU's CUs, so the sweep
+    splits the 12 shifts of each tile over 8 workgroups."""
     sc = synth.make_scene(synth.config("c1"))
-    z, _, _ = solve_gpu(sc)
+    z, plan, _ = solve_gpu(sc)
+    assert plan.info().sweep_split == 8
     ref = solve_oracle(sc)
     assert rel_rmse(z, ref) <= 1e-4
+
+
+def test_sweep_split_rule():
+    # one workgroup per (tile, band) from 256 such pairs on (plans only, no solve); below
+    # that, enough parts of W+ for about 256 workgroups, at most one shift each
+    R = np.full((4, 1), 0.25, dtype=np.float32)
+    blur = np.ones((3, 3), dtype=np.float32) / 9
+    kw = dict(Lh=1, d=4, blur=blur, R=R, iters=1, lam=1e-3, rho=1e-2, h=1.0)
+    cases = [((512, 512, 4, 2, 5), 1),     # 256 tiles x 4 bands
+             ((256, 256, 4, 1, 1), 1),     # 64 tiles x 4 bands: exactly 256 pairs
+             ((256, 256, 3, 1, 1), 2),     # 64 tiles x 3 bands: 192 pairs, 2 parts
+             ((128, 128, 4, 1, 1), 4),     # 16 tiles x 4 bands, 4 shifts: one each
+             ((64, 64, 4, 1, 2), 12),      # 4 tiles x 4 bands, 12 shifts: one each
+             ((64, 64, 4, 1, 0), 1)]       # no window
+    for (p, q, L, K, Sw), want in cases:
+        Rl = np.full((L, 1), 1.0 / L, dtype=np.float32)
+        plan = nlpr.Plan(p=p, q=q, L=L, K=K, Sw=Sw, **dict(kw, R=Rl))
+        assert plan.info().sweep_split == want, (p, q, L, K, Sw, plan.info().sweep_split)
 
 
 @pytest.mark.parametrize("name", ["ragged", "radix3", "wide", "thin"])
