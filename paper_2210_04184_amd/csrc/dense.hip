@@ -643,17 +643,29 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
       const float4 t = ldg4(a2 + o0);
       v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
     }
-    for (int j = 1; j < ns; ++j) {
-      const float4 t = ldg4(cs + (size_t)(j - 1) * cs_stride + o0);
-      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+    // the parts are loaded four at a time before they are added (in order; an absent part
+    // adds zero), so their latencies overlap
+    for (int j = 1; j < ns; j += 4) {
+      float4 t[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        t[u] = j + u < ns ? ldg4(cs + (size_t)(j + u - 1) * cs_stride + o0)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { v.x += t[u].x; v.y += t[u].y; v.z += t[u].z; v.w += t[u].w; }
     }
     for (int h = 0; h < H; ++h) {
       const int r0 = wrapi(gy2 + H - h, p);
       if (r0 % R) continue;
       const size_t ho = (((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx0;
-      for (int j = 0; j < ns; ++j) {
-        const float4 t = ldg4(hb + (size_t)j * hb_stride + ho);
-        v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+      for (int j = 0; j < ns; j += 4) {
+        float4 t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          t[u] = j + u < ns ? ldg4(hb + (size_t)(j + u) * hb_stride + ho)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { v.x += t[u].x; v.y += t[u].y; v.z += t[u].z; v.w += t[u].w; }
       }
     }
     stg4(out + o0, v);
@@ -667,12 +679,24 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
     float v = acc[e];
     if (a1) v += a1[o];
     if (a2) v += a2[o];
-    for (int j = 1; j < ns; ++j) v += cs[(size_t)(j - 1) * cs_stride + o];
+    for (int j = 1; j < ns; j += 4) {
+      float t[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] = j + u < ns ? cs[(size_t)(j + u - 1) * cs_stride + o] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v += t[u];
+    }
     for (int h = 0; h < H; ++h) {
       const int r0 = wrapi(gy2 + H - h, p);
       if (r0 % R) continue;
       const size_t ho = (((size_t)c * S.ntiles + r0 / R) * H + h) * q + gx2;
-      for (int j = 0; j < ns; ++j) v += hb[(size_t)j * hb_stride + ho];
+      for (int j = 0; j < ns; j += 4) {
+        float t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = j + u < ns ? hb[(size_t)(j + u) * hb_stride + ho] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v += t[u];
+      }
     }
     out[o] = v;
   }
