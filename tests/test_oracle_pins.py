@@ -442,6 +442,75 @@ def test_admm_reaches_the_optimum_of_an_independent_solver():
         assert f_admm == pytest.approx(f_pd, rel=1e-10)
 
 
+def _brute_force_fused_minimiser(y, edges, w):
+    """Exact minimiser of 1/2 ||y - x||^2 + sum_e w_e |x_a - x_b| by enumerating the branch of
+    every pair: x_a > x_b, x_a < x_b or x_a = x_b.  A pattern holds at the optimum when its
+    optimality system is feasible (stationarity, with subgradients z_e in [-w_e, w_e] on the
+    fused pairs and the given signs on the others), which is a linear program.  The objective
+    is strictly convex, so every feasible pattern gives the same x."""
+    from scipy.optimize import linprog
+    n, sols = len(y), []
+    for pat in itertools.product((1, -1, 0), repeat=len(edges)):
+        fused = [k for k, sg in enumerate(pat) if sg == 0]
+        nf = len(fused)
+        A_eq = np.zeros((n + nf, n + nf))
+        b_eq = np.concatenate([np.asarray(y, dtype=float), np.zeros(nf)])
+        A_eq[:n, :n] = np.eye(n)
+        A_ub, b_ub = [], []
+        for k, (a, b) in enumerate(edges):
+            if pat[k]:
+                b_eq[a] -= w[k] * pat[k]
+                b_eq[b] += w[k] * pat[k]
+                row = np.zeros(n + nf)
+                row[a], row[b] = -pat[k], pat[k]          # pat (x_a - x_b) >= 0
+                A_ub.append(row)
+                b_ub.append(0.0)
+        for j, k in enumerate(fused):
+            a, b = edges[k]
+            A_eq[a, n + j] += 1.0
+            A_eq[b, n + j] -= 1.0
+            A_eq[n + j, a], A_eq[n + j, b] = 1.0, -1.0    # x_a = x_b
+        res = linprog(np.zeros(n + nf), A_ub=np.array(A_ub) if A_ub else None,
+                      b_ub=np.array(b_ub) if b_ub else None, A_eq=A_eq, b_eq=b_eq,
+                      bounds=[(None, None)] * n + [(-w[k], w[k]) for k in fused], method="highs")
+        if res.status == 0:
+            sols.append(res.x[:n])
+    assert sols
+    X = np.array(sols)
+    assert np.ptp(X, axis=0).max() <= 1e-9        # one minimiser
+    return X[0]
+
+
+@pytest.mark.parametrize("p,q,lam", [(1, 4, 0.02), (1, 4, 0.05), (2, 2, 0.02), (1, 6, 0.05)])
+def test_admm_reaches_the_brute_force_active_set_solution(p, q, lam):
+    """With d = 1, B = I and lambda_1 = 0, eq. (ouroptim) is the weighted nonlocal TV
+    denoising of Y_l: 1/2 ||Y_l - X||^2 + lambda_2 sum_{tau in W} sum_i omega_{i tau}
+    |X(i) - X(i - tau)| (patch 1 x 1).  Its exact minimiser comes from enumerating the branch of
+    every pixel pair; the cases cover no fusion (1 x 4, lambda_2 = 0.02) and partial fusion
+    (3 distinct values of 4 or 6).  Theorem 1: ADMM reaches it from any start and rho."""
+    rng = np.random.default_rng(7)
+    pr = o.Problem(p=p, q=q, L=1, d=1, b=np.ones((1, 1)), R=np.ones((1, 1)), K=0, S=1, lam=lam,
+                   rho=1.0, h=0.8, lam1=0.0)
+    Yl = rng.uniform(0, 1, (1, p, q))
+    Yh = rng.uniform(0, 1, (1, p, q))
+    om = o.weights(Yh, pr.window, pr.K, pr.h, pr.unweighted)
+    pix = lambda a, b: (a % p) * q + (b % q)
+    wsum = {}
+    for n, t in enumerate(pr.window):
+        for i1 in range(p):
+            for i2 in range(q):
+                u, v = pix(i1, i2), pix(i1 - t[0], i2 - t[1])
+                if u != v:
+                    key = (min(u, v), max(u, v))
+                    wsum[key] = wsum.get(key, 0.0) + lam * om[n][i1, i2]
+    edges = sorted(wsum)
+    xs = _brute_force_fused_minimiser(Yl.ravel(), edges, np.array([wsum[e] for e in edges]))
+    for rho, iters in ((1.0, 3000), (0.3, 6000)):
+        pr.rho = rho
+        X = o.solve(Yl, Yh, pr, iters, init="zero").X.ravel()
+        assert np.abs(X - xs).max() <= 1e-9
+
+
 @pytest.mark.parametrize("S,rho,iters", [(0, 0.5, 500), (1, 0.1, 3000)])
 def test_lambda2_zero_with_square_R_gives_the_least_squares_solution(S, rho, iters):
     # lambda2 = 0 and an invertible L x L response: the unique minimiser solves the normal
