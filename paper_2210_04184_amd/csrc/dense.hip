@@ -869,8 +869,7 @@ __global__ void set_slots_kernel(SceneDesc* sd, SlotSet set) {
   if (i < set.n) sd->buf[set.slot[i]] = set.ptr[i];
 }
 
-// Reference stream: one 16-byte non-temporal load and store per thread, in place.
-// The sweep's access shape without its arithmetic: workgroup b owns chunk
+// Reference stream with the sweep's access shape and none of its arithmetic: workgroup b owns chunk
 // (b mod bands) * per_band + b / bands of chunk4 float4s and negates it in place, P planes of
 // 256 float4 (4 KB) at a time, all loads of a step before its stores.  The dynamic LDS the
 // launch asks for is reserved per workgroup but not used: it limits the workgroups per CU as
@@ -892,6 +891,7 @@ __global__ void __launch_bounds__(256) stream_chunks_kernel(float* buf, size_t c
   }
 }
 
+// Reference stream: one 16-byte non-temporal load and store per thread, in place.
 __global__ void __launch_bounds__(256) stream_rmw_kernel(float* buf, size_t n4) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n4) return;
