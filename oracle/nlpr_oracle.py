@@ -48,7 +48,8 @@ Readings of points the paper leaves open:
 from __future__ import annotations
 
 import dataclasses
-from typing import List, Optional, Sequence, Tuple
+from concurrent.futures import ThreadPoolExecutor
+from typing import Callable, Iterator, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -394,30 +395,56 @@ def initial_state(Yl: np.ndarray, pr: Problem, init: str = "upsample") -> Tuple[
     return X0, st
 
 
-def rhs(st: State, pr: Problem) -> np.ndarray:
+# The (tau, k) loops below may run on a thread pool (``workers`` > 1).  That changes no
+# arithmetic: every (tau, k) term is computed by the same numpy calls, the Q and Sigma
+# updates write disjoint slices, and the terms of the sum over (tau, k) are still added
+# to C one at a time in the serial loop order, so the result is bit-identical to one worker.
+def _in_order(pool: Optional[ThreadPoolExecutor], fn: Callable, items: Sequence) -> Iterator:
+    """fn(x) for every x of ``items``, yielded in the order of ``items``.  With a pool, a
+    few items per worker are computed at a time, so at most that many results are held."""
+    if pool is None:
+        for x in items:
+            yield fn(x)
+        return
+    step = 4 * pool._max_workers
+    for s in range(0, len(items), step):
+        yield from pool.map(fn, items[s:s + step])
+
+
+def _pairs(pr: Problem) -> List[Tuple[int, Offset, int, Offset]]:
+    """(n, tau, m, k) for tau = window[n], k = patch[m], in the loop order of the sums."""
+    return [(n, t, m, k) for n, t in enumerate(pr.window) for m, k in enumerate(pr.patch)]
+
+
+def rhs(st: State, pr: Problem, pool: Optional[ThreadPoolExecutor] = None) -> np.ndarray:
     """C = B^T(P1 + Lambda1) + P2 + Lambda2 + sum_tau sum_k D_{tau k}^T (Q_{tau k} + Sigma_{tau k})
     (after eq. (x_linear_system_main))."""
     C = blur_T(st.P1 + st.Lam1, pr.b) + st.P2 + st.Lam2
-    for n, t in enumerate(pr.window):
-        for m, k in enumerate(pr.patch):
-            C += D_T(st.Q[n, m] + st.Sig[n, m], t, k)
+    term = lambda a: D_T(st.Q[a[0], a[2]] + st.Sig[a[0], a[2]], a[1], a[3])
+    for T in _in_order(pool, term, _pairs(pr)):
+        C += T
     return C
 
 
 def admm_step(st: State, Yl: np.ndarray, Yh: np.ndarray, pr: Problem, den: np.ndarray,
-              mu: np.ndarray, F: np.ndarray) -> Tuple[np.ndarray, State]:
+              mu: np.ndarray, F: np.ndarray,
+              pool: Optional[ThreadPoolExecutor] = None) -> Tuple[np.ndarray, State]:
     """One ADMM iteration t -> t+1 in the paper's order.  ``mu`` = lambda2 omega / rho."""
-    X = x_update(rhs(st, pr), den)                                   # eq. (inv)
+    X = x_update(rhs(st, pr, pool), den)                             # eq. (inv)
     BX = blur(X, pr.b)
     P1 = p1_update(BX, st.Lam1, Yl, pr)                              # eq. (Qh_update)
     P2 = p2_update(X, st.Lam2, Yh, pr, F)                            # eq. (Qm_update)
     Q = np.empty_like(st.Q)
     Sig = np.empty_like(st.Sig)
-    for n, t in enumerate(pr.window):
-        for m, k in enumerate(pr.patch):
-            DX = D(X, t, k)
-            Q[n, m] = soft_threshold(DX - st.Sig[n, m], mu[n][None])  # eq. (Qj_main)
-            Sig[n, m] = st.Sig[n, m] - (DX - Q[n, m])                 # eq. (dualvar3_main)
+
+    def q_sigma(a):
+        n, t, m, k = a
+        DX = D(X, t, k)
+        Q[n, m] = soft_threshold(DX - st.Sig[n, m], mu[n][None])      # eq. (Qj_main)
+        Sig[n, m] = st.Sig[n, m] - (DX - Q[n, m])                     # eq. (dualvar3_main)
+
+    for _ in _in_order(pool, q_sigma, _pairs(pr)):
+        pass
     Lam1 = st.Lam1 - (BX - P1)                                       # eq. (dualvar1_main)
     Lam2 = st.Lam2 - (X - P2)                                        # eq. (dualvar2_main)
     return X, State(P1=P1, P2=P2, Q=Q, Lam1=Lam1, Lam2=Lam2, Sig=Sig)
@@ -498,9 +525,18 @@ class Result:
 
 def solve(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, init: str = "upsample",
           track: bool = False, state: Optional[Tuple[np.ndarray, State]] = None,
-          monitor_every: int = 0) -> Result:
+          monitor_every: int = 0, workers: int = 1) -> Result:
     """Run ``iters`` ADMM iterations; X^{(iters)} and Z = X E.  With monitor_every = N > 0,
-    ``monitor`` holds a record after iterations N, 2N, ... and after the last one."""
+    ``monitor`` holds a record after iterations N, 2N, ... and after the last one.
+    ``workers`` > 1 runs the (tau, k) loops of the paper's splitting on that many threads,
+    with results bit-identical to one worker."""
+    if workers > 1 and not pr.fused:
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            return _solve(Yl, Yh, pr, iters, init, track, state, monitor_every, pool)
+    return _solve(Yl, Yh, pr, iters, init, track, state, monitor_every, None)
+
+
+def _solve(Yl, Yh, pr, iters, init, track, state, monitor_every, pool) -> Result:
     Yl = Yl.astype(np.float64)
     Yh = Yh.astype(np.float64)
     den = denominator(pr.p, pr.q, pr.b, pr.window, pr.K)
@@ -514,7 +550,7 @@ def solve(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, init: str = "
         C0 = blur_T(decimate_T(Yl, pr.d, pr.p, pr.q), pr.b) / pr.rho
         step = lambda st_: admm_step_fused(st_, Yl, Yh, pr, a, C0, mu, F)
     else:
-        step = lambda st_: admm_step(st_, Yl, Yh, pr, den, mu, F)
+        step = lambda st_: admm_step(st_, Yl, Yh, pr, den, mu, F, pool)
     objs: List[float] = []
     res: List[float] = []
     mons: List[Monitor] = []

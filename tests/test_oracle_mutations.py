@@ -28,6 +28,8 @@ FAST_PINS = [
     lambda: pins.test_objective_terms_equal_dense_operator_forms(None),
     lambda: pins.test_primal_residuals_are_the_lambda_steps(None),
     lambda: pins.test_fused_x_update_equals_dense_solve(8, 12, 2, 1, 1),
+    pins.test_initial_state_by_index_loops,
+    pins.test_initial_state_hand_computed,
 ]
 
 _orig = {name: getattr(o, name) for name in dir(o) if callable(getattr(o, name))}
@@ -73,7 +75,7 @@ def _mut_shift(X, t):                # shift in the wrong direction
     return np.roll(X, shift=(-t[0], -t[1]), axis=(-2, -1))
 
 
-def _mut_rhs(st, pr):                # dropped Lambda2 from the right-hand side
+def _mut_rhs(st, pr, pool=None):     # dropped Lambda2 from the right-hand side
     C = o.blur_T(st.P1 + st.Lam1, pr.b) + st.P2
     for n, t in enumerate(pr.window):
         for m, k in enumerate(pr.patch):
@@ -93,8 +95,8 @@ MUTATIONS = {
 }
 
 
-def _admm_dual_sign(st, Yl, Yh, pr, den, mu, F):      # dual update with the wrong sign
-    X, nst = _orig["admm_step"](st, Yl, Yh, pr, den, mu, F)
+def _admm_dual_sign(st, Yl, Yh, pr, den, mu, F, pool=None):   # dual update with the wrong sign
+    X, nst = _orig["admm_step"](st, Yl, Yh, pr, den, mu, F, pool)
     BX = o.blur(X, pr.b)
     nst.Lam1 = st.Lam1 + (BX - nst.P1)
     return X, nst
@@ -123,6 +125,18 @@ def _mut_aliasing_groups(p, q, d):                      # aliases along one axis
     return rows, np.repeat(cols[:, :1], cols.shape[1], axis=1)
 
 
+def _mut_upsample(Yl, d):                              # upsample shifted by one pixel
+    return np.roll(_orig["upsample_nn"](Yl, d), 1, axis=-1)
+
+
+def _mut_initial_state(Yl, pr, init="upsample"):       # P1 started at X0 instead of B X0
+    X0, st = _orig["initial_state"](Yl, pr, init)
+    st.P1 = X0.copy()
+    return X0, st
+
+
+MUTATIONS["upsample_nn"] = _mut_upsample
+MUTATIONS["initial_state"] = _mut_initial_state
 MUTATIONS["objective_terms"] = _mut_objective_terms
 MUTATIONS["fused_denominator"] = _mut_fused_denominator
 MUTATIONS["aliasing_groups"] = _mut_aliasing_groups

@@ -312,6 +312,46 @@ def test_subspace_admm_reaches_the_optimum_of_an_independent_solver():
     np.testing.assert_allclose(vec(res.Z), vec(res.X) @ pr.E, atol=1e-14)
 
 
+def test_initial_state_by_index_loops():
+    """The start (the paper names the initial values but does not give them; the reading
+    is X0 = nearest-neighbour upsample of Y_l, P1 = B X0, P2 = X0, all else 0), checked
+    with pure-Python index loops and the dense blur matrix, on a non-square image with
+    decimation 3 and an asymmetric blur."""
+    pr, Yl, Yh = tiny_problem(p=6, q=9, L=2, d=3, r=1)
+    X0, st = o.initial_state(Yl, pr)
+    ref = np.zeros((pr.L, pr.p, pr.q))
+    for c in range(pr.L):
+        for i1 in range(pr.p):
+            for i2 in range(pr.q):
+                ref[c, i1, i2] = Yl[c, i1 // pr.d, i2 // pr.d]
+    np.testing.assert_array_equal(X0, ref)
+    Bm = dense_blur(pr.p, pr.q, pr.b)
+    for c in range(pr.L):
+        np.testing.assert_allclose(st.P1[c].ravel(), Bm @ ref[c].ravel(), atol=1e-14)
+    np.testing.assert_array_equal(st.P2, ref)
+    for f in ("Q", "Sig", "Lam1", "Lam2"):
+        assert not np.any(getattr(st, f)), f
+    assert st.Q.shape == st.Sig.shape == (len(pr.window), len(pr.patch), pr.L, pr.p, pr.q)
+    Xz, sz = o.initial_state(Yl, pr, init="zero")
+    for a in (Xz, sz.P1, sz.P2, sz.Q, sz.Sig, sz.Lam1, sz.Lam2):
+        assert not np.any(a)
+
+
+def test_initial_state_hand_computed():
+    """A 2 x 2 Y_l with d = 2 and the two-tap blur b(0, 0) = b(0, 1) = 1/2, written out by
+    hand: X0 repeats each low-resolution pixel over its 2 x 2 block, and
+    P1(i) = (X0(i1, i2) + X0(i1, i2 - 1)) / 2 with the column index taken mod 4."""
+    b = np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.0, 0.0, 0.0]])
+    pr = o.Problem(p=4, q=4, L=1, d=2, b=b, R=np.ones((1, 1)), K=0, S=1, lam=0.1,
+                   rho=0.5, h=1.0)
+    Yl = np.array([[[1.0, 2.0], [3.0, 4.0]]])
+    X0, st = o.initial_state(Yl, pr)
+    np.testing.assert_array_equal(X0[0], [[1, 1, 2, 2], [1, 1, 2, 2], [3, 3, 4, 4], [3, 3, 4, 4]])
+    np.testing.assert_allclose(st.P1[0], [[1.5, 1, 1.5, 2], [1.5, 1, 1.5, 2],
+                                          [3.5, 3, 3.5, 4], [3.5, 3, 3.5, 4]], atol=1e-15)
+    np.testing.assert_array_equal(st.P2[0], X0[0])
+
+
 def test_subspace_start_is_the_least_squares_coefficient_image():
     pr, Yl, Yh = tiny_problem(Ls=2)
     X0, _ = o.initial_state(Yl, pr)
@@ -645,3 +685,14 @@ def test_fused_admm_reaches_the_optimum_of_an_independent_solver():
     f = _dense_objective(vec(res.X).T.ravel(), H, bb, c0, G, w)
     assert f == pytest.approx(f_pd, rel=1e-10)
     assert res.monitor[-1].r1 == 0.0 and res.monitor[-1].r2 < 1e-9
+
+
+def test_thread_pool_gives_bit_identical_iterates():
+    """``workers`` > 1 runs the (tau, k) loops on threads and must not change a bit: the
+    terms of C are still added in the serial order."""
+    pr, Yl, Yh = tiny_problem(p=8, q=12, L=3, Lh=2, d=2, K=1, S=2, lam=0.05, rho=0.3)
+    a = o.solve(Yl, Yh, pr, 6, workers=1)
+    b = o.solve(Yl, Yh, pr, 6, workers=5)
+    np.testing.assert_array_equal(a.X, b.X)
+    for f in ("P1", "P2", "Q", "Lam1", "Lam2", "Sig"):
+        np.testing.assert_array_equal(getattr(a.state, f), getattr(b.state, f))
