@@ -29,8 +29,12 @@
  *     stream.
  *   - Every function returns an nlpr_status.  No C++ exception crosses the ABI.  On error
  *     nlpr_last_error() returns a message for the calling thread.
- *   - Functions are thread-safe for distinct plans.  Calls that share a plan or a
- *     workspace must not overlap.
+ *   - Functions are thread-safe for distinct plans.  Host calls that share a plan must not
+ *     overlap (one host thread at a time per plan).  On the device, the work of successive
+ *     calls on one plan runs in call order even when the calls pass different streams:
+ *     each call's stream first waits for the device work of the previous call on that
+ *     plan.  Concurrent solves therefore need one plan each; calls that share a workspace
+ *     must not run concurrently on the device.
  */
 #ifndef NLPR_H
 #define NLPR_H

@@ -507,9 +507,14 @@ int batch_build(Batch& B) {
 }
 
 // Write the descriptors (sizes, tables, buffers) to the device if they changed.  The pinned
-// staging copy is rewritten only after the previous upload from it has completed.
+// staging copy is rewritten only after the previous upload from it has completed.  Every
+// call that launches work on a plan comes through here first, and its stream waits for the
+// device work of the previous call on the plan (done_ev, recorded at the end of each call):
+// the previous call's kernels read the device descriptor until they finish, so calls on one
+// plan run on the device in the order they were made, whatever streams they use.
 int upload_desc(Batch& B, const std::vector<SceneDesc>& descs, hipStream_t s) {
   const size_t n = descs.size();
+  NLPR_HIP_TRY(hipStreamWaitEvent(s, B.done_ev, 0));
   if (B.desc_valid && std::memcmp(B.uploaded.data(), descs.data(), n * sizeof(SceneDesc)) == 0)
     return NLPR_OK;
   NLPR_HIP_TRY(hipEventSynchronize(B.upload_ev));
@@ -1162,7 +1167,9 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
     descs[0] = d;
     int r2 = upload_desc(B, descs, s);
     if (r2) return r2;
-    return body();
+    if ((r2 = body())) return r2;
+    NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
+    return NLPR_OK;
   };
   switch (stage) {
     case NLPR_STAGE_WEIGHTS:
