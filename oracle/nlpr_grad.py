@@ -69,8 +69,16 @@ def weights(Yh: torch.Tensor, pr: Problem) -> torch.Tensor:
 
 
 def unrolled(Yl: torch.Tensor, Yh: torch.Tensor, lam: torch.Tensor, rho: torch.Tensor,
-             pr: Problem, iters: int, init: str = "upsample") -> torch.Tensor:
-    """X^(iters) of the paper's iteration (E = I), differentiable in Yl, Yh, lam, rho."""
+             pr: Problem, iters: int, init: str = "upsample", segments: int = 0) -> torch.Tensor:
+    """X^(iters) of the paper's iteration (E = I), differentiable in Yl, Yh, lam, rho.
+
+    ``segments`` > 0 changes only what reverse mode keeps in memory, not a single value:
+    the iterations run in that many segments, each a recomputation checkpoint
+    (``torch.utils.checkpoint``, non-reentrant) whose iterations are checkpoints in turn.
+    The forward then keeps only the state entering each segment; the backward of a segment
+    reruns it keeping the state entering each of its iterations, and the backward of an
+    iteration reruns that iteration.  Every rerun repeats the same float64 operations on
+    the same values, so the gradient is the same, bit for bit."""
     assert pr.E is None and not pr.fused
     p, q, L, d = pr.p, pr.q, pr.L, pr.d
     W, P = pr.window, patch_offsets(pr.K)
@@ -94,34 +102,71 @@ def unrolled(Yl: torch.Tensor, Yh: torch.Tensor, lam: torch.Tensor, rho: torch.T
     YhRt = (Yh.reshape(Yh.shape[0], -1).T @ R.T)                     # n_h x L
     mu = lam * weights(Yh, pr) / rho                                  # thresholds of eq. (Qj_main)
     shape = (L, p, q)
-    if init == "upsample":
-        X = Yl.repeat_interleave(d, dim=-2).repeat_interleave(d, dim=-1)
-        P1, P2 = blur(X), X
-    else:
-        P1 = P2 = torch.zeros(shape, dtype=DT)
-    Lam1 = torch.zeros(shape, dtype=DT)
-    Lam2 = torch.zeros(shape, dtype=DT)
-    Q = [[torch.zeros(shape, dtype=DT) for _ in P] for _ in W]
-    Sig = [[torch.zeros(shape, dtype=DT) for _ in P] for _ in W]
-    for _ in range(iters):
+    nwp = len(W) * len(P)
+
+    def step(*state):
+        """One iteration.  state = (P1, P2, Lam1, Lam2, Q..., Sigma...) with Q and Sigma
+        listed for (tau, k) in the loop order; returns (X, new state...)."""
+        P1, P2, Lam1, Lam2 = state[:4]
+        Q, Sig = state[4:4 + nwp], state[4 + nwp:]
         C = blur_T(P1 + Lam1) + P2 + Lam2
-        for a, t in enumerate(W):
-            for m, k in enumerate(P):
-                C = C + _DT(Q[a][m] + Sig[a][m], t, k)
+        n = 0
+        for t in W:
+            for k in P:
+                C = C + _DT(Q[n] + Sig[n], t, k)
+                n += 1
         X = torch.fft.ifft2(torch.fft.fft2(C) / den).real             # eq. (inv)
         BX = blur(X)
         P1 = (mask * (rho * BX + StYl - rho * Lam1) / (1.0 + rho)
               + (1.0 - mask) * (BX - Lam1))                            # eq. (Qh_update), E = I
         A = (X - Lam2).reshape(L, -1).T + (pr.lam1 / rho) * YhRt
         P2 = (A @ F).T.reshape(shape)                                 # eq. (Qm_update)
+        Qn, Sn = [], []
+        n = 0
         for a, t in enumerate(W):
-            for m, k in enumerate(P):
-                V = _D(X, t, k) - Sig[a][m]
-                Q[a][m] = torch.sign(V) * torch.relu(torch.abs(V) - mu[a])   # eq. (Qj_main)
-                Sig[a][m] = -(V - Q[a][m])                             # eq. (dualvar3_main)
+            for k in P:
+                V = _D(X, t, k) - Sig[n]
+                Qn.append(torch.sign(V) * torch.relu(torch.abs(V) - mu[a]))   # eq. (Qj_main)
+                Sn.append(-(V - Qn[-1]))                                 # eq. (dualvar3_main)
+                n += 1
         Lam1 = Lam1 - (BX - P1)                                       # eq. (dualvar1_main)
         Lam2 = Lam2 - (X - P2)                                        # eq. (dualvar2_main)
-    return X
+        return (X, P1, P2, Lam1, Lam2, *Qn, *Sn)
+
+    if init == "upsample":
+        X = Yl.repeat_interleave(d, dim=-2).repeat_interleave(d, dim=-1)
+        P1, P2 = blur(X), X
+    else:
+        P1 = P2 = torch.zeros(shape, dtype=DT)
+    zeros = lambda: torch.zeros(shape, dtype=DT)
+    state = (P1, P2, zeros(), zeros(), *[zeros() for _ in range(2 * nwp)])
+    if iters == 0:
+        return X if init == "upsample" else torch.zeros(shape, dtype=DT)
+    if segments <= 0:
+        for _ in range(iters):
+            X, *state = step(*state)
+        return X
+
+    from torch.utils.checkpoint import checkpoint
+
+    def run(n_iter):
+        def seg(*st):
+            out = None
+            for _ in range(n_iter):
+                out = checkpoint(step, *st, use_reentrant=False)
+                st = out[1:]
+            return out
+        return seg
+
+    bounds = [iters * j // segments for j in range(segments + 1)]
+    out = None
+    for j in range(segments):
+        n_iter = bounds[j + 1] - bounds[j]
+        if n_iter == 0:
+            continue
+        out = checkpoint(run(n_iter), *state, use_reentrant=False)
+        state = out[1:]
+    return out[0]
 
 
 def mse(X: torch.Tensor, Zt: torch.Tensor) -> torch.Tensor:
@@ -129,14 +174,15 @@ def mse(X: torch.Tensor, Zt: torch.Tensor) -> torch.Tensor:
 
 
 def gradient(Yl: np.ndarray, Yh: np.ndarray, pr: Problem, iters: int, Zt: np.ndarray,
-             init: str = "upsample"):
+             init: str = "upsample", segments: int = 0):
     """Loss = mean((X^(iters) - Zt)^2) and its gradient with respect to
-    (Y_l, Y_h, lambda_2, rho), all float64."""
+    (Y_l, Y_h, lambda_2, rho), all float64.  ``segments``: see ``unrolled``."""
     yl = torch.tensor(np.asarray(Yl, dtype=np.float64), requires_grad=True)
     yh = torch.tensor(np.asarray(Yh, dtype=np.float64), requires_grad=True)
     lam = torch.tensor(float(pr.lam), dtype=DT, requires_grad=True)
     rho = torch.tensor(float(pr.rho), dtype=DT, requires_grad=True)
-    loss = mse(unrolled(yl, yh, lam, rho, pr, iters, init), torch.as_tensor(Zt, dtype=DT))
+    loss = mse(unrolled(yl, yh, lam, rho, pr, iters, init, segments),
+               torch.as_tensor(Zt, dtype=DT))
     loss.backward()
     return (loss.item(), yl.grad.numpy(), yh.grad.numpy(), lam.grad.item(), rho.grad.item())
 

@@ -66,3 +66,15 @@ def test_gradient_from_the_zero_start():
     fd = (g.loss_at(Yl + 1e-6 * v, Yh, pr, 3, Zt, init="zero")
           - g.loss_at(Yl - 1e-6 * v, Yh, pr, 3, Zt, init="zero")) / 2e-6
     assert float(np.sum(gYl * v)) == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("segments", [1, 2, 3])
+def test_recomputation_checkpoints_leave_every_bit(segments):
+    """Segments of recomputation change what reverse mode keeps, not the arithmetic."""
+    pr, Yl, Yh = problem(seed=6)
+    Zt = np.random.default_rng(3).uniform(0, 1, (pr.L, pr.p, pr.q))
+    a = g.gradient(Yl, Yh, pr, 5, Zt)
+    b = g.gradient(Yl, Yh, pr, 5, Zt, segments=segments)
+    assert a[0] == b[0] and a[3] == b[3] and a[4] == b[4]
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
