@@ -67,8 +67,12 @@ enum {
   NLPR_UNWEIGHTED = 1u << 2,    /* omega = 1 (ablation cases C2 / C4 of the paper)                    */
   NLPR_LOCAL_WINDOW = 1u << 3,  /* W = {0, +-e1, +-e2}: local pixel differences (ablation C5);
                                    requires Sw == 1                                                  */
-  NLPR_CHECK_FINITE = 1u << 4,  /* nlpr_solve checks Z for NaN/Inf at the end; this synchronises
-                                   the stream and may return NLPR_ERR_NUMERICAL                      */
+  NLPR_CHECK_FINITE = 1u << 4,  /* check the iterate X for NaN/Inf on the device after every 8th
+                                   iteration and after the last one, without waiting; the
+                                   first checked iteration that finds one is kept in a device
+                                   flag, which nlpr_solve reads once at the end (this
+                                   synchronises the stream) and then returns NLPR_ERR_NUMERICAL
+                                   (see nlpr_nonfinite_iteration)                                   */
   NLPR_TIMING = 1u << 5,        /* record HIP events around every stage; read with nlpr_stage_time   */
   NLPR_GRAPH = 1u << 6,         /* capture the whole solve (weights, start, all iterations) in a HIP
                                    graph on the first call and replay it on later calls; ignored
@@ -175,6 +179,11 @@ int nlpr_workspace_size(const nlpr_plan* plan, size_t* bytes);
  */
 int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void* ws,
                size_t ws_bytes, void* stream);
+
+/* For plans created with NLPR_CHECK_FINITE (else NLPR_ERR_NOT_ENABLED): the iteration t
+ * whose check (t = 8, 16, ... and the last; 0 for a solve of 0 iterations) first found NaN
+ * or Inf in the iterate during the last solve, or -1 if none did.  iter : host, receives t. */
+int nlpr_nonfinite_iteration(const nlpr_plan* plan, int32_t* iter);
 
 /* Release the plan and its device tables.  NULL is accepted. */
 int nlpr_plan_destroy(nlpr_plan* plan);

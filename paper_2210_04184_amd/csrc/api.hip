@@ -1,6 +1,7 @@
 // C ABI of libnlpr: plans and batches, workspace layout, the ADMM solve sequence, per-stage
 // entry points for testing, stage timing and graph capture.  See include/nlpr.h.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -574,6 +575,8 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
   // solve, so the per-iteration right-hand side W2 + C_reg stays of the size of X.  W1
   // holds Xc0 and L1 serves as scratch.
   const bool fused = (B.flags & NLPR_FUSED_S) != 0;
+  const bool check = (B.flags & NLPR_CHECK_FINITE) != 0;
+  if (check && (rc = launch_finite_clear(B.d_flag, s))) return rc;
   if (sub) {
     StageTimer tm(B, s, NLPR_STAGE_INIT);
     if ((rc = launch_project(B, B_YL, B_YLE, B_YLP, s))) return rc;
@@ -606,6 +609,9 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
       StageTimer tm(B, s, NLPR_STAGE_XSOLVE);
       if ((rc = launch_xsolve(B, B_C, B_Z, B_F, fused ? B_W1 : -1, s))) return rc;
     }
+    if (check && ((t + 1) % kFiniteEvery == 0 || t + 1 == B.iters) &&
+        (rc = launch_finite(B, B_Z, B.d_flag, t + 1, s)))
+      return rc;
     if (!fused || mon) {           // fused-S needs B X only for the monitor's data term
       StageTimer tm(B, s, NLPR_STAGE_BLUR);
       if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
@@ -630,6 +636,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
       if ((rc = launch_conv(B, fused ? -1 : B_W1, B_C, true, B_W2, B_C, B_HALO, 2 | 4, s))) return rc;
     }
   }
+  if (check && B.iters == 0 && (rc = launch_finite(B, B_Z, B.d_flag, 0, s))) return rc;
   if (sub) {
     StageTimer tm(B, s, NLPR_STAGE_INIT);
     if ((rc = launch_compose(B, B_Z, B_OUT, s))) return rc;
@@ -716,11 +723,14 @@ int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float*
   NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
   B.mon_last = monitor_points(B.iters, B.monitor_every);
   if (B.flags & NLPR_CHECK_FINITE) {
-    if ((rc = launch_finite(B, B_Z, B.d_flag, s))) return rc;
+    // the checks ran inside the solve without waiting; read their verdict once
     int hflag = 0;
     NLPR_HIP_TRY(hipMemcpyAsync(&hflag, B.d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     NLPR_HIP_TRY(hipStreamSynchronize(s));
-    if (hflag) return fail(NLPR_ERR_NUMERICAL, "NaN or Inf in Z");
+    B.nonfinite_iter = hflag == INT_MAX ? -1 : hflag;
+    if (B.nonfinite_iter >= 0)
+      return fail(NLPR_ERR_NUMERICAL, "NaN or Inf in the iterate X, first found by the check "
+                                      "after iteration " + std::to_string(B.nonfinite_iter));
   }
   return NLPR_OK;
 }
@@ -1107,6 +1117,14 @@ int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void
                size_t ws_bytes, void* stream) {
   if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
   return batch_solve(plan->B, &Yl, &Yh, &Z, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int nlpr_nonfinite_iteration(const nlpr_plan* plan, int32_t* iter) {
+  if (!plan || !iter) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  if (!(plan->B.flags & NLPR_CHECK_FINITE))
+    return fail(NLPR_ERR_NOT_ENABLED, "created without NLPR_CHECK_FINITE");
+  *iter = plan->B.nonfinite_iter;
+  return NLPR_OK;
 }
 
 int nlpr_monitor(const nlpr_plan* plan, double* trace, int32_t cap, int32_t* n) {

@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <climits>
+
 #include "nlpr_internal.h"
 
 namespace nlpr {
@@ -453,18 +455,20 @@ fill_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   if (e < (size_t)S.L * S.p * S.q) gslot<gfloat>(S, s_)[e] = 0.f;
 }
 
-// flag[0] |= 1 if any element of the slot is NaN or Inf (the flag is cleared beforehand by
-// a one-thread launch, so no memset is recorded into a captured graph)
+// flag[0] = min(flag[0], iter) if any element of the slot is NaN or Inf.  The flag is set to
+// INT_MAX at the start of a solve by a one-thread launch (so no memset is recorded into a
+// captured graph); it then holds the first checked iteration that found a non-finite value.
 __global__ void __launch_bounds__(256)
 finite_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int z_s,
-              int* flag) {
+              int* flag, int iter) {
   const int2 it = items[blockIdx.x];
   const SceneDesc& S = sd[it.x];
   const size_t e = (size_t)it.y * 256 + threadIdx.x;
-  if (e < (size_t)S.L * S.p * S.q && !isfinite(gslot<const gfloat>(S, z_s)[e])) flag[0] = 1;
+  if (e < (size_t)S.L * S.p * S.q && !isfinite(gslot<const gfloat>(S, z_s)[e]))
+    atomicMin(flag, iter);
 }
 
-__global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
+__global__ void clear_flag_kernel(int* flag) { flag[0] = INT_MAX; }
 
 // ------------------------------------------------------------------------------- conv
 // out(i) = sum_m b(m) in(i - m)      (B, circular convolution)        TR = false
@@ -1012,10 +1016,14 @@ int launch_fill(const Batch& B, int slot_, hipStream_t s) {
   return launch_groups(B, KD_PLANE, "fill_kernel", fill_kernel, s, slot_);
 }
 
-int launch_finite(const Batch& B, int z, int* flag, hipStream_t s) {
+int launch_finite_clear(int* flag, hipStream_t s) {
   hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
   NLPR_LAUNCH_CHECK("clear_flag_kernel");
-  return launch_groups(B, KD_PLANE, "finite_kernel", finite_kernel, s, z, flag);
+  return NLPR_OK;
+}
+
+int launch_finite(const Batch& B, int z, int* flag, int iter, hipStream_t s) {
+  return launch_groups(B, KD_PLANE, "finite_kernel", finite_kernel, s, z, flag, iter);
 }
 
 int conv_class(int r) {

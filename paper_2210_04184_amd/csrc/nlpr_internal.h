@@ -180,7 +180,8 @@ struct Batch {
   bool desc_valid = false;
   hipEvent_t upload_ev = nullptr;
   std::vector<Group> groups[KD_COUNT];
-  int* d_flag = nullptr;           // result of the finite check
+  int* d_flag = nullptr;           // finite check: first checked iteration with NaN / Inf
+  int nonfinite_iter = -1;         // what the last checked solve found (-1: nothing)
   // graph
   bool use_graph = false;
   hipGraphExec_t graph = nullptr;
@@ -333,7 +334,10 @@ int launch_weights_bwd(const Batch& B, int yh, int mub, int eb, int part, int w0
 int launch_yh_bwd(const Batch& B, int yh, int eb, int gyh, hipStream_t s);
 int launch_upsample_bwd(const Batch& B, int x0b, int gyl, hipStream_t s);
 int launch_grad_scalars(const Batch& B, int part, int npix, int nw, double* out, hipStream_t s);
-int launch_finite(const Batch& B, int z, int* flag, hipStream_t s);
+// Finite check every kFiniteEvery iterations (and after the last) with NLPR_CHECK_FINITE.
+constexpr int kFiniteEvery = 8;
+int launch_finite_clear(int* flag, hipStream_t s);
+int launch_finite(const Batch& B, int z, int* flag, int iter, hipStream_t s);
 int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] slot
 int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s);   // S^T Y_l / rho
 // X = solve(C) (+ add, a [L][p][q] slot, when add >= 0); the fused-S system for fused scenes

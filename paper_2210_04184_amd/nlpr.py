@@ -65,7 +65,7 @@ EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlp
                    "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
                    "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor",
                    "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward", "nlpr_stream_rmw",
-                   "nlpr_stream_chunks"])
+                   "nlpr_stream_chunks", "nlpr_nonfinite_iteration"])
 
 
 class NlprError(RuntimeError):
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_plan_create.argtypes = [ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(vp)]
     lib.nlpr_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.nlpr_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.nlpr_nonfinite_iteration.argtypes = [vp, ctypes.POINTER(i32)]
     lib.nlpr_plan_destroy.argtypes = [vp]
     lib.nlpr_status_string.argtypes = [ctypes.c_int]
     lib.nlpr_status_string.restype = ctypes.c_char_p
@@ -287,6 +288,13 @@ class Plan:
         _check(load().nlpr_solve(self.handle, _ptr(Yl), _ptr(Yh), _ptr(Z), _ptr(ws),
                                  ws.numel() * ws.element_size(), _stream_handle(stream)))
         return Z, ws
+
+    def nonfinite_iteration(self) -> int:
+        """With CHECK_FINITE: the first checked iteration of the last solve that found NaN or
+        Inf in the iterate, or -1."""
+        t = ctypes.c_int32()
+        _check(load().nlpr_nonfinite_iteration(self.handle, ctypes.byref(t)))
+        return t.value
 
     def stage(self, stage: int, bufs, stream=None):
         arr = (ctypes.c_void_p * len(bufs))(*[_ptr(b) for b in bufs])
