@@ -180,6 +180,23 @@ int nlpr_workspace_size(const nlpr_plan* plan, size_t* bytes);
 int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void* ws,
                size_t ws_bytes, void* stream);
 
+/*
+ * nlpr_solve for callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it).  Same result as
+ * nlpr_solve, bit for bit, but the workspace is a static device array inside the library
+ * of NLPR_NOALLOC_WORKSPACE_BYTES (64 MiB); each GPU the library runs on holds one until
+ * the process ends.  No device memory is allocated or freed by this call.
+ *   Yl, Yh, Z : as for nlpr_solve.
+ * Errors: NLPR_ERR_WORKSPACE_TOO_SMALL when nlpr_workspace_size() exceeds
+ * NLPR_NOALLOC_WORKSPACE_BYTES; NLPR_ERR_INVALID_ARG for a plan created with NLPR_STATE_IN,
+ * NLPR_GRAPH or NLPR_TIMING.  Every call on one GPU shares that GPU's array and leaves its
+ * state there: calls that overlap on one GPU (from any plan, stream or thread) race and
+ * give undefined results.  Asynchronous on `stream` unless NLPR_CHECK_FINITE is set.
+ */
+#define NLPR_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+int nlpr_solve_noalloc(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z,
+                       void* stream);
+
 /* For plans created with NLPR_CHECK_FINITE (else NLPR_ERR_NOT_ENABLED): the iteration t
  * whose check (t = 8, 16, ... and the last; 0 for a solve of 0 iterations) first found NaN
  * or Inf in the iterate during the last solve, or -1 if none did.  iter : host, receives t. */

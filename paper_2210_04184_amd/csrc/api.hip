@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -666,10 +667,10 @@ SceneDesc solve_desc(const Plan& P, char* base, const float* Yl, const float* Yh
 }
 
 int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float* const* Z,
-                void* ws, size_t ws_bytes, hipStream_t s) {
+                void* ws, size_t ws_bytes, hipStream_t s, bool ws_is_static = false) {
   const int n = (int)B.scenes.size();
   int rc;
-  if ((rc = check_device_ptr(ws, "ws"))) return rc;
+  if (!ws_is_static && (rc = check_device_ptr(ws, "ws"))) return rc;
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NLPR_ERR_INVALID_ARG, "ws must be 256-byte aligned");
   if (ws_bytes < B.ws_bytes)
     return fail(NLPR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than the required size");
@@ -1117,6 +1118,59 @@ int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void
                size_t ws_bytes, void* stream) {
   if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
   return batch_solve(plan->B, &Yl, &Yh, &Z, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------- solve without any allocation
+// The workspace of nlpr_solve_noalloc: a file-scope device array.  Each GPU the library runs
+// on holds its own copy, at its own address, until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): it uses the device address that hipGetSymbolAddress returns, looked up once per
+// device with that device current and kept below.
+static __device__ __align__(256) unsigned char scratch[NLPR_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev`, which must be the current device.
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return fail(NLPR_ERR_HIP, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(NLPR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                    hipGetErrorString(e));
+    if (reinterpret_cast<uintptr_t>(ptr) % 256)
+      return fail(NLPR_ERR_HIP, "the static workspace is not 256-byte aligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NLPR_OK;
+}
+}  // namespace
+
+int nlpr_solve_noalloc(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z,
+                       void* stream) {
+  if (!plan) return fail(NLPR_ERR_INVALID_ARG, "plan is NULL");
+  Batch& B = plan->B;
+  if (B.ws_bytes > NLPR_NOALLOC_WORKSPACE_BYTES)
+    return fail(NLPR_ERR_WORKSPACE_TOO_SMALL,
+                "nlpr_solve_noalloc: the plan needs a workspace of " + std::to_string(B.ws_bytes) +
+                    " bytes, more than the static workspace of " +
+                    std::to_string((size_t)NLPR_NOALLOC_WORKSPACE_BYTES) +
+                    " bytes; use nlpr_solve with a caller workspace");
+  if (B.flags & (NLPR_STATE_IN | NLPR_GRAPH | NLPR_TIMING))
+    return fail(NLPR_ERR_INVALID_ARG,
+                "nlpr_solve_noalloc takes plans without NLPR_STATE_IN, NLPR_GRAPH and NLPR_TIMING");
+  DeviceGuard dg(B.device);
+  void* ws = nullptr;
+  int rc = scratch_address(B.device, &ws);
+  if (rc) return rc;
+  return batch_solve(B, &Yl, &Yh, &Z, ws, NLPR_NOALLOC_WORKSPACE_BYTES,
+                     static_cast<hipStream_t>(stream), true);
 }
 
 int nlpr_nonfinite_iteration(const nlpr_plan* plan, int32_t* iter) {

@@ -65,7 +65,10 @@ EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlp
                    "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
                    "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor",
                    "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward", "nlpr_stream_rmw",
-                   "nlpr_stream_chunks", "nlpr_nonfinite_iteration"])
+                   "nlpr_stream_chunks", "nlpr_solve_noalloc", "nlpr_nonfinite_iteration"])
+
+# size of the library's static workspace used by nlpr_solve_noalloc (include/nlpr.h)
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 
 class NlprError(RuntimeError):
@@ -106,6 +109,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_plan_create.argtypes = [ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(vp)]
     lib.nlpr_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.nlpr_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.nlpr_solve_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.nlpr_nonfinite_iteration.argtypes = [vp, ctypes.POINTER(i32)]
     lib.nlpr_plan_destroy.argtypes = [vp]
     lib.nlpr_status_string.argtypes = [ctypes.c_int]
@@ -295,6 +299,13 @@ class Plan:
         t = ctypes.c_int32()
         _check(load().nlpr_nonfinite_iteration(self.handle, ctypes.byref(t)))
         return t.value
+
+    def solve_noalloc(self, Yl, Yh, Z, stream=None):
+        """nlpr_solve_noalloc: the solve with the library's static workspace; Z is the
+        caller's output tensor.  Calls that overlap on one GPU race (they share the array)."""
+        _check(load().nlpr_solve_noalloc(self.handle, _ptr(Yl), _ptr(Yh), _ptr(Z),
+                                         _stream_handle(stream)))
+        return Z
 
     def stage(self, stage: int, bufs, stream=None):
         arr = (ctypes.c_void_p * len(bufs))(*[_ptr(b) for b in bufs])
