@@ -39,12 +39,28 @@ def workload_name(spec) -> str:
 
 
 def sweep_bytes_per_launch(spec, npairs: int) -> int:
-    """Algorithmic HBM bytes of one sweep launch: Sigma' read + write (8 B per pair, patch
-    offset, pixel and band), X read and C write (8 B per pixel and band), thresholds mu read
-    once (4 B per pair and pixel)."""
+    """HBM bytes of one sweep launch were Sigma' stored densely: Sigma' read + write (8 B per
+    pair, patch offset, pixel and band), X read and C write (8 B per pixel and band),
+    thresholds mu read once (4 B per pair and pixel)."""
     npatch = (2 * spec.K + 1) ** 2
     n = spec.p * spec.q
     return (8 * npairs * npatch + 8) * n * spec.L + 4 * npairs * n
+
+
+def coded_sweep_bytes(spec, npairs: int, lx: int, counts):
+    """Algorithmic HBM bytes of each sweep launch of a solve with the coded Sigma' (one code
+    byte per float4 item, and 16 B per open item): launch t reads the codes and open items
+    launch t-1 wrote (nothing for t = 0) and writes its own, plus X read, C write and mu read
+    once.  counts[t] = open items written by launch t (nlpr_sweep_counts)."""
+    npatch = (2 * spec.K + 1) ** 2
+    n = spec.p * spec.q
+    items = npairs * npatch * n * lx // 4
+    fixed = 8 * n * lx + 4 * npairs * n
+    out = []
+    for t, c in enumerate(counts):
+        rd = (items + 16 * counts[t - 1]) if t > 0 else 0
+        out.append(fixed + rd + items + 16 * c)
+    return out
 
 
 def sweep_shape_stream(plan, ws, spec, lx: int, reps: int = 3):
@@ -86,9 +102,9 @@ def sweep_kernel_sha() -> str:
 
 
 def measured_traffic(config: str):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it was
-    taken on the current sweep source and workload; else None."""
-    import hashlib
+    """The committed rocprofv3 counter record of the sweep (HBM bytes per launch of the
+    profiled launches, and their ratio to the algorithmic bytes of the same launches), if it
+    was taken on the current sweep source and workload; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -97,7 +113,7 @@ def measured_traffic(config: str):
         return None
     if rec.get("sweep_source_sha256") != sha or rec.get("config") != config:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
 
 
 def hbm_reference(gib: float):
@@ -129,43 +145,70 @@ def hbm_reference(gib: float):
     return out
 
 
-def cpu_baseline(seconds_target: float = 15.0):
-    """The FP64 oracle on a sample of the same workload: a 64 x 64 x 16-band scene from the
-    same generator with the same guide bands, blur, decimation, patch and window."""
+def host_cores() -> int:
+    """Cores this process may use (its CPU affinity), at most 16: the host share one GPU
+    comes with."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                        "")
+    except OSError:
+        return ""
+
+
+def cpu_baseline(seconds_target: float = 12.0):
+    """The FP64 oracle on a sample of the same workload: a 32 x 32 scene with all 128 bands
+    of the HS+MS workload, its 4-band guide, 9x9 blur, decimation 4, patch 5x5 and window
+    11x11, drawn by the same generator; ADMM iterations until ``seconds_target`` has passed,
+    once on every usable host core (the oracle's (shift, patch offset) loops on a thread
+    pool, results bit-identical to one thread) and once on one thread."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import synth
     from oracle import nlpr_oracle as o
 
-    spec = synth.config("c3", p=64, q=64, L=16, iters=1)
+    spec = synth.config("c3", p=32, q=32, iters=1)
     sc = synth.make_scene(spec)
     pr = o.Problem.from_scene(sc)
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        iters = 0
-        X, st = o.initial_state(sc.Yl.astype(np.float64), pr)
-        den = o.denominator(pr.p, pr.q, pr.b, pr.window, pr.K)
-        mu = pr.lam * o.weights(sc.Yh.astype(np.float64), pr.window, pr.K, pr.h) / pr.rho
-        F = o.p2_matrix(pr)
-        while True:
-            X, st = o.admm_step(st, sc.Yl.astype(np.float64), sc.Yh.astype(np.float64), pr, den,
-                                mu, F)
-            iters += 1
-            if time.perf_counter() - t0 >= seconds_target:
-                break
-        dt = time.perf_counter() - t0
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
-                         "")
-    except OSError:
-        pass
-    return {"value": spec.p * spec.q * spec.L * iters / dt, "unit": "pixel*band*iter/s",
-            "cores": 1, "kind": "oracle", "host": {"cpu": model, "cpu_count": os.cpu_count()},
-            "sample": f"literal FP64 oracle, 64x64x16 bands, Lh=4, patch 5x5, window 11x11, "
-                      f"{iters} iterations incl. weights/setup in {dt:.1f} s, 1 thread"}
+    Yl, Yh = sc.Yl.astype(np.float64), sc.Yh.astype(np.float64)
+
+    def timed(workers):
+        with threadpool_limits(1), ThreadPoolExecutor(max_workers=workers) as pool:
+            t0 = time.perf_counter()
+            iters = 0
+            X, st = o.initial_state(Yl, pr)
+            den = o.denominator(pr.p, pr.q, pr.b, pr.window, pr.K)
+            mu = pr.lam * o.weights(Yh, pr.window, pr.K, pr.h) / pr.rho
+            F = o.p2_matrix(pr)
+            while True:
+                X, st = o.admm_step(st, Yl, Yh, pr, den, mu, F, pool if workers > 1 else None)
+                iters += 1
+                if time.perf_counter() - t0 >= seconds_target:
+                    break
+            return iters, time.perf_counter() - t0
+
+    cores = host_cores()
+    it_n, dt_n = timed(cores)
+    it_1, dt_1 = timed(1)
+    pb = spec.p * spec.q * spec.L
+    return {"value": pb * it_n / dt_n, "unit": "pixel*band*iter/s", "cores": cores,
+            "kind": "oracle",
+            "host": {"cpu": cpu_model(), "cpu_count": os.cpu_count(), "cores_used": cores},
+            "one_thread_value": pb * it_1 / dt_1,
+            "sample": f"literal FP64 oracle, 32x32x128 bands, Lh=4, 9x9 blur, d=4, patch 5x5, "
+                      f"window 11x11: {it_n} iterations incl. weights/setup in {dt_n:.1f} s on "
+                      f"{cores} threads; {it_1} in {dt_1:.1f} s on 1 thread"}
 
 
 def run_batch(args):
@@ -329,6 +372,8 @@ def main():
                     help="override the band count (e.g. 16: one GPU's share of the 128-band "
                          "scene split over 8 GPUs by bands)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 3x3 plain-solve leg of the default run")
     ap.add_argument("--subspace", type=int, default=0,
                     help="Ls > 0: solve for Z = X E with E the Ls leading right singular "
                          "vectors of Y_l")
@@ -368,82 +413,15 @@ def main():
     ref = hbm_reference(args.calib_gib) if args.calib_gib > 0 else None
     if ref:
         log(f"[bench] reference streams: {ref}")
-    log(f"[bench] generating {workload_name(spec)}")
-    sc = synth.make_scene(spec)
-    dev = torch.device("cuda:0")
-    Yl = torch.from_numpy(sc.Yl).to(dev)
-    Yh = torch.from_numpy(sc.Yh).to(dev)
-    E = None
-    if args.subspace:
-        M = sc.Yl.reshape(spec.L, -1).T.astype(np.float64)
-        E = np.ascontiguousarray(np.linalg.svd(M, full_matrices=False)[2][:args.subspace],
-                                 dtype=np.float32)
-    flags = (nlpr.GRAPH if args.graph else nlpr.TIMING) | (nlpr.FUSED_S if args.fused else 0)
-    plan = nlpr.Plan.from_scene(sc, flags=flags, E=E, monitor_every=args.monitor)
-    npairs = len(plan.half_window())
-    ws = plan.alloc_workspace()
-    Z = torch.empty((spec.L, spec.p, spec.q), dtype=torch.float32, device=dev)
-    log(f"[bench] workspace {plan.workspace_bytes / 1e9:.1f} GB; warmup {args.warmup}")
-    for i in range(args.warmup):
-        plan.solve(Yl, Yh, Z=Z, ws=ws)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {i + 1} done")
-    if not args.graph:
-        for st in nlpr.STAGE_NAMES:
-            plan.stage_time(st, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    step_s = []
-    for i in range(args.steps):
-        t1 = time.perf_counter()
-        plan.solve(Yl, Yh, Z=Z, ws=ws)
-        torch.cuda.synchronize()
-        step_s.append(time.perf_counter() - t1)
-        log(f"[bench] step {i + 1} done at {time.perf_counter() - t0:.2f} s")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = {}
-    for st, name in ([] if args.graph else nlpr.STAGE_NAMES.items()):
-        ms, n = plan.stage_time(st)
-        if n:
-            stages[name] = {"ms_total": round(ms, 3), "launches": n, "ms_avg": round(ms / n, 4)}
-    finite = bool(torch.isfinite(Z).all().item())
-    shape_gbs = sweep_shape_stream(plan, ws, spec, args.subspace or spec.L) if (ref and npairs) else None
-    if shape_gbs:
-        ref["sweep_shape_stream_GBs"] = shape_gbs
-
-    pbi = spec.p * spec.q * spec.L * spec.iters * args.steps
-    value = pbi / elapsed
-    sw = stages.get("sweep")
-    roof = None
-    if sw:
-        bytes_launch = sweep_bytes_per_launch(spec.replace(L=args.subspace or spec.L), npairs)
-        achieved = bytes_launch / (sw["ms_avg"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "sweep_kernel", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if (args.subspace or args.bands)
-                else measured_traffic(args.config),
-                "bytes_per_launch": bytes_launch,
-                "ms_per_launch": sw["ms_avg"],
-                "frac_of_sweep_shape_stream": round(achieved / shape_gbs, 4) if shape_gbs else None}
-    # the iterations alone (HIP events around every stage launch, weights and start excluded)
-    # against the algorithmic bytes of an iteration: Sigma' read + write plus 16 dense FP32
-    # touches (X, BX, C, Lambda1, Lambda2, W1, W2, FFT in/out) per pixel, band and iteration
-    loop_ms = sum(v["ms_total"] for k, v in stages.items() if k not in ("weights", "init"))
-    lx = args.subspace or spec.L
-    loop_bytes_pbi = 8 * npairs * (2 * spec.K + 1) ** 2 + 64
-    loop = None
-    if loop_ms:
-        gbs = loop_bytes_pbi * spec.p * spec.q * lx * spec.iters * args.steps / (loop_ms * 1e-3) / 1e9
-        loop = {"t_loop_ms_per_solve": round(loop_ms / args.steps, 3),
-                "t_total_ms_per_solve": round(elapsed / args.steps * 1e3, 3),
-                "step_ms_median": round(sorted(step_s)[len(step_s) // 2] * 1e3, 3),
-                "bytes_per_pbi": loop_bytes_pbi, "achieved_GBs": round(gbs, 1),
-                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    res = measure_solve(spec, args.steps, args.warmup, subspace=args.subspace, graph=args.graph,
+                        fused=args.fused, monitor=args.monitor, shape_stream=ref is not None,
+                        traffic_key=None if (args.subspace or args.bands) else args.config)
+    if ref and res["sweep_shape_stream_GBs"]:
+        ref["sweep_shape_stream_GBs"] = res["sweep_shape_stream_GBs"]
     out = {
         "metric": "ADMM pixel*band*iter/s (+ % HBM roofline) at <=1e-4 rel. RMSE vs FP64 oracle",
-        "value": value, "unit": "pixel*band*iter/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "value": res["value"], "unit": "pixel*band*iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload_name(spec) + (f", subspace Ls={args.subspace}"
@@ -454,18 +432,143 @@ def main():
                    "Lh": spec.Lh, "d": spec.d, "blur": 2 * spec.blur_radius + 1,
                    "patch": 2 * spec.K + 1, "window": 2 * spec.Sw + 1, "iters": spec.iters,
                    "lambda": spec.lam, "rho": spec.rho, "seed": spec.seed},
-        "roofline": roof,
-        "loop_pbi_per_s": spec.p * spec.q * spec.L * spec.iters * args.steps / (loop_ms * 1e-3)
-        if loop_ms else None,
-        "loop": loop,
-        "stages": stages, "finite": finite, "hbm_reference": ref,
+        "roofline": res["roofline"],
+        "loop_pbi_per_s": res["loop_pbi_per_s"],
+        "loop": res["loop"],
+        "stages": res["stages"], "finite": res["finite"], "hbm_reference": ref,
     }
     if args.monitor:
-        out["monitor"] = [dict(zip(nlpr.MON_FIELDS, map(float, r))) for r in plan.monitor()]
+        out["monitor"] = res["monitor"]
+    if args.config == "c3" and not (args.subspace or args.bands or args.fused or args.graph
+                                    or args.iters is not None) and not args.no_small:
+        # the paper's own window and patch (3x3 / 3x3) on the differentiated workload's
+        # scene, plain solve: the same measurement at a small dual state
+        c5 = synth.config("c5")
+        log(f"[bench] 3x3 leg: {workload_name(c5)}")
+        r5 = measure_solve(c5, 10, 2, shape_stream=ref is not None)
+        out["w3p3_plain_solve"] = {
+            "workload": workload_name(c5), "pbi_per_s": r5["value"],
+            "ms_per_solve": r5["ms_per_step"], "loop": r5["loop"], "roofline": r5["roofline"],
+            "stages": r5["stages"], "finite": r5["finite"]}
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a sample")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def measure_solve(spec, steps, warmup, subspace=0, graph=False, fused=False, monitor=0,
+                  shape_stream=False, traffic_key=None):
+    """Solve one synthetic scene `warmup` + `steps` times with the inputs resident in HBM and
+    report throughput, per-stage HIP-event times, the loop's HBM fraction and the sweep's
+    roofline (and its rate against the sweep-shaped reference stream)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2210_04184_amd import nlpr
+
+    log(f"[bench] generating {workload_name(spec)}")
+    sc = synth.make_scene(spec)
+    dev = torch.device("cuda:0")
+    Yl = torch.from_numpy(sc.Yl).to(dev)
+    Yh = torch.from_numpy(sc.Yh).to(dev)
+    E = None
+    if subspace:
+        M = sc.Yl.reshape(spec.L, -1).T.astype(np.float64)
+        E = np.ascontiguousarray(np.linalg.svd(M, full_matrices=False)[2][:subspace],
+                                 dtype=np.float32)
+    flags = (nlpr.GRAPH if graph else nlpr.TIMING) | (nlpr.FUSED_S if fused else 0)
+    plan = nlpr.Plan.from_scene(sc, flags=flags, E=E, monitor_every=monitor)
+    npairs = len(plan.half_window())
+    ws = plan.alloc_workspace()
+    Z = torch.empty((spec.L, spec.p, spec.q), dtype=torch.float32, device=dev)
+    log(f"[bench] workspace {plan.workspace_bytes / 1e9:.1f} GB; warmup {warmup}")
+    for i in range(warmup):
+        plan.solve(Yl, Yh, Z=Z, ws=ws)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1} done")
+    if not graph:
+        for st in nlpr.STAGE_NAMES:
+            plan.stage_time(st, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_s = []
+    for i in range(steps):
+        t1 = time.perf_counter()
+        plan.solve(Yl, Yh, Z=Z, ws=ws)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t1)
+        log(f"[bench] step {i + 1} done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = {}
+    for st, name in ([] if graph else nlpr.STAGE_NAMES.items()):
+        ms, n = plan.stage_time(st)
+        if n:
+            stages[name] = {"ms_total": round(ms, 3), "launches": n, "ms_avg": round(ms / n, 4)}
+    finite = bool(torch.isfinite(Z).all().item())
+    lx = subspace or spec.L
+    shape_gbs = sweep_shape_stream(plan, ws, spec, lx) if (shape_stream and npairs) else None
+    value = spec.p * spec.q * spec.L * spec.iters * steps / elapsed
+    sw = stages.get("sweep")
+    roof = None
+    counts = plan.sweep_counts() if (npairs and not graph) else []
+    sweep_bytes = coded_sweep_bytes(spec, npairs, lx, counts) if counts else []
+    if sw and len(sweep_bytes) > 1:
+        # the timed "sweep" launches are iterations 2 .. T of every solve (the first sweep of a
+        # solve, which reads no state, is timed as "sweep_first")
+        bytes_launch = sum(sweep_bytes[1:]) / len(sweep_bytes[1:])
+        achieved = bytes_launch / (sw["ms_avg"] * 1e-3) / 1e9
+        dense = sweep_bytes_per_launch(spec.replace(L=lx), npairs)
+        items = npairs * (2 * spec.K + 1) ** 2 * spec.p * spec.q * lx // 4
+        roof = {"bound": "hbm", "kernel": "sweep_kernel", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_launch": round(bytes_launch),
+                "ms_per_launch": sw["ms_avg"],
+                "open_item_fraction": round(sum(counts[1:]) / len(counts[1:]) / items, 4),
+                "dense_format_bytes_per_launch": dense,
+                "dense_format_equivalent_GBs": round(dense / (sw["ms_avg"] * 1e-3) / 1e9, 1),
+                "frac_of_sweep_shape_stream": round(achieved / shape_gbs, 4) if shape_gbs else None}
+    tr = measured_traffic(traffic_key) if (traffic_key and roof) else None
+    if tr:
+        roof["traffic"] = tr["hbm_bytes_per_launch"]
+        roof["traffic_launches"] = tr.get("launches")
+        roof["traffic_over_algorithmic"] = tr.get("traffic_over_algorithmic")
+    # the iterations alone (HIP events around every stage launch, weights and start excluded):
+    # bytes of an iteration = the sweep's (coded Sigma', X, C, mu) + 16 dense FP32 touches of
+    # the other stages (X, BX, C, Lambda1, Lambda2, W1, W2, FFT in/out) per pixel and band;
+    # also against the bytes the dual state would move stored densely (8 N_pairs |P| + 64 B
+    # per pixel, band and iteration)
+    loop_ms = sum(v["ms_total"] for k, v in stages.items() if k not in ("weights", "init"))
+    loop_bytes_pbi = 8 * npairs * (2 * spec.K + 1) ** 2 + 64
+    loop = None
+    if loop_ms:
+        pbi = spec.p * spec.q * lx * spec.iters * steps
+        dense_gbs = loop_bytes_pbi * pbi / (loop_ms * 1e-3) / 1e9
+        loop = {"t_loop_ms_per_solve": round(loop_ms / steps, 3),
+                "t_total_ms_per_solve": round(elapsed / steps * 1e3, 3),
+                "step_ms_median": round(sorted(step_s)[len(step_s) // 2] * 1e3, 3),
+                "dense_format_bytes_per_pbi": loop_bytes_pbi,
+                "dense_format_equivalent_GBs": round(dense_gbs, 1),
+                "dense_format_hbm_frac": round(dense_gbs / HBM_PEAK_GBS, 4)}
+        if sweep_bytes:
+            coded = (sum(sweep_bytes) + 64 * spec.p * spec.q * lx * spec.iters) * steps
+            gbs = coded / (loop_ms * 1e-3) / 1e9
+            loop.update({"bytes_per_solve": sum(sweep_bytes) + 64 * spec.p * spec.q * lx *
+                         spec.iters, "achieved_GBs": round(gbs, 1),
+                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+    res = {"value": value, "ms_per_step": elapsed / steps * 1e3, "roofline": roof,
+           "loop_pbi_per_s": spec.p * spec.q * spec.L * spec.iters * steps / (loop_ms * 1e-3)
+           if loop_ms else None,
+           "loop": loop, "stages": stages, "finite": finite,
+           "sweep_shape_stream_GBs": shape_gbs}
+    if monitor:
+        res["monitor"] = [dict(zip(nlpr.MON_FIELDS, map(float, r))) for r in plan.monitor()]
+    del ws, Z, Yl, Yh
+    plan.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -197,6 +197,29 @@ int nlpr_solve(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z, void
 int nlpr_solve_noalloc(nlpr_plan* plan, const float* Yl, const float* Yh, float* Z,
                        void* stream);
 
+/*
+ * Decode the coded dual state (NLPR_REGION_SIGMA with its NLPR_REGION_SIGMA_CODES) of bands
+ * [c0, c1) into dense FP32: out[c - c0][n][k][i1][i2] = Sigma'_{tau_n, k}(i1, i2) of band c,
+ * tau_n the n-th shift of nlpr_half_window, k as in NLPR_REGION_SIGMA, (i1, i2) image pixels.
+ *   sigma, codes : device, the two regions (of a workspace, or the Sigma' buffer of the SWEEP
+ *                  stage and the code region of its ws);
+ *   mu           : device, the thresholds [Npairs][p][q] the state was produced with
+ *                  (NLPR_REGION_MU);
+ *   out          : device, (c1 - c0) * Npairs * (2K+1)^2 * p * q floats.
+ * Asynchronous on `stream`; ordered after the plan's earlier calls like any call on the plan.
+ */
+int nlpr_sigma_expand(const nlpr_plan* plan, const float* sigma, const void* codes,
+                      const float* mu, int32_t c0, int32_t c1, float* out, void* stream);
+
+/*
+ * For plans created with NLPR_TIMING (else NLPR_ERR_NOT_ENABLED): the number of open items
+ * (float4s of NLPR_REGION_SIGMA stored) each sweep of the last solve wrote, one count per
+ * iteration.  counts : host, receives min(cap, n) values; n : receives iters (0 without a
+ * search window).  Waits for the last solve.  The next sweep reads what the previous one
+ * wrote, so these counts give the dual state's HBM bytes of every launch.
+ */
+int nlpr_sweep_counts(const nlpr_plan* plan, int64_t* counts, int32_t cap, int32_t* n);
+
 /* For plans created with NLPR_CHECK_FINITE (else NLPR_ERR_NOT_ENABLED): the iteration t
  * whose check (t = 8, 16, ... and the last; 0 for a solve of 0 iterations) first found NaN
  * or Inf in the iterate during the last solve, or -1 if none did.  iter : host, receives t. */
@@ -238,16 +261,27 @@ int nlpr_plan_get_info(const nlpr_plan* plan, nlpr_plan_info* info);
 typedef enum nlpr_region {
   NLPR_REGION_SIGMA = 0,  /* Sigma', the dual of eq. (dualvar3_main) for tau in W+ (order of
                              nlpr_half_window) and k in P (k1 major, then k2, each from -K to
-                             K), stored source-aligned: Sigma'_{tau k}(j) = Sigma_{tau k}(j + k).
-                             Layout [L][ntiles][Npairs][|P|][R][q] (nlpr_plan_get_info): image
-                             row i of band c lives in tile i / R at row i % R, so one sweep
-                             workgroup streams one contiguous block; rows past p in a ragged
-                             last tile are unused.                                            */
+                             K), stored source-aligned: Sigma'_{tau k}(j) = Sigma_{tau k}(j + k),
+                             in coded form (with NLPR_REGION_SIGMA_CODES; read it with
+                             nlpr_sigma_expand).  Its planes are laid out
+                             [L][ntiles][Npairs][|P|][R][q] (nlpr_plan_get_info): image row i
+                             of band c lives in tile i / R at row i % R, so one sweep workgroup
+                             streams one contiguous block.  Each plane is cut into items of 4
+                             consecutive floats and segments of 64 items (1 KB).  Every dual
+                             value is -clip(V, +-mu) (eqs. (Qj_main), (dualvar3_main)), so an
+                             element on the threshold is -mu (V > 0) or +mu (V < 0) and is not
+                             stored; for an item with any element off the threshold ("open")
+                             the 4 values -Sigma' = clip(V, +-mu) are stored, packed at the
+                             start of the item's segment in item order.                      */
   NLPR_REGION_MU = 1,     /* mu [Npairs][p][q] = lambda * omega_{i tau} / rho, the thresholds         */
   NLPR_REGION_C = 2,      /* C [L][p][q], right-hand side of eq. (x_linear_system_main)                */
   NLPR_REGION_LAMBDA1 = 3,/* Lambda1 [L][p][q]                                                       */
   NLPR_REGION_LAMBDA2 = 4,/* Lambda2 [L][p][q]                                                       */
-  NLPR_REGION_COUNT = 5
+  NLPR_REGION_SIGMA_CODES = 5, /* one byte per item of NLPR_REGION_SIGMA (byte index = float
+                             offset of the item / 4), bits (2e, 2e+1) for element e: bit 2e set
+                             if |V| >= mu (the element is on the threshold), bit 2e+1 set if
+                             V < 0 (its value is then +mu, else -mu)                          */
+  NLPR_REGION_COUNT = 6
 } nlpr_region;
 int nlpr_workspace_region(const nlpr_plan* plan, int region, size_t* offset, size_t* bytes);
 
@@ -265,7 +299,8 @@ int nlpr_workspace_region(const nlpr_plan* plan, int region, size_t* offset, siz
  *                          W1 = P1 + Lambda1 and W2 = P2 + Lambda2 with the new duals.
  *   NLPR_STAGE_SWEEP       {X, mu, Sigma', Creg, ws}  Q-update (eq. (Qj_main)) and Sigma-update
  *                          (eq. (dualvar3_main)) for every tau in W, k in P, in place on Sigma'
- *                          (sigma_elems floats, layout of NLPR_REGION_SIGMA);
+ *                          (sigma_elems floats, coded as NLPR_REGION_SIGMA, with its code bytes
+ *                          in the NLPR_REGION_SIGMA_CODES region of ws);
  *                          Creg = sum_{tau in W} sum_k D_{tau k}^T (Q_{tau k} + Sigma_{tau k}).
  *   NLPR_STAGE_SWEEP_FIRST same, with Sigma' taken as 0 on input (only written).
  *   NLPR_STAGE_ASSEMBLE    {W1, W2, Creg, C}          C = B^T W1 + W2 + Creg

@@ -265,6 +265,7 @@ int scene_create(const nlpr_params& prm, const float* blur_host, const float* R_
   };
   const size_t pl = plane * Lx * sizeof(float);
   take(B_SIGMA, sweep_sigma_bytes(P->sweep, q, Lx, P->npairs, P->npatch));
+  take(B_SCODE, P->npairs ? P->sz[B_SIGMA] / 16 : 0);     // one code byte per float4
   take(B_MU, (size_t)P->npairs * plane * sizeof(float));
   take(B_C, pl);
   take(B_L1, pl);
@@ -350,6 +351,7 @@ void batch_release(Batch& B) {
   hipFree(B.d_desc);
   if (B.h_desc) hipHostFree(B.h_desc);
   hipFree(B.d_flag);
+  hipFree(B.d_counts);
   if (B.upload_ev) hipEventDestroy(B.upload_ev);
   if (B.done_ev) hipEventDestroy(B.done_ev);
   if (B.graph) hipGraphExecDestroy(B.graph);
@@ -360,6 +362,7 @@ void batch_release(Batch& B) {
   B.d_desc = nullptr;
   B.h_desc = nullptr;
   B.d_flag = nullptr;
+  B.d_counts = nullptr;
   B.upload_ev = nullptr;
   B.done_ev = nullptr;
   B.graph = nullptr;
@@ -482,25 +485,30 @@ int batch_build(Batch& B) {
   }
   if ((rc = simple(KD_ROWS, rows_blocks, rows_lds, rows_block))) return rc;
   if ((rc = simple(KD_COLS, cols_blocks, cols_lds, cols_block))) return rc;
-  // the sweep: one launch per (patch radius, items per thread)
+  // the sweep: one launch per (patch radius, tile size, workgroup size)
   for (int K = 0; K <= kMaxK; ++K)
-    for (int items = 1; items <= 4; items *= 2) {
-      std::vector<int2> it;
-      size_t l = 0;
-      for (int s = 0; s < n; ++s) {
-        const Plan& P = *B.scenes[s];
-        if (P.npairs == 0 || P.prm.K != K || P.sweep.items != items) continue;
-        const int c = sweep_blocks(P);
-        for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
-        l = std::max(l, P.sweep.lds);
+    for (int items = 1; items <= 4; items *= 2)
+      for (int threads : {128, 256}) {
+        std::vector<int2> it;
+        size_t l = 0;
+        for (int s = 0; s < n; ++s) {
+          const Plan& P = *B.scenes[s];
+          if (P.npairs == 0 || P.prm.K != K || P.sweep.items != items ||
+              P.sweep.threads != threads)
+            continue;
+          const int c = sweep_blocks(P);
+          for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+          l = std::max(l, P.sweep.lds);
+        }
+        if (it.empty()) continue;
+        if ((rc = add_group(B, KD_SWEEP, it, threads, l, K, items))) return rc;
+        if ((rc = sweep_prepare(K, items, threads))) return rc;
       }
-      if (it.empty()) continue;
-      if ((rc = add_group(B, KD_SWEEP, it, 256, l, K, items))) return rc;
-      if ((rc = sweep_prepare(K, items))) return rc;
-    }
   NLPR_HIP_TRY(hipMalloc(&B.d_desc, n * sizeof(SceneDesc)));
   NLPR_HIP_TRY(hipHostMalloc(&B.h_desc, n * sizeof(SceneDesc)));
   NLPR_HIP_TRY(hipMalloc(&B.d_flag, 256));
+  if (B.timing)
+    NLPR_HIP_TRY(hipMalloc(&B.d_counts, std::max(B.iters, 1) * sizeof(unsigned long long)));
   NLPR_HIP_TRY(hipEventCreateWithFlags(&B.upload_ev, hipEventDisableTiming));
   NLPR_HIP_TRY(hipEventCreateWithFlags(&B.done_ev, hipEventDisableTiming));
   B.uploaded.resize(n);
@@ -578,6 +586,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
   const bool fused = (B.flags & NLPR_FUSED_S) != 0;
   const bool check = (B.flags & NLPR_CHECK_FINITE) != 0;
   if (check && (rc = launch_finite_clear(B.d_flag, s))) return rc;
+  if (B.d_counts && (rc = launch_zero_u64(B.d_counts, B.iters, s))) return rc;
   if (sub) {
     StageTimer tm(B, s, NLPR_STAGE_INIT);
     if ((rc = launch_project(B, B_YL, B_YLE, B_YLP, s))) return rc;
@@ -630,7 +639,9 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     if (reg) {
       const bool first = (t == 0 && !resume);
       StageTimer tm(B, s, first ? NLPR_STAGE_SWEEP_FIRST : NLPR_STAGE_SWEEP);
-      if ((rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, first, s))) return rc;
+      if ((rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, first, s, nullptr,
+                             B.d_counts ? B.d_counts + t : nullptr)))
+        return rc;
     }
     {
       StageTimer tm(B, s, NLPR_STAGE_ASSEMBLE);
@@ -648,7 +659,7 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
 // Descriptor of one scene for a solve: workspace regions, observations and output.
 SceneDesc solve_desc(const Plan& P, char* base, const float* Yl, const float* Yh, float* Z) {
   SceneDesc d = static_desc(P);
-  for (int k : {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO, B_CSPLIT})
+  for (int k : {B_SIGMA, B_SCODE, B_MU, B_C, B_L1, B_L2, B_BX, B_W1, B_W2, B_F, B_HALO, B_CSPLIT})
     d.buf[k] = base + P.off[k];
   d.buf[B_L1O] = d.buf[B_L1];
   d.buf[B_L2O] = d.buf[B_L2];
@@ -969,7 +980,7 @@ int batch_stage_time(Batch& B, int stage, double* ms_total, int64_t* launches, i
 }
 
 int region_of(const Plan& P, int region, size_t* offset, size_t* bytes) {
-  static const int slot_of[NLPR_REGION_COUNT] = {B_SIGMA, B_MU, B_C, B_L1, B_L2};
+  static const int slot_of[NLPR_REGION_COUNT] = {B_SIGMA, B_MU, B_C, B_L1, B_L2, B_SCODE};
   if (region < 0 || region >= NLPR_REGION_COUNT) return fail(NLPR_ERR_INVALID_ARG, "unknown workspace region");
   *offset = P.off[slot_of[region]];
   *bytes = P.sz[slot_of[region]];
@@ -1173,6 +1184,46 @@ int nlpr_solve_noalloc(nlpr_plan* plan, const float* Yl, const float* Yh, float*
                      static_cast<hipStream_t>(stream), true);
 }
 
+int nlpr_sigma_expand(const nlpr_plan* plan, const float* sigma, const void* codes,
+                      const float* mu, int32_t c0, int32_t c1, float* out, void* stream) {
+  if (!plan || !sigma || !codes || !mu || !out) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  const Batch& B = plan->B;
+  const Plan& P = *B.scenes[0];
+  if (c0 < 0 || c1 > P.Lx || c0 > c1) return fail(NLPR_ERR_INVALID_ARG, "bad band range");
+  if (P.npairs == 0) return NLPR_OK;
+  int rc;
+  for (const void* ptr : {(const void*)sigma, codes, (const void*)mu, (const void*)out})
+    if ((rc = check_device_ptr(ptr, "sigma expand buffer"))) return rc;
+  DeviceGuard dg(B.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the kernel reads sizes only (descriptor 0): wait for the plan's previous work as any call
+  NLPR_HIP_TRY(hipStreamWaitEvent(s, B.done_ev, 0));
+  if (!B.desc_valid) {
+    std::vector<SceneDesc> descs{static_desc(P)};
+    if ((rc = upload_desc(const_cast<Batch&>(B), descs, s))) return rc;
+  }
+  if ((rc = launch_sigma_expand(B, sigma, static_cast<const uint8_t*>(codes), mu, c0, c1 - c0,
+                                out, s)))
+    return rc;
+  NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));   // later calls on the plan wait for the reads
+  return NLPR_OK;
+}
+
+int nlpr_sweep_counts(const nlpr_plan* plan, int64_t* counts, int32_t cap, int32_t* n) {
+  if (!plan || !n) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
+  const Batch& B = plan->B;
+  if (!B.timing) return fail(NLPR_ERR_NOT_ENABLED, "created without NLPR_TIMING");
+  *n = B.scenes[0]->npairs ? B.iters : 0;
+  if (!counts || cap <= 0 || *n == 0) return NLPR_OK;
+  DeviceGuard dg(B.device);
+  NLPR_HIP_TRY(hipEventSynchronize(B.done_ev));
+  std::vector<unsigned long long> h(B.iters);
+  NLPR_HIP_TRY(hipMemcpy(h.data(), B.d_counts, B.iters * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost));
+  for (int i = 0; i < std::min(cap, *n); ++i) counts[i] = (int64_t)h[i];
+  return NLPR_OK;
+}
+
 int nlpr_nonfinite_iteration(const nlpr_plan* plan, int32_t* iter) {
   if (!plan || !iter) return fail(NLPR_ERR_INVALID_ARG, "NULL argument");
   if (!(plan->B.flags & NLPR_CHECK_FINITE))
@@ -1265,6 +1316,7 @@ int nlpr_debug_stage(nlpr_plan* plan, int stage, void* const* bufs, int32_t nbuf
       // Creg = the sweep's own-tile part (scratch TMP) + the folded halo rows, assembled by
       // the B^T kernel over a zero image
       put(B_Z, 0); put(B_MU, 1); put(B_SIGMA, 2); put(B_C, 3);
+      scratch(B_SCODE, 4, B_SCODE);
       scratch(B_HALO, 4, B_HALO);
       scratch(B_CSPLIT, 4, B_CSPLIT);
       scratch(B_W1, 4, B_W1);

@@ -470,6 +470,11 @@ finite_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, 
 
 __global__ void clear_flag_kernel(int* flag) { flag[0] = INT_MAX; }
 
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
 // ------------------------------------------------------------------------------- conv
 // out(i) = sum_m b(m) in(i - m)      (B, circular convolution)        TR = false
 // out(i) = sum_m b(m) in(i + m)      (B^T, circular correlation)      TR = true
@@ -1014,6 +1019,13 @@ int launch_stream_chunks(float* buf, size_t chunk4, int nchunks, int bands, int 
 
 int launch_fill(const Batch& B, int slot_, hipStream_t s) {
   return launch_groups(B, KD_PLANE, "fill_kernel", fill_kernel, s, slot_);
+}
+
+int launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  if (n <= 0) return NLPR_OK;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  NLPR_LAUNCH_CHECK("zero_u64_kernel");
+  return NLPR_OK;
 }
 
 int launch_finite_clear(int* flag, hipStream_t s) {

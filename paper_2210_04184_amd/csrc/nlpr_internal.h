@@ -46,6 +46,7 @@ enum Slot {
   B_YLP,     // Y_l E^+, [Ls][p/d][q/d]
   B_L1O, B_L2O,   // where the P-update writes Lambda1, Lambda2 when not in place (checkpoints)
   B_CSPLIT,  // regulariser planes of sweep parts 1 .. psplit-1, [psplit-1][L][p][q]
+  B_SCODE,   // Sigma' codes: one byte per float4 item of Sigma' (sweep.hip)
   // reverse mode (single scene): adjoints of the iteration's variables and the outputs
   B_GZ,      // Z' (input)
   B_GC,      // C'
@@ -100,8 +101,8 @@ struct SceneDesc {
 
 struct SweepShape {
   int rows;      // tile height R
-  int items;     // float4 items per thread
-  int threads;   // workgroup size
+  int items;     // tile size in units of 256 float4 items (1024 pixels): 1, 2 or 4
+  int threads;   // workgroup size: 256 (items per thread = items) or 128 (2 per thread)
   int ntiles;    // ceil(p / R)
   int halo;      // rows above the tile reached by the adjoint scatter (max tau1)
   int split;     // workgroups per (tile, band), each over a contiguous part of W+
@@ -180,6 +181,7 @@ struct Batch {
   bool desc_valid = false;
   hipEvent_t upload_ev = nullptr;
   std::vector<Group> groups[KD_COUNT];
+  unsigned long long* d_counts = nullptr;  // open Sigma' items written per sweep (timing)
   int* d_flag = nullptr;           // finite check: first checked iteration with NaN / Inf
   int nonfinite_iter = -1;         // what the last checked solve found (-1: nothing)
   // graph
@@ -342,11 +344,18 @@ int launch_fill(const Batch& B, int slot, hipStream_t s);   // zero a [L][p][q] 
 int launch_upsample_zero(const Batch& B, int yl, int t, hipStream_t s);   // S^T Y_l / rho
 // X = solve(C) (+ add, a [L][p][q] slot, when add >= 0); the fused-S system for fused scenes
 int launch_xsolve(const Batch& B, int c, int x, int f, int add, hipStream_t s);
-// Sigma' is updated in place.  codes (differentiated form, one item per thread): also
-// write each dual element's 2-bit threshold branch there, one byte per float4 of Sigma'
+// Sigma' (coded: values in slot `sigma`, code bytes in slot B_SCODE) is updated in place.
+// codes (differentiated form, one item per thread): also write each dual element's 2-bit
+// threshold branch there, one byte per float4 of Sigma'.  count: if not null, add the
+// number of open items written (float4s stored) to *count.
 int launch_sweep(const Batch& B, int x, int mu, int sigma, int creg, int halo, bool first,
-                 hipStream_t s, uint8_t* codes = nullptr);
-int sweep_prepare(int K, int items);   // kernel attributes; call before launches or capture
+                 hipStream_t s, uint8_t* codes = nullptr, unsigned long long* count = nullptr);
+// Dense Sigma' of bands [c0, c0 + nb) of scene 0: [nb][Npairs][|P|][p][q]
+int launch_sigma_expand(const Batch& B, const float* sig, const uint8_t* codes, const float* mu,
+                        int c0, int nb, float* out, hipStream_t s);
+// zero n 64-bit counters
+int launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+int sweep_prepare(int K, int items, int threads);   // kernel attributes; before launches or capture
 
 // ---- shapes and tuning
 SweepShape choose_sweep_shape(int p, int q, int K, int halo);

@@ -62,14 +62,30 @@ __device__ __forceinline__ void st_nt(gfloat* p, float4 v) {
 __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v, -m), m); }
 
 // ---- sweep kernel begin (the traffic record of the benchmark is keyed to this text)
+// Storage of Sigma' (coded).  Every new dual value is -clip(V, +-mu), so an element that
+// reached the threshold (|V| >= mu) holds exactly -mu (V > 0) or +mu (V < 0): its value
+// follows from the threshold, which the sweep has at hand, and one sign bit.  Per float4
+// item of a plane the state keeps a code byte, bits (2e, 2e+1) for element e:
+//   bit 2e   on: |V| >= mu (false for a NaN), the value is -mu or +mu;
+//   bit 2e+1 the sign of V (V < 0: the value is +mu).
+// An item with any element off the threshold is "open": its four values are stored as a
+// float4, as clip(V, +-mu) = -Sigma' (so the next sweep adds them: V = g - Sigma').  Open items are packed per wave: the 64 items a wave owns in a plane (one 1 KB
+// segment of the plane) keep the float4s of their open items at the start of that segment,
+// in lane order, so a wave reads and writes only as many 16-byte slots as it has open
+// items (mbcnt of the ballot gives each open lane its slot).  A wave reads its whole old
+// run before it writes the new one, and each segment belongs to one wave, so the update is
+// in place.  Decoding is exact: the stored values are the values, and -mu, +mu are the
+// thresholds that produced the on-threshold ones.
 // CODES (differentiated form): also record, per dual element, which branch of the
 // threshold it took, which is all the sweep's adjoint needs of this iteration: 2 bits, 0 for
 // |V| < mu, 1 for V >= mu, 2 for V <= -mu, 3 for V = 0 with mu = 0 (or V not a number).  The
 // four elements of a float4 item share one byte, at the item's float offset / 4.
+// COUNT: add the number of open items written by each wave to *count.
 template <int K, int ITEMS, int NT, bool FIRST, bool CODES>
 __global__ void __launch_bounds__(NT)
 sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s, int mu_s,
-             int sig_s, int creg_s, int halo_s, uint8_t* codes) {
+             int sig_s, int code_s, int creg_s, int halo_s, uint8_t* codes,
+             unsigned long long* count) {
   const int2 it_ = items[blockIdx.x];
   const SceneDesc& S = sd[it_.x];
   const int p = S.p, q = S.q, L = S.L, npairs = S.npairs, R = S.rows, ntiles = S.ntiles,
@@ -77,6 +93,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const gfloat* __restrict__ X = gslot<const gfloat>(S, x_s);
   const gfloat* __restrict__ mu = gslot<const gfloat>(S, mu_s);
   gfloat* sig = gslot<gfloat>(S, sig_s);   // updated in place
+  gu8* scode = gslot<gu8>(S, code_s);      // updated in place
   constexpr int KW = 2 * K + 1;
   constexpr int NP = KW * KW;
   extern __shared__ float4 lds4[];
@@ -110,7 +127,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   }
   __syncthreads();
 
-  int row[ITEMS], col[ITEMS];
+  int row[ITEMS], col[ITEMS], seg[ITEMS];
   bool ok[ITEMS];
   float4 xv[ITEMS], cp[ITEMS];
 #pragma unroll
@@ -118,17 +135,31 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
     const int it = threadIdx.x + NT * m;
     row[m] = it / q4;
     col[m] = (it - row[m] * q4) * 4;
+    seg[m] = 4 * (it & ~63);            // float offset of the wave's segment in a plane
     ok[m] = row[m] < rows;
     xv[m] = ok[m] ? *reinterpret_cast<const float4*>(Xs + (row[m] + H) * q + col[m])
                   : make_float4(0.f, 0.f, 0.f, 0.f);
     cp[m] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
+  unsigned open_written = 0;            // open items this wave wrote (wave-uniform)
 
   // Sigma' as [L][tiles][Npairs][|P|][R][q]: the whole state of one workgroup is one
   // contiguous stream, each (tau, k) slab of it R*q floats.
   const size_t kstride = (size_t)R * q;             // between patch offsets
   const size_t tstride = (size_t)NP * kstride;      // between shifts
   const size_t tile_off = ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
+  // code bytes of the next patch row to process, requested one row ahead
+  unsigned cbn[KW][ITEMS];
+  auto load_codes = [&](size_t row_off) {
+#pragma unroll
+    for (int k2 = 0; k2 < KW; ++k2) {
+      const gu8* cbp = scode + ((row_off + (size_t)k2 * kstride) >> 2);
+#pragma unroll
+      for (int m = 0; m < ITEMS; ++m)
+        cbn[k2][m] = __builtin_nontemporal_load(cbp + (threadIdx.x + NT * m));
+    }
+  };
+  if (!FIRST && n_begin < n_end) load_codes(tile_off + (size_t)n_begin * tstride);
 
   for (int n = n_begin; n < n_end; ++n) {
     const int2 t = tau_at(S, n);
@@ -176,47 +207,92 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
         mw[m][4] = b.x; mw[m][5] = b.y; mw[m][6] = b.z; mw[m][7] = b.w;
         mw[m][8] = d.x; mw[m][9] = d.y; mw[m][10] = d.z; mw[m][11] = d.w;
       }
+      const size_t row_off = n_off + (size_t)((k1 + K) * KW) * kstride;
+      // the old state of this patch row's planes: the code bytes (loaded with the previous
+      // row), then the open items' float4s from the waves' packed runs.  The next row's code
+      // bytes (or the next shift's first row) are requested before this row's values.
+      unsigned cb[KW][ITEMS];
       float4 s[KW][ITEMS];
       if (!FIRST) {
 #pragma unroll
-        for (int k2 = 0; k2 < KW; ++k2) {
-          const gfloat* base = sig + n_off + (size_t)((k1 + K) * KW + k2) * kstride;
+        for (int k2 = 0; k2 < KW; ++k2)
 #pragma unroll
-          for (int m = 0; m < ITEMS; ++m)
-            s[k2][m] = ok[m] ? ld_nt(base + (size_t)row[m] * q + col[m])
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
+          for (int m = 0; m < ITEMS; ++m) cb[k2][m] = cbn[k2][m];
+        if (k1 < K)
+          load_codes(row_off + (size_t)KW * kstride);
+        else if (n + 1 < n_end)
+          load_codes(n_off + tstride);
+#pragma unroll
+        for (int k2 = 0; k2 < KW; ++k2) {
+          const gfloat* vb = sig + row_off + (size_t)k2 * kstride;
+#pragma unroll
+          for (int m = 0; m < ITEMS; ++m) {
+            const bool open = ok[m] && (cb[k2][m] & 0x55u) != 0x55u;
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(open);
+            const unsigned slot = __builtin_amdgcn_mbcnt_hi(
+                (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            // a wave with open items loads on every lane (lanes past the tile from the start
+            // of the segment): the closed lanes' slots lie inside the open run, so no extra
+            // line is read and no lane branches
+            if (bal) s[k2][m] = ld_nt(vb + (seg[m] + 4u * (ok[m] ? slot : 0u)));
+          }
         }
       }
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
-        const size_t pl_off = n_off + (size_t)((k1 + K) * KW + k2) * kstride;
-        gfloat* base = sig + pl_off;
+        const size_t pl_off = row_off + (size_t)k2 * kstride;
+        gfloat* vb = sig + pl_off;
+        gu8* cbp = scode + (pl_off >> 2);
 #pragma unroll
         for (int m = 0; m < ITEMS; ++m) {
-          if (!ok[m]) continue;
-          const float4 sv = FIRST ? make_float4(0.f, 0.f, 0.f, 0.f) : s[k2][m];
           const int o = 4 + (k2 - K);  // window index of column col + (k2 - K)
-          float4 v, cl;
-          v.x = g[m].x - sv.x; cl.x = clampf(v.x, mw[m][o + 0]);
-          v.y = g[m].y - sv.y; cl.y = clampf(v.y, mw[m][o + 1]);
-          v.z = g[m].z - sv.z; cl.z = clampf(v.z, mw[m][o + 2]);
-          v.w = g[m].w - sv.w; cl.w = clampf(v.w, mw[m][o + 3]);
-          A[m].x += v.x - 2.f * cl.x;
-          A[m].y += v.y - 2.f * cl.y;
-          A[m].z += v.z - 2.f * cl.z;
-          A[m].w += v.w - 2.f * cl.w;
-          st_nt(base + (size_t)row[m] * q + col[m], make_float4(-cl.x, -cl.y, -cl.z, -cl.w));
-          if (CODES) {
-            const float va[4] = {v.x, v.y, v.z, v.w};
-            unsigned byte = 0;
+          const float mu4[4] = {mw[m][o + 0], mw[m][o + 1], mw[m][o + 2], mw[m][o + 3]};
+          float sv[4];
+          if (FIRST) {
+            sv[0] = sv[1] = sv[2] = sv[3] = 0.f;
+          } else {
+            // sv = -Sigma' = clip(V_old, +-mu): the stored value, or on the threshold mu with
+            // the sign of V_old (bit 2e+1), i.e. mu's magnitude under that sign bit
+            const bool open = ok[m] && (cb[k2][m] & 0x55u) != 0x55u;
+            const float st[4] = {s[k2][m].x, s[k2][m].y, s[k2][m].z, s[k2][m].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const unsigned code = fabsf(va[e]) < mw[m][o + e] ? 0u
-                                    : (va[e] > 0.f ? 1u : (va[e] < 0.f ? 2u : 3u));
-              byte |= code << (2 * e);
+              const float on = __uint_as_float(__builtin_amdgcn_ubfe(cb[k2][m], 2 * e + 1, 1) << 31 |
+                                               __float_as_uint(mu4[e]));
+              sv[e] = open ? st[e] : on;
             }
-            ((gu8*)codes)[(pl_off + (size_t)row[m] * q + col[m]) >> 2] =
-                (uint8_t)byte;
+          }
+          const float gv[4] = {g[m].x, g[m].y, g[m].z, g[m].w};
+          float nv[4], acc[4];
+          unsigned code = 0, branch = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float v = gv[e] + sv[e];
+            const float cl = __builtin_amdgcn_fmed3f(v, -mu4[e], mu4[e]);
+            acc[e] = __builtin_fmaf(-2.f, cl, v);
+            nv[e] = cl;
+            code |= (fabsf(v) >= mu4[e] ? 1u : 0u) << (2 * e);
+            code |= (__float_as_uint(v) >> 31) << (2 * e + 1);
+            if (CODES) {
+              const unsigned bc = fabsf(v) < mu4[e] ? 0u : (v > 0.f ? 1u : (v < 0.f ? 2u : 3u));
+              branch |= bc << (2 * e);
+            }
+          }
+          if (ok[m]) {
+            A[m].x += acc[0];
+            A[m].y += acc[1];
+            A[m].z += acc[2];
+            A[m].w += acc[3];
+          }
+          const bool opn = ok[m] && (code & 0x55u) != 0x55u;
+          const unsigned long long bal = __builtin_amdgcn_ballot_w64(opn);
+          const unsigned slot = __builtin_amdgcn_mbcnt_hi(
+              (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+          open_written += (unsigned)__builtin_popcountll(bal);
+          if (opn) st_nt(vb + (seg[m] + 4u * slot), make_float4(nv[0], nv[1], nv[2], nv[3]));
+          if (ok[m]) {
+            __builtin_nontemporal_store((uint8_t)code, cbp + (threadIdx.x + NT * m));
+            if (CODES) ((gu8*)codes)[(pl_off >> 2) + threadIdx.x + NT * m] = (uint8_t)branch;
           }
         }
       }
@@ -236,6 +312,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       }
     }
   }
+  if (count && (threadIdx.x & 63) == 0) atomicAdd(count, (unsigned long long)open_written);
   __syncthreads();
 
   gfloat* cregc = creg + (size_t)c * plane + (size_t)r0 * q;
@@ -258,38 +335,36 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
 
 // ---- sweep kernel end
 
-#ifndef NLPR_SWEEP_THREADS
-#define NLPR_SWEEP_THREADS 256
-#endif
-#ifndef NLPR_SWEEP_MIN_ITEMS
-#define NLPR_SWEEP_MIN_ITEMS 1
-#endif
-// Workgroup size and the smallest number of float4 items per thread.  One item per thread
-// (tiles of 2 rows at q = 512, 90 VGPRs, three workgroups per CU) streamed Sigma' fastest
-// among 1, 2 and 4 items and 256 / 512 / 1024 threads; wider images take 2 or 4 items so
-// that one workgroup covers at least one full row.
-constexpr int kThreads = NLPR_SWEEP_THREADS;
-constexpr int kMinItems = NLPR_SWEEP_MIN_ITEMS;
+// Tiles and launch shapes.  A tile is 1024 * items pixels (items = 1, 2 or 4: the fewest with
+// one full image row per tile), i.e. 256 * items float4 items, whatever the workgroup shape:
+// the layout of Sigma' and of its codes depends on the tile only (segments of 64 items).  A
+// tile runs on 256 threads with `items` items each, or, for patches of at most 3 x 3 with
+// single-item tiles, on 128 threads with 2 items each: a 3 x 3 patch leaves each workgroup
+// only 9 planes per shift, and two independent items per thread keep its dependent chains of
+// loads, ballots and stores overlapped (256 x 256 x 31: 134 -> 108 us per launch; for 5 x 5
+// the second item's registers cost occupancy, 32 -> 38 ms at 512 x 512 x 128).
+constexpr int kThreads = 256;
 
-template <int K, int ITEMS, bool FIRST, bool CODES>
+template <int K, int ITEMS, int NT, bool FIRST, bool CODES>
 int launch_k(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
-             uint8_t* codes, hipStream_t s) {
-  auto kern = sweep_kernel<K, ITEMS, kThreads, FIRST, CODES>;
-  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(kThreads), g.lds, s, B.d_desc, g.d_items, x, mu,
-                     sig, creg, halo, codes);
+             uint8_t* codes, unsigned long long* count, hipStream_t s) {
+  auto kern = sweep_kernel<K, ITEMS, NT, FIRST, CODES>;
+  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(NT), g.lds, s, B.d_desc, g.d_items, x, mu,
+                     sig, (int)B_SCODE, creg, halo, codes, count);
   NLPR_LAUNCH_CHECK("sweep_kernel");
   return NLPR_OK;
 }
 
 // Allow the sweep's dynamic LDS beyond the default limit (done when a batch is built, not
-// during graph capture).  The branch-recording variant exists for one item per thread only.
-template <int K, int ITEMS>
+// during graph capture).  The branch-recording variant exists for single-item tiles.
+template <int K, int ITEMS, int NT>
 int set_lds_limit() {
+  const bool single = ITEMS * NT == 256;
   const void* kern[4] = {
-      reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, true, false>),
-      reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, kThreads, false, false>),
-      ITEMS == 1 ? reinterpret_cast<const void*>(sweep_kernel<K, 1, kThreads, true, true>) : nullptr,
-      ITEMS == 1 ? reinterpret_cast<const void*>(sweep_kernel<K, 1, kThreads, false, true>) : nullptr};
+      reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, NT, true, false>),
+      reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, NT, false, false>),
+      single ? reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, NT, true, true>) : nullptr,
+      single ? reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, NT, false, true>) : nullptr};
   for (const void* k : kern)
     if (k) NLPR_HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                             (int)kMaxSweepLds));
@@ -297,32 +372,40 @@ int set_lds_limit() {
 }
 
 template <int K>
-int set_lds_limit_items(int items) {
+int set_lds_limit_items(int items, int threads) {
+  if constexpr (K <= 1) {
+    if (threads == 128) return set_lds_limit<K, 2, 128>();
+  }
   switch (items) {
-    case 1: return set_lds_limit<K, (kMinItems > 1 ? kMinItems : 1)>();
-    case 2: return set_lds_limit<K, (kMinItems > 2 ? kMinItems : 2)>();
-    default: return set_lds_limit<K, 4>();
+    case 1: return set_lds_limit<K, 1, 256>();
+    case 2: return set_lds_limit<K, 2, 256>();
+    default: return set_lds_limit<K, 4, 256>();
   }
 }
 
+// g.key1 = tile items, g.block = threads
 template <int K, bool FIRST>
 int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
-                 uint8_t* codes, hipStream_t s) {
-  if (codes) {
-    if (g.key1 != 1 || kMinItems != 1) {
-      set_error("sweep: branch codes need one item per thread");
-      return NLPR_ERR_UNSUPPORTED_SHAPE;
-    }
-    return launch_k<K, 1, FIRST, true>(B, g, x, mu, sig, creg, halo, codes, s);
+                 uint8_t* codes, unsigned long long* count, hipStream_t s) {
+  if (codes && g.key1 != 1) {
+    set_error("sweep: branch codes need single-item tiles");
+    return NLPR_ERR_UNSUPPORTED_SHAPE;
   }
+  if constexpr (K <= 1) {
+    if (g.block == 128)
+      return codes ? launch_k<K, 2, 128, FIRST, true>(B, g, x, mu, sig, creg, halo, codes, count,
+                                                      s)
+                   : launch_k<K, 2, 128, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr,
+                                                       count, s);
+  }
+  if (codes) return launch_k<K, 1, 256, FIRST, true>(B, g, x, mu, sig, creg, halo, codes, count, s);
   switch (g.key1) {
     case 1:
-      return launch_k<K, (kMinItems > 1 ? kMinItems : 1), FIRST, false>(B, g, x, mu, sig, creg,
-                                                                         halo, nullptr, s);
+      return launch_k<K, 1, 256, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
     case 2:
-      return launch_k<K, (kMinItems > 2 ? kMinItems : 2), FIRST, false>(B, g, x, mu, sig, creg,
-                                                                         halo, nullptr, s);
-    default: return launch_k<K, 4, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, s);
+      return launch_k<K, 2, 256, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
+    default:
+      return launch_k<K, 4, 256, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
   }
 }
 
@@ -330,10 +413,10 @@ int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int cre
 
 SweepShape choose_sweep_shape(int p, int q, int K, int halo) {
   SweepShape sh{};
-  sh.threads = kThreads;
-  int items = kMinItems;
+  int items = 1;
   while (items < 4 && kThreads * items * 4 < q) items *= 2;
   sh.items = items;
+  sh.threads = (items == 1 && K <= 1) ? 128 : kThreads;
   const int per_block = kThreads * items * 4;  // pixels per workgroup
   sh.rows = std::max(1, std::min(p, per_block / q));
   sh.ntiles = ceil_div(p, sh.rows);
@@ -356,27 +439,27 @@ int choose_pair_split(int blocks, int npairs) {
 
 int sweep_blocks(const Plan& P) { return P.sweep.ntiles * P.Lx * P.sweep.split; }
 
-int sweep_prepare(int K, int items) {
+int sweep_prepare(int K, int items, int threads) {
   switch (K) {
-    case 0: return set_lds_limit_items<0>(items);
-    case 1: return set_lds_limit_items<1>(items);
-    case 2: return set_lds_limit_items<2>(items);
-    case 3: return set_lds_limit_items<3>(items);
-    case 4: return set_lds_limit_items<4>(items);
+    case 0: return set_lds_limit_items<0>(items, threads);
+    case 1: return set_lds_limit_items<1>(items, threads);
+    case 2: return set_lds_limit_items<2>(items, threads);
+    case 3: return set_lds_limit_items<3>(items, threads);
+    case 4: return set_lds_limit_items<4>(items, threads);
     default: set_error("sweep: unsupported patch radius"); return NLPR_ERR_UNSUPPORTED_SHAPE;
   }
 }
 
 int launch_sweep(const Batch& B, int x, int mu, int sig, int creg, int halo, bool first,
-                 hipStream_t s, uint8_t* codes) {
+                 hipStream_t s, uint8_t* codes, unsigned long long* count) {
   for (const Group& g : B.groups[KD_SWEEP]) {
     if (!g.nitems) continue;
     int rc;
     switch (g.key0) {
 #define NLPR_SW(KK)                                                                            \
   case KK:                                                                                     \
-    rc = first ? launch_items<KK, true>(B, g, x, mu, sig, creg, halo, codes, s)               \
-               : launch_items<KK, false>(B, g, x, mu, sig, creg, halo, codes, s);             \
+    rc = first ? launch_items<KK, true>(B, g, x, mu, sig, creg, halo, codes, count, s)        \
+               : launch_items<KK, false>(B, g, x, mu, sig, creg, halo, codes, count, s);      \
     break;
       NLPR_SW(0)
       NLPR_SW(1)
@@ -390,6 +473,78 @@ int launch_sweep(const Batch& B, int x, int mu, int sig, int creg, int halo, boo
     }
     if (rc) return rc;
   }
+  return NLPR_OK;
+}
+
+// ------------------------------------------------------------------ decoding Sigma'
+namespace {
+// Dense Sigma' of bands [c0, c0 + nb) from the coded state: out[c - c0][n][k][i1][i2] =
+// Sigma'_{tau_n, k}(i1, i2) of band c (image rows, not tiles).  One thread per float4 item of a
+// plane, in the sweep's order (ITEMS * NT items per plane, 64 per wave), so every wave sees
+// the packed run of the segment the sweep's wave wrote.
+__global__ void __launch_bounds__(256)
+sigma_expand_kernel(const SceneDesc* __restrict__ sd, const gfloat* __restrict__ sig,
+                    const gu8* __restrict__ scode, const gfloat* __restrict__ mu, int c0, int nb,
+                    int per_plane, gfloat* __restrict__ out) {
+  const SceneDesc& S = sd[0];
+  const int p = S.p, q = S.q, K = S.K, npairs = S.npairs, npatch = S.npatch, R = S.rows,
+            ntiles = S.ntiles, q4 = q >> 2, KW = 2 * K + 1;
+  const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t planes = (size_t)nb * ntiles * npairs * npatch;
+  const bool live = g < planes * per_plane;        // whole waves are live or not
+  const size_t pi = live ? g / per_plane : 0;
+  const int it = (int)(g - pi * per_plane);
+  // plane index pi = ((cl * ntiles + tile) * npairs + n) * npatch + k
+  const int k = (int)(pi % npatch);
+  const size_t r1 = pi / npatch;
+  const int n = (int)(r1 % npairs);
+  const size_t r2 = r1 / npairs;
+  const int tile = (int)(r2 % ntiles);
+  const int cl = (int)(r2 / ntiles);
+  const int r0 = tile * R, rows = min(R, p - r0);
+  const int row = it / q4, col = (it - row * q4) * 4;
+  const bool ok = live && row < rows;
+  const size_t pl_off = (((size_t)(c0 + cl) * ntiles + tile) * npairs + n) * npatch * ((size_t)R * q) +
+                        (size_t)k * R * q;
+  const unsigned cb = ok ? scode[(pl_off >> 2) + it] : 0x55u;
+  const bool open = ok && (cb & 0x55u) != 0x55u;
+  const unsigned long long bal = __builtin_amdgcn_ballot_w64(open);
+  const unsigned slot = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+  if (!ok) return;
+  float v[4];
+  if (open) {
+    const float4 t = ldg4(sig + pl_off + 4 * (it & ~63) + 4 * slot);   // clip(V) = -Sigma'
+    v[0] = -t.x; v[1] = -t.y; v[2] = -t.z; v[3] = -t.w;
+  } else {
+    const int k1 = k / KW - K, k2 = k % KW - K;
+    const int mr = (r0 + row + k1 + p) % p;
+    const gfloat* mun = mu + (size_t)n * p * q + (size_t)mr * q;
+    for (int e = 0; e < 4; ++e) {
+      const float m = mun[(col + e + k2 + q) % q];
+      v[e] = (cb >> (2 * e + 1)) & 1u ? m : -m;
+    }
+  }
+  const size_t o = ((((size_t)cl * npairs + n) * npatch + k) * p + (r0 + row)) * q + col;
+  stg4(out + o, make_float4(v[0], v[1], v[2], v[3]));
+}
+}  // namespace
+
+int launch_sigma_expand(const Batch& B, const float* sig, const uint8_t* codes, const float* mu,
+                        int c0, int nb, float* out, hipStream_t s) {
+  const Plan& P = *B.scenes[0];
+  const int per_plane = kThreads * P.sweep.items;
+  const size_t total = (size_t)nb * P.sweep.ntiles * P.npairs * P.npatch * per_plane;
+  if (total == 0) return NLPR_OK;
+  const size_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffffu) {
+    set_error("sigma expand: too many bands at once");
+    return NLPR_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(sigma_expand_kernel, dim3((unsigned)blocks), dim3(256), 0, s, B.d_desc,
+                     (const gfloat*)sig, (const gu8*)codes, (const gfloat*)mu, c0, nb, per_plane,
+                     (gfloat*)out);
+  NLPR_LAUNCH_CHECK("sigma_expand_kernel");
   return NLPR_OK;
 }
 

@@ -57,6 +57,7 @@ REGION_MU = 1
 REGION_C = 2
 REGION_LAMBDA1 = 3
 REGION_LAMBDA2 = 4
+REGION_SIGMA_CODES = 5
 
 EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlpr_plan_destroy",
                    "nlpr_status_string", "nlpr_last_error", "nlpr_half_window",
@@ -65,7 +66,8 @@ EXPORTED = sorted(["nlpr_plan_create", "nlpr_workspace_size", "nlpr_solve", "nlp
                    "nlpr_batch_region", "nlpr_batch_solve", "nlpr_batch_stage_time",
                    "nlpr_batch_destroy", "nlpr_monitor", "nlpr_batch_monitor",
                    "nlpr_grad_sizes", "nlpr_forward", "nlpr_backward", "nlpr_stream_rmw",
-                   "nlpr_stream_chunks", "nlpr_solve_noalloc", "nlpr_nonfinite_iteration"])
+                   "nlpr_stream_chunks", "nlpr_solve_noalloc", "nlpr_nonfinite_iteration",
+                   "nlpr_sigma_expand", "nlpr_sweep_counts"])
 
 # size of the library's static workspace used by nlpr_solve_noalloc (include/nlpr.h)
 NOALLOC_WORKSPACE_BYTES = 64 << 20
@@ -111,6 +113,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.nlpr_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.nlpr_solve_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.nlpr_nonfinite_iteration.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.nlpr_sigma_expand.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
+    lib.nlpr_sweep_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32, ctypes.POINTER(i32)]
     lib.nlpr_plan_destroy.argtypes = [vp]
     lib.nlpr_status_string.argtypes = [ctypes.c_int]
     lib.nlpr_status_string.restype = ctypes.c_char_p
@@ -256,18 +260,44 @@ class Plan:
         return inf
 
     def alloc_sigma(self, fill: float = float("nan")):
-        """A standalone Sigma' buffer (layout of the workspace region) for the sweep stage."""
+        """A standalone Sigma' buffer (the values of the coded layout of the workspace region)
+        for the sweep stage; its code bytes live in the stage's workspace."""
         import torch
         return torch.full((self.info().sigma_elems,), fill, dtype=torch.float32, device="cuda")
 
-    def sigma_logical(self, sig):
-        """Sigma' (tile-major, as stored) rearranged to [Npairs][|P|][L][p][q]."""
+    def sigma_expand(self, sig, codes, mu, c0: int = 0, c1: Optional[int] = None, stream=None):
+        """Dense Sigma' of bands [c0, c1) from its coded form: [Npairs][|P|][c1 - c0][p][q].
+        sig, codes, mu: float32, uint8 and float32 device tensors (values, code bytes and
+        thresholds)."""
+        import torch
         inf = self.info()
         _, p, q = self.shape
-        L = self.xbands
-        t = sig.view(L, inf.ntiles, inf.npairs, inf.npatch, inf.tile_rows, q)
-        t = t.permute(2, 3, 0, 1, 4, 5).reshape(inf.npairs, inf.npatch, L, inf.ntiles * inf.tile_rows, q)
-        return t[:, :, :, :p, :]
+        c1 = self.xbands if c1 is None else c1
+        out = torch.empty((c1 - c0, inf.npairs, inf.npatch, p, q), dtype=torch.float32,
+                          device="cuda")
+        _check(load().nlpr_sigma_expand(self.handle, _ptr(sig), _ptr(codes), _ptr(mu), c0, c1,
+                                        _ptr(out), _stream_handle(stream)))
+        return out.permute(1, 2, 0, 3, 4)
+
+    def state_sigma(self, ws, c0: int = 0, c1: Optional[int] = None, stream=None):
+        """Dense Sigma' [Npairs][|P|][c1 - c0][p][q] of the state a solve left in ws."""
+        return self.sigma_expand(self.region_view(ws, REGION_SIGMA),
+                                 self.region_bytes(ws, REGION_SIGMA_CODES),
+                                 self.region_view(ws, REGION_MU), c0, c1, stream)
+
+    def region_bytes(self, ws, which: int):
+        """A uint8 view of one workspace region (ws is a uint8 device tensor)."""
+        off, nb = self.region(which)
+        return ws[off:off + nb]
+
+    def sweep_counts(self):
+        """Open Sigma' items (float4s stored) written by each sweep of the last solve
+        (plans created with TIMING)."""
+        n = ctypes.c_int32()
+        _check(load().nlpr_sweep_counts(self.handle, None, 0, ctypes.byref(n)))
+        out = (ctypes.c_int64 * max(n.value, 1))()
+        _check(load().nlpr_sweep_counts(self.handle, out, n.value, ctypes.byref(n)))
+        return [out[i] for i in range(n.value)]
 
     def region(self, which: int) -> Tuple[int, int]:
         off, nb = ctypes.c_size_t(), ctypes.c_size_t()

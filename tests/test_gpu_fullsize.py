@@ -65,16 +65,15 @@ def test_full_size_solve_properties():
         assert torch.equal(Z1, Z2)
         npairs = len(plan.half_window())
         npatch = (2 * spec.K + 1) ** 2
-        inf = plan.info()
-        sig = plan.region_view(ws, nlpr.REGION_SIGMA).view(spec.L, inf.ntiles, npairs, npatch,
-                                                            inf.tile_rows, spec.q)
         mu = plan.region_view(ws, nlpr.REGION_MU).view(npairs, spec.p, spec.q)
         rng = np.random.default_rng(0)
         fracs = []
         P = o.patch_offsets(spec.K)
         for _ in range(6):
             n, m, c = int(rng.integers(npairs)), int(rng.integers(npatch)), int(rng.integers(spec.L))
-            s = sig[c, :, n, m].reshape(-1, spec.q)[:spec.p].cpu().numpy().astype(np.float64)
+            sig = plan.state_sigma(ws, c, c + 1)                       # [n][k][1][p][q]
+            s = sig[n, m, 0].cpu().numpy().astype(np.float64)
+            del sig
             k = P[m]
             bound = o.shift(mu[n].cpu().numpy().astype(np.float64), (-k[0], -k[1]))
             assert np.all(np.abs(s) <= bound * (1 + 1e-6) + 1e-30)
@@ -82,7 +81,7 @@ def test_full_size_solve_properties():
         frac = float(np.mean(fracs))
         print(f"[fullsize] fraction of duals on the threshold: {frac:.3f}", flush=True)
         assert 0.02 <= frac <= 0.98
-        del sig, mu, ws, Z1, Z2
+        del mu, ws, Z1, Z2
     finally:
         plan.close()
         release()

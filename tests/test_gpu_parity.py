@@ -202,7 +202,7 @@ def test_sweep_stage_two_steps(name):
                 newSig[a, m] = Sig[a, m] - (DX - Q)
                 Cw += o.D_T(Q + newSig[a, m], t, k)
         Sig = newSig
-        gs = host(plan.sigma_logical(sig))
+        gs = host(plan.sigma_expand(sig, plan.region_bytes(ws, nlpr.REGION_SIGMA_CODES), tmu))
         scale = mu.max()
         for n, a in enumerate(idx):
             for m, k in enumerate(P):
@@ -339,7 +339,7 @@ def test_sigma_stays_within_thresholds_and_shrink_branch_is_exercised():
     sc = synth.make_scene(synth.config("c1"))
     z, plan, ws = solve_gpu(sc)
     npairs = len(plan.half_window())
-    sig = host(plan.sigma_logical(plan.region_view(ws, nlpr.REGION_SIGMA)))
+    sig = host(plan.state_sigma(ws))
     mu = host(plan.region_view(ws, nlpr.REGION_MU)).reshape(npairs, *z.shape[1:])
     on_bound = []
     for m, k in enumerate(o.patch_offsets(sc.spec.K)):
@@ -348,6 +348,32 @@ def test_sigma_stays_within_thresholds_and_shrink_branch_is_exercised():
         on_bound.append(np.abs(np.abs(sig[:, m]) - bound) <= 1e-7 * bound)
     frac = float(np.mean(on_bound))
     assert 0.05 <= frac <= 0.95, frac
+
+
+@pytest.mark.parametrize("name", ["ragged", "wide", "radix3"])
+def test_coded_dual_state_counts_its_open_items(name):
+    """Sigma' keeps only the float4 items with an element off the threshold (|Sigma'| < mu);
+    the number the last sweep reports writing equals the number of such items in the
+    decoded state, and the state decodes to values within the thresholds."""
+    sc = scene_for(name, iters=5)
+    plan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING)
+    Z, ws = plan.solve(dev(sc.Yl), dev(sc.Yh))
+    counts = plan.sweep_counts()
+    assert len(counts) == 5 and all(c >= 0 for c in counts)
+    inf = plan.info()
+    npairs, npatch = inf.npairs, inf.npatch
+    _, p, q = plan.shape
+    sig = host(plan.state_sigma(ws))                                   # [n][k][L][p][q]
+    mu = host(plan.region_view(ws, nlpr.REGION_MU)).reshape(npairs, p, q)
+    P = o.patch_offsets(sc.spec.K)
+    opened = 0
+    for m, k in enumerate(P):
+        bound = np.stack([o.shift(mu[n], (-k[0], -k[1])) for n in range(npairs)])[:, None]
+        inside = np.abs(sig[:, m]) < bound
+        assert np.all(np.abs(sig[:, m]) <= bound)
+        opened += int(inside.reshape(npairs, -1, p, q // 4, 4).any(axis=-1).sum())
+    assert counts[-1] == opened, (counts, opened)
+    assert 0 < opened < npairs * npatch * sc.spec.L * p * q // 4
 
 
 def test_host_checks_on_device_buffers():
