@@ -63,7 +63,9 @@ enum {
                                    Q = Sigma = Lambda1 = Lambda2 = 0 (the paper names but does not
                                    give the initial values, Sec. "Optimization")                       */
   NLPR_STATE_IN = 1u << 1,      /* resume: the workspace holds the state left by an earlier
-                                   nlpr_solve with the same plan; run `iters` more iterations          */
+                                   nlpr_solve with the same plan and the same Y_h (the dual state
+                                   keeps elements on the threshold by reference to the thresholds,
+                                   which each solve derives from Y_h); run `iters` more iterations */
   NLPR_UNWEIGHTED = 1u << 2,    /* omega = 1 (ablation cases C2 / C4 of the paper)                    */
   NLPR_LOCAL_WINDOW = 1u << 3,  /* W = {0, +-e1, +-e2}: local pixel differences (ablation C5);
                                    requires Sw == 1                                                  */
