@@ -458,9 +458,12 @@ def main():
 
 def measure_solve(spec, steps, warmup, subspace=0, graph=False, fused=False, monitor=0,
                   shape_stream=False, traffic_key=None):
-    """Solve one synthetic scene `warmup` + `steps` times with the inputs resident in HBM and
-    report throughput, per-stage HIP-event times, the loop's HBM fraction and the sweep's
-    roofline (and its rate against the sweep-shaped reference stream)."""
+    """Solve one synthetic scene `warmup` + `steps` times with the inputs resident in HBM: the
+    timed region, on a plan without stage timers (an event recorded between two launches
+    costs a short kernel several microseconds).  Then, unless the solve runs as one graph,
+    solve it again on a plan with HIP events around every stage launch for the per-stage
+    times, the sweep's launch duration and open-item counts (the roofline), the loop's HBM
+    fraction and the sweep-shaped reference stream."""
     import numpy as np
     import torch
 
@@ -477,8 +480,9 @@ def measure_solve(spec, steps, warmup, subspace=0, graph=False, fused=False, mon
         M = sc.Yl.reshape(spec.L, -1).T.astype(np.float64)
         E = np.ascontiguousarray(np.linalg.svd(M, full_matrices=False)[2][:subspace],
                                  dtype=np.float32)
-    flags = (nlpr.GRAPH if graph else nlpr.TIMING) | (nlpr.FUSED_S if fused else 0)
-    plan = nlpr.Plan.from_scene(sc, flags=flags, E=E, monitor_every=monitor)
+    form = nlpr.FUSED_S if fused else 0
+    plan = nlpr.Plan.from_scene(sc, flags=(nlpr.GRAPH if graph else 0) | form, E=E,
+                                monitor_every=monitor)
     npairs = len(plan.half_window())
     ws = plan.alloc_workspace()
     Z = torch.empty((spec.L, spec.p, spec.q), dtype=torch.float32, device=dev)
@@ -487,9 +491,6 @@ def measure_solve(spec, steps, warmup, subspace=0, graph=False, fused=False, mon
         plan.solve(Yl, Yh, Z=Z, ws=ws)
         torch.cuda.synchronize()
         log(f"[bench] warmup {i + 1} done")
-    if not graph:
-        for st in nlpr.STAGE_NAMES:
-            plan.stage_time(st, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step_s = []
@@ -501,18 +502,37 @@ def measure_solve(spec, steps, warmup, subspace=0, graph=False, fused=False, mon
         log(f"[bench] step {i + 1} done at {time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    stages = {}
-    for st, name in ([] if graph else nlpr.STAGE_NAMES.items()):
-        ms, n = plan.stage_time(st)
-        if n:
-            stages[name] = {"ms_total": round(ms, 3), "launches": n, "ms_avg": round(ms / n, 4)}
     finite = bool(torch.isfinite(Z).all().item())
-    lx = subspace or spec.L
-    shape_gbs = sweep_shape_stream(plan, ws, spec, lx) if (shape_stream and npairs) else None
+    mon = ([dict(zip(nlpr.MON_FIELDS, map(float, r))) for r in plan.monitor()]
+           if monitor else None)
+    plan.close()
     value = spec.p * spec.q * spec.L * spec.iters * steps / elapsed
+    lx = subspace or spec.L
+
+    # stage timers: per-stage HIP events, the sweep's open-item counts
+    stages, counts, shape_gbs, prof_steps = {}, [], None, 0
+    if not graph:
+        prof_steps = max(1, min(steps, 3))
+        tplan = nlpr.Plan.from_scene(sc, flags=nlpr.TIMING | form, E=E)
+        tplan.solve(Yl, Yh, Z=Z, ws=ws)
+        torch.cuda.synchronize()
+        for st in nlpr.STAGE_NAMES:
+            tplan.stage_time(st, reset=True)
+        for i in range(prof_steps):
+            tplan.solve(Yl, Yh, Z=Z, ws=ws)
+            torch.cuda.synchronize()
+        log(f"[bench] {prof_steps} solves with stage timers done")
+        for st, name in nlpr.STAGE_NAMES.items():
+            ms, n = tplan.stage_time(st)
+            if n:
+                stages[name] = {"ms_total": round(ms, 3), "launches": n,
+                                "ms_avg": round(ms / n, 4)}
+        counts = tplan.sweep_counts() if npairs else []
+        if shape_stream and npairs:
+            shape_gbs = sweep_shape_stream(tplan, ws, spec, lx)
+        tplan.close()
     sw = stages.get("sweep")
     roof = None
-    counts = plan.sweep_counts() if (npairs and not graph) else []
     sweep_bytes = coded_sweep_bytes(spec, npairs, lx, counts) if counts else []
     if sw and len(sweep_bytes) > 1:
         # the timed "sweep" launches are iterations 2 .. T of every solve (the first sweep of a
@@ -534,38 +554,42 @@ def measure_solve(spec, steps, warmup, subspace=0, graph=False, fused=False, mon
         roof["traffic"] = tr["hbm_bytes_per_launch"]
         roof["traffic_launches"] = tr.get("launches")
         roof["traffic_over_algorithmic"] = tr.get("traffic_over_algorithmic")
-    # the iterations alone (HIP events around every stage launch, weights and start excluded):
-    # bytes of an iteration = the sweep's (coded Sigma', X, C, mu) + 16 dense FP32 touches of
-    # the other stages (X, BX, C, Lambda1, Lambda2, W1, W2, FFT in/out) per pixel and band;
-    # also against the bytes the dual state would move stored densely (8 N_pairs |P| + 64 B
-    # per pixel, band and iteration)
-    loop_ms = sum(v["ms_total"] for k, v in stages.items() if k not in ("weights", "init"))
-    loop_bytes_pbi = 8 * npairs * (2 * spec.K + 1) ** 2 + 64
+    # the iterations alone: the timed solve's wall time less the weights and start (their
+    # event times from the profiled solves).  Bytes of an iteration = the sweep's (coded
+    # Sigma', X, C, mu) + 16 dense FP32 touches of the other stages (X, BX, C, Lambda1,
+    # Lambda2, W1, W2, FFT in/out) per pixel and band; also against the bytes the dual state
+    # would move stored densely (8 N_pairs |P| + 64 B per pixel, band and iteration)
     loop = None
-    if loop_ms:
-        pbi = spec.p * spec.q * lx * spec.iters * steps
+    if prof_steps:
+        setup_ms = sum(stages[k]["ms_total"] for k in ("weights", "init") if k in stages)
+        setup_ms /= prof_steps
+        events_ms = sum(v["ms_total"] for k, v in stages.items()
+                        if k not in ("weights", "init")) / prof_steps
+        loop_ms = elapsed / steps * 1e3 - setup_ms          # per solve
+        pbi = spec.p * spec.q * lx * spec.iters
+        loop_bytes_pbi = 8 * npairs * (2 * spec.K + 1) ** 2 + 64
         dense_gbs = loop_bytes_pbi * pbi / (loop_ms * 1e-3) / 1e9
-        loop = {"t_loop_ms_per_solve": round(loop_ms / steps, 3),
+        loop = {"t_loop_ms_per_solve": round(loop_ms, 3),
                 "t_total_ms_per_solve": round(elapsed / steps * 1e3, 3),
+                "t_setup_ms_per_solve": round(setup_ms, 3),
+                "t_stage_events_ms_per_solve": round(events_ms, 3),
                 "step_ms_median": round(sorted(step_s)[len(step_s) // 2] * 1e3, 3),
                 "dense_format_bytes_per_pbi": loop_bytes_pbi,
                 "dense_format_equivalent_GBs": round(dense_gbs, 1),
                 "dense_format_hbm_frac": round(dense_gbs / HBM_PEAK_GBS, 4)}
         if sweep_bytes:
-            coded = (sum(sweep_bytes) + 64 * spec.p * spec.q * lx * spec.iters) * steps
+            coded = sum(sweep_bytes) + 64 * pbi
             gbs = coded / (loop_ms * 1e-3) / 1e9
-            loop.update({"bytes_per_solve": sum(sweep_bytes) + 64 * spec.p * spec.q * lx *
-                         spec.iters, "achieved_GBs": round(gbs, 1),
+            loop.update({"bytes_per_solve": coded, "achieved_GBs": round(gbs, 1),
                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
     res = {"value": value, "ms_per_step": elapsed / steps * 1e3, "roofline": roof,
-           "loop_pbi_per_s": spec.p * spec.q * spec.L * spec.iters * steps / (loop_ms * 1e-3)
-           if loop_ms else None,
+           "loop_pbi_per_s": spec.p * spec.q * spec.L * spec.iters / (loop["t_loop_ms_per_solve"]
+                                                                     * 1e-3) if loop else None,
            "loop": loop, "stages": stages, "finite": finite,
            "sweep_shape_stream_GBs": shape_gbs}
     if monitor:
-        res["monitor"] = [dict(zip(nlpr.MON_FIELDS, map(float, r))) for r in plan.monitor()]
+        res["monitor"] = mon
     del ws, Z, Yl, Yh
-    plan.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return res

@@ -485,30 +485,28 @@ int batch_build(Batch& B) {
   }
   if ((rc = simple(KD_ROWS, rows_blocks, rows_lds, rows_block))) return rc;
   if ((rc = simple(KD_COLS, cols_blocks, cols_lds, cols_block))) return rc;
-  // the sweep: one launch per (patch radius, tile size, workgroup size)
+  // the sweep: one launch per (patch radius, tile size)
   for (int K = 0; K <= kMaxK; ++K)
-    for (int items = 1; items <= 4; items *= 2)
-      for (int threads : {128, 256}) {
-        std::vector<int2> it;
-        size_t l = 0;
-        for (int s = 0; s < n; ++s) {
-          const Plan& P = *B.scenes[s];
-          if (P.npairs == 0 || P.prm.K != K || P.sweep.items != items ||
-              P.sweep.threads != threads)
-            continue;
-          const int c = sweep_blocks(P);
-          for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
-          l = std::max(l, P.sweep.lds);
-        }
-        if (it.empty()) continue;
-        if ((rc = add_group(B, KD_SWEEP, it, threads, l, K, items))) return rc;
-        if ((rc = sweep_prepare(K, items, threads))) return rc;
+    for (int items = 1; items <= 4; items *= 2) {
+      std::vector<int2> it;
+      size_t l = 0;
+      for (int s = 0; s < n; ++s) {
+        const Plan& P = *B.scenes[s];
+        if (P.npairs == 0 || P.prm.K != K || P.sweep.items != items) continue;
+        const int c = sweep_blocks(P);
+        for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
+        l = std::max(l, P.sweep.lds);
       }
+      if (it.empty()) continue;
+      if ((rc = add_group(B, KD_SWEEP, it, kSweepThreads, l, K, items))) return rc;
+      if ((rc = sweep_prepare(K, items))) return rc;
+    }
   NLPR_HIP_TRY(hipMalloc(&B.d_desc, n * sizeof(SceneDesc)));
   NLPR_HIP_TRY(hipHostMalloc(&B.h_desc, n * sizeof(SceneDesc)));
   NLPR_HIP_TRY(hipMalloc(&B.d_flag, 256));
   if (B.timing)
-    NLPR_HIP_TRY(hipMalloc(&B.d_counts, std::max(B.iters, 1) * sizeof(unsigned long long)));
+    NLPR_HIP_TRY(hipMalloc(&B.d_counts, (size_t)std::max(B.iters, 1) * kCountSlots * kCountStride *
+                                            sizeof(unsigned long long)));
   NLPR_HIP_TRY(hipEventCreateWithFlags(&B.upload_ev, hipEventDisableTiming));
   NLPR_HIP_TRY(hipEventCreateWithFlags(&B.done_ev, hipEventDisableTiming));
   B.uploaded.resize(n);
@@ -586,7 +584,9 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
   const bool fused = (B.flags & NLPR_FUSED_S) != 0;
   const bool check = (B.flags & NLPR_CHECK_FINITE) != 0;
   if (check && (rc = launch_finite_clear(B.d_flag, s))) return rc;
-  if (B.d_counts && (rc = launch_zero_u64(B.d_counts, B.iters, s))) return rc;
+  if (B.d_counts &&
+      (rc = launch_zero_u64(B.d_counts, B.iters * kCountSlots * kCountStride, s)))
+    return rc;
   if (sub) {
     StageTimer tm(B, s, NLPR_STAGE_INIT);
     if ((rc = launch_project(B, B_YL, B_YLE, B_YLP, s))) return rc;
@@ -640,7 +640,8 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
       const bool first = (t == 0 && !resume);
       StageTimer tm(B, s, first ? NLPR_STAGE_SWEEP_FIRST : NLPR_STAGE_SWEEP);
       if ((rc = launch_sweep(B, B_Z, B_MU, B_SIGMA, B_C, B_HALO, first, s, nullptr,
-                             B.d_counts ? B.d_counts + t : nullptr)))
+                             B.d_counts ? B.d_counts + (size_t)t * kCountSlots * kCountStride
+                                        : nullptr)))
         return rc;
     }
     {
@@ -1217,10 +1218,15 @@ int nlpr_sweep_counts(const nlpr_plan* plan, int64_t* counts, int32_t cap, int32
   if (!counts || cap <= 0 || *n == 0) return NLPR_OK;
   DeviceGuard dg(B.device);
   NLPR_HIP_TRY(hipEventSynchronize(B.done_ev));
-  std::vector<unsigned long long> h(B.iters);
-  NLPR_HIP_TRY(hipMemcpy(h.data(), B.d_counts, B.iters * sizeof(unsigned long long),
+  const size_t per = (size_t)kCountSlots * kCountStride;
+  std::vector<unsigned long long> h(B.iters * per);
+  NLPR_HIP_TRY(hipMemcpy(h.data(), B.d_counts, h.size() * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost));
-  for (int i = 0; i < std::min(cap, *n); ++i) counts[i] = (int64_t)h[i];
+  for (int i = 0; i < std::min(cap, *n); ++i) {
+    unsigned long long sum = 0;
+    for (int k = 0; k < kCountSlots; ++k) sum += h[i * per + (size_t)k * kCountStride];
+    counts[i] = (int64_t)sum;
+  }
   return NLPR_OK;
 }
 

@@ -99,10 +99,14 @@ struct SceneDesc {
   void* buf[B_COUNT];
 };
 
+constexpr int kSweepThreads = 256;   // workgroup size of the sweep
+// open-item counters of one sweep launch (timing plans): kCountSlots, kCountStride apart
+constexpr int kCountSlots = 64;
+constexpr int kCountStride = 16;
+
 struct SweepShape {
   int rows;      // tile height R
   int items;     // tile size in units of 256 float4 items (1024 pixels): 1, 2 or 4
-  int threads;   // workgroup size: 256 (items per thread = items) or 128 (2 per thread)
   int ntiles;    // ceil(p / R)
   int halo;      // rows above the tile reached by the adjoint scatter (max tau1)
   int split;     // workgroups per (tile, band), each over a contiguous part of W+
@@ -355,7 +359,7 @@ int launch_sigma_expand(const Batch& B, const float* sig, const uint8_t* codes, 
                         int c0, int nb, float* out, hipStream_t s);
 // zero n 64-bit counters
 int launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
-int sweep_prepare(int K, int items, int threads);   // kernel attributes; before launches or capture
+int sweep_prepare(int K, int items);   // kernel attributes; before launches or capture
 
 // ---- shapes and tuning
 SweepShape choose_sweep_shape(int p, int q, int K, int halo);

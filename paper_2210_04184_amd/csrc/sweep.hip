@@ -80,7 +80,8 @@ __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v
 // threshold it took, which is all the sweep's adjoint needs of this iteration: 2 bits, 0 for
 // |V| < mu, 1 for V >= mu, 2 for V <= -mu, 3 for V = 0 with mu = 0 (or V not a number).  The
 // four elements of a float4 item share one byte, at the item's float offset / 4.
-// COUNT: add the number of open items written by each wave to *count.
+// COUNT: add the number of open items written by each wave to one of the kCountSlots
+// counters at count (kCountStride apart); their sum is the launch's count.
 template <int K, int ITEMS, int NT, bool FIRST, bool CODES>
 __global__ void __launch_bounds__(NT)
 sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s, int mu_s,
@@ -312,7 +313,12 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
       }
     }
   }
-  if (count && (threadIdx.x & 63) == 0) atomicAdd(count, (unsigned long long)open_written);
+  if (count && (threadIdx.x & 63) == 0) {
+    // spread over kCountSlots counters a cache line apart: waves that end together on one
+    // address would queue behind each other at the L2
+    const unsigned slot = (blockIdx.x * (NT / 64) + threadIdx.x / 64) % kCountSlots;
+    atomicAdd(count + (size_t)slot * kCountStride, (unsigned long long)open_written);
+  }
   __syncthreads();
 
   gfloat* cregc = creg + (size_t)c * plane + (size_t)r0 * q;
@@ -336,14 +342,11 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
 // ---- sweep kernel end
 
 // Tiles and launch shapes.  A tile is 1024 * items pixels (items = 1, 2 or 4: the fewest with
-// one full image row per tile), i.e. 256 * items float4 items, whatever the workgroup shape:
-// the layout of Sigma' and of its codes depends on the tile only (segments of 64 items).  A
-// tile runs on 256 threads with `items` items each, or, for patches of at most 3 x 3 with
-// single-item tiles, on 128 threads with 2 items each: a 3 x 3 patch leaves each workgroup
-// only 9 planes per shift, and two independent items per thread keep its dependent chains of
-// loads, ballots and stores overlapped (256 x 256 x 31: 134 -> 108 us per launch; for 5 x 5
-// the second item's registers cost occupancy, 32 -> 38 ms at 512 x 512 x 128).
-constexpr int kThreads = 256;
+// one full image row per tile), i.e. 256 * items float4 items, on a workgroup of 256 threads
+// with `items` items each; the layout of Sigma' and of its codes depends on the tile only
+// (segments of 64 items).  For 3 x 3 patches at 256 x 256 x 31 this shape is faster than 128
+// threads with two items each (89 against 154 VGPRs: five waves per SIMD instead of three;
+// 20-iteration solve 2.88 against 3.16 ms).
 
 template <int K, int ITEMS, int NT, bool FIRST, bool CODES>
 int launch_k(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
@@ -359,7 +362,7 @@ int launch_k(const Batch& B, const Group& g, int x, int mu, int sig, int creg, i
 // during graph capture).  The branch-recording variant exists for single-item tiles.
 template <int K, int ITEMS, int NT>
 int set_lds_limit() {
-  const bool single = ITEMS * NT == 256;
+  const bool single = ITEMS == 1;
   const void* kern[4] = {
       reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, NT, true, false>),
       reinterpret_cast<const void*>(sweep_kernel<K, ITEMS, NT, false, false>),
@@ -372,18 +375,15 @@ int set_lds_limit() {
 }
 
 template <int K>
-int set_lds_limit_items(int items, int threads) {
-  if constexpr (K <= 1) {
-    if (threads == 128) return set_lds_limit<K, 2, 128>();
-  }
+int set_lds_limit_items(int items) {
   switch (items) {
-    case 1: return set_lds_limit<K, 1, 256>();
-    case 2: return set_lds_limit<K, 2, 256>();
-    default: return set_lds_limit<K, 4, 256>();
+    case 1: return set_lds_limit<K, 1, kSweepThreads>();
+    case 2: return set_lds_limit<K, 2, kSweepThreads>();
+    default: return set_lds_limit<K, 4, kSweepThreads>();
   }
 }
 
-// g.key1 = tile items, g.block = threads
+// g.key1 = tile items
 template <int K, bool FIRST>
 int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
                  uint8_t* codes, unsigned long long* count, hipStream_t s) {
@@ -391,21 +391,14 @@ int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int cre
     set_error("sweep: branch codes need single-item tiles");
     return NLPR_ERR_UNSUPPORTED_SHAPE;
   }
-  if constexpr (K <= 1) {
-    if (g.block == 128)
-      return codes ? launch_k<K, 2, 128, FIRST, true>(B, g, x, mu, sig, creg, halo, codes, count,
-                                                      s)
-                   : launch_k<K, 2, 128, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr,
-                                                       count, s);
-  }
-  if (codes) return launch_k<K, 1, 256, FIRST, true>(B, g, x, mu, sig, creg, halo, codes, count, s);
+  if (codes) return launch_k<K, 1, kSweepThreads, FIRST, true>(B, g, x, mu, sig, creg, halo, codes, count, s);
   switch (g.key1) {
     case 1:
-      return launch_k<K, 1, 256, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
+      return launch_k<K, 1, kSweepThreads, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
     case 2:
-      return launch_k<K, 2, 256, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
+      return launch_k<K, 2, kSweepThreads, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
     default:
-      return launch_k<K, 4, 256, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
+      return launch_k<K, 4, kSweepThreads, FIRST, false>(B, g, x, mu, sig, creg, halo, nullptr, count, s);
   }
 }
 
@@ -414,10 +407,9 @@ int launch_items(const Batch& B, const Group& g, int x, int mu, int sig, int cre
 SweepShape choose_sweep_shape(int p, int q, int K, int halo) {
   SweepShape sh{};
   int items = 1;
-  while (items < 4 && kThreads * items * 4 < q) items *= 2;
+  while (items < 4 && kSweepThreads * items * 4 < q) items *= 2;
   sh.items = items;
-  sh.threads = (items == 1 && K <= 1) ? 128 : kThreads;
-  const int per_block = kThreads * items * 4;  // pixels per workgroup
+  const int per_block = kSweepThreads * items * 4;  // pixels per workgroup
   sh.rows = std::max(1, std::min(p, per_block / q));
   sh.ntiles = ceil_div(p, sh.rows);
   sh.halo = halo;
@@ -439,13 +431,13 @@ int choose_pair_split(int blocks, int npairs) {
 
 int sweep_blocks(const Plan& P) { return P.sweep.ntiles * P.Lx * P.sweep.split; }
 
-int sweep_prepare(int K, int items, int threads) {
+int sweep_prepare(int K, int items) {
   switch (K) {
-    case 0: return set_lds_limit_items<0>(items, threads);
-    case 1: return set_lds_limit_items<1>(items, threads);
-    case 2: return set_lds_limit_items<2>(items, threads);
-    case 3: return set_lds_limit_items<3>(items, threads);
-    case 4: return set_lds_limit_items<4>(items, threads);
+    case 0: return set_lds_limit_items<0>(items);
+    case 1: return set_lds_limit_items<1>(items);
+    case 2: return set_lds_limit_items<2>(items);
+    case 3: return set_lds_limit_items<3>(items);
+    case 4: return set_lds_limit_items<4>(items);
     default: set_error("sweep: unsupported patch radius"); return NLPR_ERR_UNSUPPORTED_SHAPE;
   }
 }
@@ -533,7 +525,7 @@ sigma_expand_kernel(const SceneDesc* __restrict__ sd, const gfloat* __restrict__
 int launch_sigma_expand(const Batch& B, const float* sig, const uint8_t* codes, const float* mu,
                         int c0, int nb, float* out, hipStream_t s) {
   const Plan& P = *B.scenes[0];
-  const int per_plane = kThreads * P.sweep.items;
+  const int per_plane = kSweepThreads * P.sweep.items;
   const size_t total = (size_t)nb * P.sweep.ntiles * P.npairs * P.npatch * per_plane;
   if (total == 0) return NLPR_OK;
   const size_t blocks = (total + 255) / 256;
