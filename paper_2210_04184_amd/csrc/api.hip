@@ -352,6 +352,12 @@ void batch_release(Batch& B) {
   if (B.h_desc) hipHostFree(B.h_desc);
   hipFree(B.d_flag);
   hipFree(B.d_counts);
+  if (B.side) {
+    hipStreamSynchronize(B.side);
+    hipStreamDestroy(B.side);
+  }
+  if (B.fork_ev) hipEventDestroy(B.fork_ev);
+  if (B.join_ev) hipEventDestroy(B.join_ev);
   if (B.upload_ev) hipEventDestroy(B.upload_ev);
   if (B.done_ev) hipEventDestroy(B.done_ev);
   if (B.graph) hipGraphExecDestroy(B.graph);
@@ -365,6 +371,9 @@ void batch_release(Batch& B) {
   B.d_counts = nullptr;
   B.upload_ev = nullptr;
   B.done_ev = nullptr;
+  B.side = nullptr;
+  B.fork_ev = nullptr;
+  B.join_ev = nullptr;
   B.graph = nullptr;
 }
 
@@ -386,8 +395,8 @@ int add_group(Batch& B, Kind kind, const std::vector<int2>& items, int block, si
 }
 
 int block256(const Plan&) { return 256; }
-int rows_block(const Plan& P) { return fft_block(P.fft.q_tpl); }
-int cols_block(const Plan& P) { return fft_block(P.fft.p_tpl); }
+int rows_block(const Plan& P) { return P.fft.q_bs; }
+int cols_block(const Plan& P) { return P.fft.p_bs; }
 size_t no_lds(const Plan&) { return 0; }
 
 // Work-item tables of every launch kind, descriptors, events.
@@ -509,6 +518,17 @@ int batch_build(Batch& B) {
                                             sizeof(unsigned long long)));
   NLPR_HIP_TRY(hipEventCreateWithFlags(&B.upload_ev, hipEventDisableTiming));
   NLPR_HIP_TRY(hipEventCreateWithFlags(&B.done_ev, hipEventDisableTiming));
+  size_t pbands = 0;
+  bool reg = false;
+  for (const Plan* P : B.scenes) {
+    pbands += (size_t)P->prm.p * P->prm.q * P->Lx;
+    reg = reg || P->npairs > 0;
+  }
+  if (reg && !B.timing && pbands >= kForkPixelBands) {
+    NLPR_HIP_TRY(hipStreamCreateWithFlags(&B.side, hipStreamNonBlocking));
+    NLPR_HIP_TRY(hipEventCreateWithFlags(&B.fork_ev, hipEventDisableTiming));
+    NLPR_HIP_TRY(hipEventCreateWithFlags(&B.join_ev, hipEventDisableTiming));
+  }
   B.uploaded.resize(n);
   B.desc_valid = false;
   return NLPR_OK;
@@ -622,16 +642,31 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
     if (check && ((t + 1) % kFiniteEvery == 0 || t + 1 == B.iters) &&
         (rc = launch_finite(B, B_Z, B.d_flag, t + 1, s)))
       return rc;
+    // The P-side (blur, P-update, and T = B^T W1 + W2, the part of the right-hand side that
+    // does not wait for the sweep, into the BX slot) and the sweep read X and write disjoint
+    // buffers.  In a batch with a side stream the P-side forks onto it and joins before the
+    // assembly adds the regulariser term, so it runs while the sweep does; a monitor record
+    // keeps this iteration on one stream.  C = (B^T W1 + W2) + C_reg either way, with the
+    // same additions in the same order.
+    const bool fork = B.side != nullptr && !mon;
+    const bool tpart = fork && !fused;
+    hipStream_t sp = s;
+    if (fork) {
+      NLPR_HIP_TRY(hipEventRecord(B.fork_ev, s));
+      NLPR_HIP_TRY(hipStreamWaitEvent(B.side, B.fork_ev, 0));
+      sp = B.side;
+    }
     if (!fused || mon) {           // fused-S needs B X only for the monitor's data term
-      StageTimer tm(B, s, NLPR_STAGE_BLUR);
-      if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, s))) return rc;
+      StageTimer tm(B, sp, NLPR_STAGE_BLUR);
+      if ((rc = launch_conv(B, B_Z, B_BX, false, -1, -1, -1, 0, sp))) return rc;
     }
     {
-      StageTimer tm(B, s, NLPR_STAGE_PUPDATE);
-      if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, B_L1, B_L2, s)))
+      StageTimer tm(B, sp, NLPR_STAGE_PUPDATE);
+      if ((rc = launch_pupdate(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_W1, B_W2, B_L1, B_L2, sp)))
         return rc;
-      if (sub && (rc = launch_p1_subspace(B, B_BX, B_YLE, B_L1, B_W1, s))) return rc;
+      if (sub && (rc = launch_p1_subspace(B, B_BX, B_YLE, B_L1, B_W1, sp))) return rc;
     }
+    if (tpart && (rc = launch_conv(B, B_W1, B_BX, true, B_W2, -1, -1, 0, sp))) return rc;
     if (mon) {
       StageTimer tm(B, s, NLPR_STAGE_MONITOR);
       if ((rc = launch_monitor(B, point++, t + 1, s))) return rc;
@@ -644,9 +679,18 @@ int enqueue_solve(Batch& B, bool resume, hipStream_t s) {
                                         : nullptr)))
         return rc;
     }
+    if (fork) {
+      NLPR_HIP_TRY(hipEventRecord(B.join_ev, sp));
+      NLPR_HIP_TRY(hipStreamWaitEvent(s, B.join_ev, 0));
+    }
     {
       StageTimer tm(B, s, NLPR_STAGE_ASSEMBLE);
-      if ((rc = launch_conv(B, fused ? -1 : B_W1, B_C, true, B_W2, B_C, B_HALO, 2 | 4, s))) return rc;
+      if (tpart) {
+        if ((rc = launch_conv(B, -1, B_C, true, B_BX, B_C, B_HALO, 2 | 4, s))) return rc;
+      } else if ((rc = launch_conv(B, fused ? -1 : B_W1, B_C, true, B_W2, B_C, B_HALO, 2 | 4,
+                                   s))) {
+        return rc;
+      }
     }
   }
   if (check && B.iters == 0 && (rc = launch_finite(B, B_Z, B.d_flag, 0, s))) return rc;

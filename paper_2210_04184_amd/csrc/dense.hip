@@ -519,6 +519,27 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
   const int y = threadIdx.x >> 4;            // 16 rows
   const int xb = (threadIdx.x & 15) * 4;     // 4 outputs per thread
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const int gy2 = y0 + y;
+  const bool reg = S.npairs > 0;
+  const gfloat* a1 = (reg || !(reg_mask & 1)) ? gslot<const gfloat>(S, add1_s) : nullptr;
+  const gfloat* a2 = (reg || !(reg_mask & 2)) ? gslot<const gfloat>(S, add2_s) : nullptr;
+  const gfloat* hb = reg ? gslot<const gfloat>(S, halo_s) : nullptr;
+  gfloat* out = gslot<gfloat>(S, out_s);
+  const int gx0 = x0 + xb;
+  const size_t o0 = (size_t)c * plane + (size_t)gy2 * q + gx0;
+  // bit 2: the regulariser term comes from a sweep split into psplit parts; parts 1 ..
+  // psplit-1 left their planes in slot B_CSPLIT and every part its own halo rows
+  const int ns = (reg && (reg_mask & 4)) ? S.psplit : 1;
+  const gfloat* cs = ns > 1 ? gslot<const gfloat>(S, B_CSPLIT) : nullptr;
+  const uintptr_t align = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(a1) |
+                          reinterpret_cast<uintptr_t>(a2) | reinterpret_cast<uintptr_t>(hb) |
+                          reinterpret_cast<uintptr_t>(cs);
+  const bool vec = gy2 < p && gx0 + 3 < q && (align & 15) == 0;
+  // the addends of the 16-byte path are requested before the convolution, so their latency
+  // overlaps it (out may be add2: each thread reads and writes only its own four outputs)
+  float4 t1 = make_float4(0.f, 0.f, 0.f, 0.f), t2 = t1;
+  if (vec && a1) t1 = ldg4(a1 + o0);
+  if (vec && a2) t2 = ldg4(a2 + o0);
   // in_s < 0: no convolution, out = add1 + add2 + halo fold (uniform over the launch)
   if (in_s >= 0) {
     const gfloat* inc = gslot<const gfloat>(S, in_s) + (size_t)c * plane;
@@ -621,36 +642,19 @@ conv_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, in
       }
     }
   }
-  const int gy2 = y0 + y;
   if (gy2 >= p) return;
-  const bool reg = S.npairs > 0;
-  const gfloat* a1 = (reg || !(reg_mask & 1)) ? gslot<const gfloat>(S, add1_s) : nullptr;
-  const gfloat* a2 = (reg || !(reg_mask & 2)) ? gslot<const gfloat>(S, add2_s) : nullptr;
-  const gfloat* hb = reg ? gslot<const gfloat>(S, halo_s) : nullptr;
-  gfloat* out = gslot<gfloat>(S, out_s);
-  const int gx0 = x0 + xb;
-  const size_t o0 = (size_t)c * plane + (size_t)gy2 * q + gx0;
   // halo rows folded into image row gy2: halo row h of the tile starting at row
   // gy2 + H - h (when that is a tile start); the same for the four columns
   const int H = hb ? S.halo : 0, R = S.rows;
-  // bit 2: the regulariser term comes from a sweep split into psplit parts; parts 1 ..
-  // psplit-1 left their planes in slot B_CSPLIT and every part its own halo rows
-  const int ns = (reg && (reg_mask & 4)) ? S.psplit : 1;
-  const gfloat* cs = ns > 1 ? gslot<const gfloat>(S, B_CSPLIT) : nullptr;
   const size_t cs_stride = (size_t)S.L * plane;
   const size_t hb_stride = (size_t)S.L * S.ntiles * H * q;
-  const uintptr_t align = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(a1) |
-                          reinterpret_cast<uintptr_t>(a2) | reinterpret_cast<uintptr_t>(hb) |
-                          reinterpret_cast<uintptr_t>(cs);
-  if (gx0 + 3 < q && (align & 15) == 0) {
+  if (vec) {
     float4 v = make_float4(acc[0], acc[1], acc[2], acc[3]);
     if (a1) {
-      const float4 t = ldg4(a1 + o0);
-      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+      v.x += t1.x; v.y += t1.y; v.z += t1.z; v.w += t1.w;
     }
     if (a2) {
-      const float4 t = ldg4(a2 + o0);
-      v.x += t.x; v.y += t.y; v.z += t.z; v.w += t.w;
+      v.x += t2.x; v.y += t2.y; v.z += t2.z; v.w += t2.w;
     }
     // the parts are loaded four at a time before they are added (in order; an absent part
     // adds zero), so their latencies overlap
@@ -778,7 +782,95 @@ __device__ __forceinline__ void pupdate_write(
   }
 }
 
-template <int LHM, int PU_NC>
+// With at most kPuKeep bands per thread, X and Lambda2 are read once: the contraction pass
+// keeps them in registers for the write pass (32 bytes per pixel and band instead of 40).
+// Same operations in the same order as the two functions above.
+constexpr int kPuKeep = 16;
+
+// All loads of the thread's bands up front (X, Lambda2, and for P1 BX and Lambda1), so that
+// their latencies overlap: the contraction pass then only waits for X and Lambda2.
+template <int LHM>
+__device__ __forceinline__ void pupdate_load_keep(const gfloat* __restrict__ X,
+                                                  const gfloat* __restrict__ L2,
+                                                  const gfloat* __restrict__ BX,
+                                                  const gfloat* __restrict__ L1,
+                                                  const gfloat* __restrict__ Yl, bool p1,
+                                                  bool sampled, size_t plane, size_t lplane,
+                                                  size_t lj, int c0, int c1, int j,
+                                                  float (&xs)[kPuKeep], float (&l2s)[kPuKeep],
+                                                  float (&bxs)[kPuKeep], float (&l1s)[kPuKeep],
+                                                  float (&yls)[kPuKeep]) {
+#pragma unroll
+  for (int i = 0; i < kPuKeep; ++i) {
+    const int c = c0 + i;
+    if (c < c1) {
+      xs[i] = X[c * plane + j];
+      l2s[i] = L2[c * plane + j];
+    }
+  }
+  if (!p1) return;
+#pragma unroll
+  for (int i = 0; i < kPuKeep; ++i) {
+    const int c = c0 + i;
+    if (c < c1) {
+      bxs[i] = BX[c * plane + j];
+      l1s[i] = L1[c * plane + j];
+      if (sampled) yls[i] = Yl[c * lplane + lj];
+    }
+  }
+}
+
+// rp += sum over bands [cs, ce) of (X - Lambda2)_c R_c, from the kept values (band c at
+// register c - c0)
+template <int LHM>
+__device__ __forceinline__ void pupdate_share_kept(const float (&xs)[kPuKeep],
+                                                   const float (&l2s)[kPuKeep],
+                                                   const gfloat* __restrict__ R,
+                                                   float (&rp)[LHM], int Lh, int c0, int cs,
+                                                   int ce) {
+#pragma unroll
+  for (int i = 0; i < kPuKeep; ++i) {
+    const int c = c0 + i;
+    if (c >= cs && c < ce) {
+      const float a0 = xs[i] - l2s[i];
+#pragma unroll
+      for (int h = 0; h < LHM; ++h)
+        if (h < Lh) rp[h] = __builtin_fmaf(a0, R[c * Lh + h], rp[h]);
+    }
+  }
+}
+
+template <int LHM>
+__device__ __forceinline__ void pupdate_write_kept(
+    const float (&xs)[kPuKeep], const float (&l2s)[kPuKeep], const float (&bxs)[kPuKeep],
+    const float (&l1s)[kPuKeep], const float (&yls)[kPuKeep], gfloat* L1o, gfloat* L2o,
+    gfloat* __restrict__ W1, gfloat* __restrict__ W2, const gfloat* __restrict__ R,
+    const float (&u)[LHM], size_t plane, bool sampled, int p1mode, int Lh, float rho,
+    float inv_1prho, int c0, int c1, int j) {
+#pragma unroll
+  for (int i = 0; i < kPuKeep; ++i) {
+    const int c = c0 + i;
+    if (c >= c1) continue;
+    const size_t o = c * plane + j;
+    float corr = 0.f;
+#pragma unroll
+    for (int h = 0; h < LHM; ++h)
+      if (h < Lh) corr += u[h] * R[c * Lh + h];
+    const float x = xs[i], l2 = l2s[i];
+    const float p2 = (x - l2) + corr;
+    const float l2n = l2 - (x - p2);
+    L2o[o] = l2n;
+    W2[o] = p2 + l2n;
+    if (p1mode == 2 || (sampled && p1mode == 1)) continue;
+    const float bx = bxs[i], l1 = l1s[i];
+    const float p1 = sampled ? (rho * bx + yls[i] - rho * l1) * inv_1prho : bx - l1;
+    const float l1n = l1 - (bx - p1);
+    L1o[o] = l1n;
+    W1[o] = p1 + l1n;
+  }
+}
+
+template <int LHM, int PU_NC, bool KEEP>
 __global__ void __launch_bounds__(256 * PU_NC)
 pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
                int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1_s, int w2_s, int l1o_s,
@@ -804,6 +896,25 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
   // is summed on its own and the parts are added in share order, so the result does not
   // depend on how many threads a pixel has.
   float res[LHM];
+  // KEEP: every scene of the launch has at most kPuKeep bands per thread
+  const int i1 = j / q, i2 = j - i1 * q;
+  const bool sampled = (i1 % d == 0) && (i2 % d == 0);
+  // p1mode 1: a basis couples the sampled pixels across bands (p1_subspace_kernel);
+  // p1mode 2: fused-S splitting, no P1
+  const int p1mode = S.fused ? 2 : (S.subspace ? 1 : 0);
+  const bool p1 = !(p1mode == 2 || (sampled && p1mode == 1));
+  const size_t lplane = (size_t)(p / d) * (q / d), lj = (size_t)(i1 / d) * (q / d) + i2 / d;
+  float xs[KEEP ? kPuKeep : 1], l2s[KEEP ? kPuKeep : 1], bxs[KEEP ? kPuKeep : 1],
+      l1s[KEEP ? kPuKeep : 1], yls[KEEP ? kPuKeep : 1], yh[LHM];
+  if constexpr (KEEP)
+    if (act)
+    pupdate_load_keep<LHM>(X, L2, gslot<const gfloat>(S, bx_s), gslot<const gfloat>(S, l1_s),
+                           gslot<const gfloat>(S, yl_s), p1, sampled, plane, lplane, lj, c0, c1,
+                           j, xs, l2s, bxs, l1s, yls);
+  if (act) {
+#pragma unroll
+    for (int h = 0; h < LHM; ++h) yh[h] = (h < Lh) ? Yh[h * plane + j] : 0.f;
+  }
   if constexpr (PU_NC == 1) {
     // one thread per pixel: the parts are added in registers, and no barrier sits between
     // the two band loops (with one the memory-bound loops of different waves do not overlap)
@@ -815,19 +926,26 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
       float rp[LHM];
 #pragma unroll
       for (int h = 0; h < LHM; ++h) rp[h] = 0.f;
-      pupdate_share<LHM>(X, L2, R, rp, plane, Lh, (L * k) / kPuShares,
-                         (L * (k + 1)) / kPuShares, j);
+      if constexpr (KEEP)
+        pupdate_share_kept<LHM>(xs, l2s, R, rp, Lh, c0, (L * k) / kPuShares,
+                                (L * (k + 1)) / kPuShares);
+      else
+        pupdate_share<LHM>(X, L2, R, rp, plane, Lh, (L * k) / kPuShares,
+                           (L * (k + 1)) / kPuShares, j);
 #pragma unroll
       for (int h = 0; h < LHM; ++h) a[h] += rp[h];
     }
 #pragma unroll
-    for (int h = 0; h < LHM; ++h) res[h] = (h < Lh) ? Yh[h * plane + j] - a[h] : 0.f;
+    for (int h = 0; h < LHM; ++h) res[h] = (h < Lh) ? yh[h] - a[h] : 0.f;
   } else {
     static_assert(PU_NC == kPuShares, "one share per thread");
     float rp[LHM];
 #pragma unroll
     for (int h = 0; h < LHM; ++h) rp[h] = 0.f;
-    if (act) pupdate_share<LHM>(X, L2, R, rp, plane, Lh, c0, c1, j);
+    if (act) {
+      if constexpr (KEEP) pupdate_share_kept<LHM>(xs, l2s, R, rp, Lh, c0, c0, c1);
+      else pupdate_share<LHM>(X, L2, R, rp, plane, Lh, c0, c1, j);
+    }
 #pragma unroll
     for (int h = 0; h < LHM; ++h) part[ch][h][pix] = rp[h];
     __syncthreads();
@@ -837,7 +955,7 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
       float a = 0.f;
 #pragma unroll
       for (int k = 0; k < PU_NC; ++k) a += part[k][h][pix];
-      res[h] = (h < Lh) ? Yh[h * plane + j] - a : 0.f;
+      res[h] = (h < Lh) ? yh[h] - a : 0.f;
     }
   }
   float u[LHM];                           // u = res G
@@ -849,15 +967,17 @@ pupdate_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items,
       if (h < Lh && h2 < Lh) sum += res[h] * G[h * Lh + h2];
     u[h2] = sum;
   }
-  const int i1 = j / q, i2 = j - i1 * q;
-  // p1mode 1: a basis couples the sampled pixels across bands (p1_subspace_kernel);
-  // p1mode 2: fused-S splitting, no P1
-  pupdate_write<LHM>(X, gslot<const gfloat>(S, bx_s), gslot<const gfloat>(S, yl_s),
-                     gslot<const gfloat>(S, l1_s), L2, gslot<gfloat>(S, l1o_s),
-                     gslot<gfloat>(S, l2o_s), gslot<gfloat>(S, w1_s), gslot<gfloat>(S, w2_s),
-                     R, u, plane, (size_t)(p / d) * (q / d),
-                     (size_t)(i1 / d) * (q / d) + i2 / d, (i1 % d == 0) && (i2 % d == 0),
-                     S.fused ? 2 : (S.subspace ? 1 : 0), Lh, S.rho, S.inv_1prho, c0, c1, j);
+  if constexpr (KEEP)
+    pupdate_write_kept<LHM>(xs, l2s, bxs, l1s, yls, gslot<gfloat>(S, l1o_s),
+                            gslot<gfloat>(S, l2o_s), gslot<gfloat>(S, w1_s),
+                            gslot<gfloat>(S, w2_s), R, u, plane, sampled, p1mode, Lh, S.rho,
+                            S.inv_1prho, c0, c1, j);
+  else
+    pupdate_write<LHM>(X, gslot<const gfloat>(S, bx_s), gslot<const gfloat>(S, yl_s),
+                       gslot<const gfloat>(S, l1_s), L2, gslot<gfloat>(S, l1o_s),
+                       gslot<gfloat>(S, l2o_s), gslot<gfloat>(S, w1_s), gslot<gfloat>(S, w2_s),
+                       R, u, plane, lplane, lj, sampled, p1mode, Lh, S.rho, S.inv_1prho, c0, c1,
+                       j);
 }
 
 template <typename Kern, typename... Args>
@@ -1075,8 +1195,14 @@ int launch_conv(const Batch& B, int in, int out, bool transpose, int add1, int a
 template <int LHM, int NC>
 void launch_pu(const Batch& B, const Group& g, int x, int bx, int yl, int yh, int l1, int l2,
                int w1, int w2, int l1o, int l2o, hipStream_t s) {
-  hipLaunchKernelGGL((pupdate_kernel<LHM, NC>), dim3(g.nitems), dim3(256 * NC), 0, s, B.d_desc,
-                     g.d_items, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o);
+  int maxL = 0;
+  for (const auto& P : B.scenes) maxL = std::max(maxL, P->Lx);
+  if (maxL <= kPuKeep * NC)
+    hipLaunchKernelGGL((pupdate_kernel<LHM, NC, true>), dim3(g.nitems), dim3(256 * NC), 0, s,
+                       B.d_desc, g.d_items, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o);
+  else
+    hipLaunchKernelGGL((pupdate_kernel<LHM, NC, false>), dim3(g.nitems), dim3(256 * NC), 0, s,
+                       B.d_desc, g.d_items, x, bx, yl, yh, l1, l2, w1, w2, l1o, l2o);
 }
 
 int launch_pupdate(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1, int w2,

@@ -271,18 +271,27 @@ __global__ void fft_cols_solve(const SceneDesc* __restrict__ sd, const int2* __r
   const int g = threadIdx.x / tpl;
   const int tl = threadIdx.x - g * tpl;
   if (!S.fused) {
+    // 1/den of the line's points is requested before the forward transform, so its latency
+    // overlaps the transform (a line has at most 8 tpl points)
     const gfloat* invden = as_global(S.invden);
     for (int base = 0; base < cb; base += G) {
       const int l = base + g;
       const bool act = (g < G) && (l < cb);
       const int t = act ? tl : tpl;
       float2* line = sh + (act ? l : 0) * p;
-      fft_line<false>(line, S.fp, t, tpl, twl);
       const int col = act ? column(l) : -1;
+      float sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = tl + u * tpl;
+        sv[u] = (col >= 0 && i < p) ? invden[(size_t)i * q + col] : 0.f;
+      }
+      fft_line<false>(line, S.fp, t, tpl, twl);
       if (col >= 0) {
-        for (int i = tl; i < p; i += tpl) {
-          const float s = invden[(size_t)i * q + col];
-          line[i] = cscale(line[i], s);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = tl + u * tpl;
+          if (i < p) line[i] = cscale(line[i], sv[u]);
         }
       }
       __syncthreads();
@@ -452,6 +461,14 @@ int fft_block(int tpl) {
   return b;
 }
 
+// Workgroup size for `lines` lines of tpl threads each: at least fft_block(tpl), and up to
+// 1024 so that all lines of the block are transformed in one round.
+static int lines_block(int tpl, int lines) {
+  int b = fft_block(tpl);
+  while (b < lines * tpl && b < 1024) b *= 2;
+  return b;
+}
+
 int rows_blocks(const Plan& P) {
   return ceil_div(P.prm.p, P.fft.q_lpb) * ((P.Lx + 1) / 2);
 }
@@ -474,6 +491,8 @@ FftShape default_fft_shape(int p, int q, int d_fused) {
   while (f.p_cb * 2 <= std::max(16, unit) &&
          (size_t)(f.p_cb * 2 + 1) * p * sizeof(float2) <= kFftLds)
     f.p_cb *= 2;
+  f.q_bs = fft_block(f.q_tpl);
+  f.p_bs = fft_block(f.p_tpl);
   return f;
 }
 
@@ -550,22 +569,28 @@ int autotune_fft(Plan& P) {
   h.buf[B_C] = d_real;
   h.buf[B_Z] = d_real;
   h.buf[B_F] = d_cplx;
+  // best of three runs of 5 launches each (single runs flip between near-equal candidates)
   auto time_it = [&](auto launch) -> float {
     launch();
-    hipEventRecord(e0, nullptr);
-    for (int r = 0; r < 5; ++r) launch();
-    hipEventRecord(e1, nullptr);
-    hipEventSynchronize(e1);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    return ms;
+    float best_ms = 1e30f;
+    for (int trial = 0; trial < 3; ++trial) {
+      hipEventRecord(e0, nullptr);
+      for (int r = 0; r < 5; ++r) launch();
+      hipEventRecord(e1, nullptr);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      best_ms = std::min(best_ms, ms);
+    }
+    return best_ms;
   };
-  // rows
+  // rows: lines per block from 1 up to what LDS holds, on a workgroup of lines_block threads
   {
-    const int tpl = best.q_tpl, bs = fft_block(tpl);
+    const int tpl = best.q_tpl;
     float tbest = 1e30f;
-    for (int lpb = 1; lpb <= bs / tpl; lpb *= 2) {
+    for (int lpb = 1; lpb * tpl <= 1024; lpb *= 2) {
       if ((size_t)(lpb + 1) * q * sizeof(float2) > kFftLds) break;
+      const int bs = lines_block(tpl, lpb);
       h.fq_tpl = tpl;
       h.fq_lpb = lpb;
       hipMemcpy(d_sd, &h, sizeof(SceneDesc), hipMemcpyHostToDevice);
@@ -578,15 +603,16 @@ int autotune_fft(Plan& P) {
                            (int)B_Z, -1);
       });
       if (hipGetLastError() != hipSuccess) { rc = NLPR_ERR_HIP; break; }
-      if (ms < tbest) { tbest = ms; best.q_lpb = lpb; }
+      if (ms < tbest) { tbest = ms; best.q_lpb = lpb; best.q_bs = bs; }
     }
   }
-  // columns
+  // columns: the same over columns per block
   if (rc == NLPR_OK) {
-    const int tpl = best.p_tpl, bs = fft_block(tpl);
+    const int tpl = best.p_tpl;
     float tbest = 1e30f;
     for (int cb = std::max(dfu, 1); cb <= std::max(32, dfu); cb *= 2) {
       if ((size_t)(cb + 1) * p * sizeof(float2) > kFftLds) break;
+      const int bs = lines_block(tpl, cb);
       h.fp_tpl = tpl;
       h.fp_cb = cb;
       hipMemcpy(d_sd, &h, sizeof(SceneDesc), hipMemcpyHostToDevice);
@@ -597,7 +623,7 @@ int autotune_fft(Plan& P) {
                            (int)B_F);
       });
       if (hipGetLastError() != hipSuccess) { rc = NLPR_ERR_HIP; break; }
-      if (ms < tbest) { tbest = ms; best.p_cb = cb; }
+      if (ms < tbest) { tbest = ms; best.p_cb = cb; best.p_bs = bs; }
     }
   }
   cleanup();

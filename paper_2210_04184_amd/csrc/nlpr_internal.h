@@ -100,6 +100,12 @@ struct SceneDesc {
 };
 
 constexpr int kSweepThreads = 256;   // workgroup size of the sweep
+// Batches of at least this many pixel-bands (summed over scenes) run the P-side of each
+// iteration on a second stream, concurrently with the sweep.  Below it the two cross-stream
+// waits of an iteration (about 6 and 11 us on MI355X) and the sweep's hold on the CUs cost
+// more than the overlap gains (256 x 256 x 31: 2.77 -> 2.90 ms per solve; 512 x 512 x 128:
+// 3.03 -> 2.98 s).
+constexpr size_t kForkPixelBands = (size_t)1 << 22;
 // open-item counters of one sweep launch (timing plans): kCountSlots, kCountStride apart
 constexpr int kCountSlots = 64;
 constexpr int kCountStride = 16;
@@ -114,8 +120,8 @@ struct SweepShape {
 };
 
 struct FftShape {
-  int q_tpl, q_lpb;   // row passes: threads per line, lines per block
-  int p_tpl, p_cb;    // column pass: threads per line, columns per block
+  int q_tpl, q_lpb, q_bs;   // row passes: threads per line, lines per block, block size
+  int p_tpl, p_cb, p_bs;    // column pass: threads per line, columns per block, block size
 };
 
 // One scene: parameters, device tables and its part of the workspace.
@@ -176,6 +182,11 @@ struct Batch {
   int monitor_every = 0;           // shared by every scene
   int mon_last = 0;                // monitor records written by the last solve
   hipEvent_t done_ev = nullptr;    // recorded after each solve
+  // second stream of the iteration (large batches only): the P-side (blur, P-update and the
+  // part of the right-hand side that does not wait for the sweep) runs on it while the sweep
+  // runs on the solve's stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::vector<Plan*> scenes;       // owned
   std::vector<size_t> base;        // workspace base of each scene
   size_t ws_bytes = 0;
