@@ -162,12 +162,50 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   };
   if (!FIRST && n_begin < n_end) load_codes(tile_off + (size_t)n_begin * tstride);
 
+  // thresholds mu(., tau) of the tile rows and their K halo, (R + 2K) q4 float4s per shift.
+  // When they fit MUR per thread their offsets in a mu plane are computed once (no integer
+  // division per shift), and for patches of at most 3 x 3 they are requested one shift ahead
+  // into registers, so their latency hides behind the previous shift (at 5 x 5 the extra
+  // registers would cost a wave per SIMD).
+  constexpr int MUR = K <= 1 ? 2 : 3;
+  constexpr bool MU_AHEAD = K <= 1;
+  const int mu_n4 = (R + 2 * K) * q4;
+  const bool mu_hoist = mu_n4 <= MUR * NT;
+  int mu_off[MUR];
+  float4 mv[MU_AHEAD ? MUR : 1];
+#pragma unroll
+  for (int u = 0; u < MUR; ++u) {
+    const int e = threadIdx.x + u * NT;
+    const int rr = e / q4, c4 = e - rr * q4;
+    int gr = (r0 - K + rr) % p;
+    if (gr < 0) gr += p;
+    mu_off[u] = e < mu_n4 ? gr * q + 4 * c4 : -1;
+  }
+  auto mu_fetch = [&](int n) {
+    const gfloat* mun = mu + (size_t)n * plane;
+#pragma unroll
+    for (int u = 0; u < MUR; ++u)
+      if (mu_off[u] >= 0) mv[MU_AHEAD ? u : 0] = ldg4(mun + mu_off[u]);
+  };
+  if (MU_AHEAD && mu_hoist && n_begin < n_end) mu_fetch(n_begin);
+
   for (int n = n_begin; n < n_end; ++n) {
     const int2 t = tau_at(S, n);
     __syncthreads();  // the previous shift's reads of Ms and updates of Cs are done
-    {
+    if (MU_AHEAD && mu_hoist) {
+#pragma unroll
+      for (int u = 0; u < MUR; ++u)
+        if (mu_off[u] >= 0) reinterpret_cast<float4*>(Ms)[threadIdx.x + u * NT] = mv[u];
+      if (n + 1 < n_end) mu_fetch(n + 1);
+    } else if (mu_hoist) {
       const gfloat* mun = mu + (size_t)n * plane;
-      for (int e = threadIdx.x; e < (R + 2 * K) * q4; e += NT) {
+#pragma unroll
+      for (int u = 0; u < MUR; ++u)
+        if (mu_off[u] >= 0)
+          reinterpret_cast<float4*>(Ms)[threadIdx.x + u * NT] = ldg4(mun + mu_off[u]);
+    } else {
+      const gfloat* mun = mu + (size_t)n * plane;
+      for (int e = threadIdx.x; e < mu_n4; e += NT) {
         const int rr = e / q4, c4 = e - rr * q4;
         int gr = (r0 - K + rr) % p;
         if (gr < 0) gr += p;
@@ -286,11 +324,16 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
             A[m].w += acc[3];
           }
           const bool opn = ok[m] && (code & 0x55u) != 0x55u;
-          const unsigned long long bal = __builtin_amdgcn_ballot_w64(opn);
-          const unsigned slot = __builtin_amdgcn_mbcnt_hi(
-              (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-          open_written += (unsigned)__builtin_popcountll(bal);
-          if (opn) st_nt(vb + (seg[m] + 4u * slot), make_float4(nv[0], nv[1], nv[2], nv[3]));
+          if (opn) {
+            // inside the branch the execution mask is the ballot of the open lanes (every
+            // lane of the wave reaches this point)
+            const unsigned long long bal = __builtin_amdgcn_read_exec();
+            const unsigned slot = __builtin_amdgcn_mbcnt_hi(
+                (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            st_nt(vb + (seg[m] + 4u * slot), make_float4(nv[0], nv[1], nv[2], nv[3]));
+          }
+          if (count)
+            open_written += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(opn));
           if (ok[m]) {
             __builtin_nontemporal_store((uint8_t)code, cbp + (threadIdx.x + NT * m));
             if (CODES) ((gu8*)codes)[(pl_off >> 2) + threadIdx.x + NT * m] = (uint8_t)branch;
