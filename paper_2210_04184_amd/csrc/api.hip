@@ -377,6 +377,21 @@ void batch_release(Batch& B) {
   B.graph = nullptr;
 }
 
+// Work items in the order that gives each XCD a contiguous range of them.  The workgroups
+// of a launch go to the 8 XCDs round-robin by workgroup index, each XCD with its own L2, so
+// workgroup b runs item start(b % 8) + b / 8, where XCD x owns the next N/8 (+1 for the first
+// N mod 8) items.  Neighbouring tiles of one band, whose halos overlap, then share an L2.
+std::vector<int2> xcd_order(const std::vector<int2>& items) {
+  constexpr int kXcds = 8;
+  const int n = (int)items.size(), q = n / kXcds, r = n % kXcds;
+  std::vector<int2> out(n);
+  for (int b = 0; b < n; ++b) {
+    const int x = b % kXcds, s = b / kXcds;
+    out[b] = items[x * q + std::min(x, r) + s];
+  }
+  return out;
+}
+
 int add_group(Batch& B, Kind kind, const std::vector<int2>& items, int block, size_t lds, int k0,
               int k1) {
   Group g;
@@ -437,7 +452,7 @@ int batch_build(Batch& B) {
       for (int i = 0; i < c; ++i) it.push_back(make_int2(s, i));
       l = std::max(l, conv_lds(P));
     }
-    if (!it.empty() && (rc = add_group(B, KD_CONV, it, 256, l, cls, 0))) return rc;
+    if (!it.empty() && (rc = add_group(B, KD_CONV, xcd_order(it), 256, l, cls, 0))) return rc;
   }
   // per-pixel launches by guide-band class (key0); key1 = threads per pixel, 4 (bands of a
   // pixel split) when the launch covers few pixels in all, else 1
