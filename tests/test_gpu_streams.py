@@ -46,3 +46,34 @@ def test_solves_and_forward_passes_on_two_streams():
         assert torch.equal(Zf, Zb_ref)
     finally:
         plan.close()
+
+
+def test_side_stream_overlap_is_bit_identical():
+    """A scene of 2^22 pixel-bands runs blur, P-update and B^T W1 + W2 of each iteration on a
+    second stream while the sweep runs; a plan with stage timers keeps one stream.  Both
+    give the same bits (the assembly adds the same terms in the same order), also through a
+    captured graph, on the caller's own stream."""
+    spec = synth.small_spec(p=128, q=128, L=256, Lh=2, d=4, blur_radius=3, K=1, Sw=2, iters=4,
+                            seed=43)
+    sc = synth.make_scene(spec)
+    print("[streams] 128x128x256 (2^22 pixel-bands), side stream against one stream", flush=True)
+    Yl, Yh = dev(sc.Yl), dev(sc.Yh)
+    out = {}
+    for name, flags in (("one stream", nlpr.TIMING), ("side stream", 0),
+                        ("graph", nlpr.GRAPH)):
+        plan = nlpr.Plan.from_scene(sc, flags=flags)
+        try:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            Z, ws = plan.solve(Yl, Yh, stream=s)
+            torch.cuda.synchronize()
+            out[name] = (Z.clone(), plan.region_view(ws, nlpr.REGION_C).clone(),
+                         plan.region_view(ws, nlpr.REGION_LAMBDA2).clone())
+            del Z, ws
+        finally:
+            plan.close()
+    ref = out["one stream"]
+    assert bool(torch.isfinite(ref[0]).all())
+    for name in ("side stream", "graph"):
+        for a, b in zip(out[name], ref):
+            assert torch.equal(a, b), name
