@@ -26,7 +26,9 @@
  *     buffer it passes; the library never frees them.
  *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).
  *     Work is enqueued asynchronously; completion is observed by synchronising the
- *     stream.
+ *     stream.  Plans and batches of at least 2^22 pixel-bands (without NLPR_TIMING) run
+ *     part of each iteration on a second stream of their own, forked from `stream` and
+ *     joined back into it within the call, so `stream` still orders all of the call's work.
  *   - Every function returns an nlpr_status.  No C++ exception crosses the ABI.  On error
  *     nlpr_last_error() returns a message for the calling thread.
  *   - Functions are thread-safe for distinct plans.  Host calls that share a plan must not

@@ -387,9 +387,9 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
 // Tiles and launch shapes.  A tile is 1024 * items pixels (items = 1, 2 or 4: the fewest with
 // one full image row per tile), i.e. 256 * items float4 items, on a workgroup of 256 threads
 // with `items` items each; the layout of Sigma' and of its codes depends on the tile only
-// (segments of 64 items).  For 3 x 3 patches at 256 x 256 x 31 this shape is faster than 128
-// threads with two items each (89 against 154 VGPRs: five waves per SIMD instead of three;
-// 20-iteration solve 2.88 against 3.16 ms).
+// (segments of 64 items).  For 3 x 3 patches at 256 x 256 x 31 this shape was faster than
+// 128 threads with two items each (89 against 154 VGPRs at the time: five waves per SIMD
+// instead of three; 20-iteration solve 2.88 against 3.16 ms).
 
 template <int K, int ITEMS, int NT, bool FIRST, bool CODES>
 int launch_k(const Batch& B, const Group& g, int x, int mu, int sig, int creg, int halo,
