@@ -795,7 +795,7 @@ int batch_solve(Batch& B, const float* const* Yl, const float* const* Yh, float*
   NLPR_HIP_TRY(hipEventRecord(B.done_ev, s));
   B.mon_last = monitor_points(B.iters, B.monitor_every);
   if (B.flags & NLPR_CHECK_FINITE) {
-    // the checks ran inside the solve without waiting; read their verdict once
+    // the checks ran inside the solve without waiting; read their flag once
     int hflag = 0;
     NLPR_HIP_TRY(hipMemcpyAsync(&hflag, B.d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     NLPR_HIP_TRY(hipStreamSynchronize(s));

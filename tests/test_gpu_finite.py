@@ -1,6 +1,6 @@
 """The device-side NaN/Inf check (NLPR_CHECK_FINITE): the iterate is checked on the device
 after every 8th iteration and after the last one, without waiting; the solve reads the
-verdict once at the end and reports the first checked iteration that found a non-finite
+flag once at the end and reports the first checked iteration that found a non-finite
 value.  The fault is planted from the host: one NaN written into the Lambda2 of a stored
 state, which a resumed solve (NLPR_STATE_IN) then carries into every pixel of X."""
 import numpy as np
