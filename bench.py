@@ -155,13 +155,24 @@ def host_cores() -> int:
     return max(1, min(n, 16))
 
 
-def cpu_model() -> str:
+def cpu_model() -> dict:
+    """Model name, family / model / stepping numbers and clock of the first host CPU, as
+    /proc/cpuinfo gives them (a virtual machine may shorten the name)."""
+    keys = {"model name": "cpu", "cpu family": "family", "model": "model",
+            "stepping": "stepping", "cpu MHz": "mhz"}
+    out = {}
     try:
         with open("/proc/cpuinfo") as f:
-            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
-                        "")
+            for ln in f:
+                if not ln.strip():
+                    break                       # first processor only
+                k, _, v = ln.partition(":")
+                k = k.strip()
+                if k in keys:
+                    out[keys[k]] = v.strip()
     except OSError:
-        return ""
+        pass
+    return out
 
 
 def cpu_baseline(seconds_target: float = 12.0):
@@ -204,7 +215,7 @@ def cpu_baseline(seconds_target: float = 12.0):
     pb = spec.p * spec.q * spec.L
     return {"value": pb * it_n / dt_n, "unit": "pixel*band*iter/s", "cores": cores,
             "kind": "oracle",
-            "host": {"cpu": cpu_model(), "cpu_count": os.cpu_count(), "cores_used": cores},
+            "host": {**cpu_model(), "cpu_count": os.cpu_count(), "cores_used": cores},
             "one_thread_value": pb * it_1 / dt_1,
             "sample": f"literal FP64 oracle, 32x32x128 bands, Lh=4, 9x9 blur, d=4, patch 5x5, "
                       f"window 11x11: {it_n} iterations incl. weights/setup in {dt_n:.1f} s on "
