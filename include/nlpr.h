@@ -282,9 +282,10 @@ typedef enum nlpr_region {
   NLPR_REGION_LAMBDA1 = 3,/* Lambda1 [L][p][q]                                                       */
   NLPR_REGION_LAMBDA2 = 4,/* Lambda2 [L][p][q]                                                       */
   NLPR_REGION_SIGMA_CODES = 5, /* one byte per item of NLPR_REGION_SIGMA (byte index = float
-                             offset of the item / 4), bits (2e, 2e+1) for element e: bit 2e set
-                             if |V| >= mu (the element is on the threshold), bit 2e+1 set if
-                             V < 0 (its value is then +mu, else -mu)                          */
+                             offset of the item / 4); for element e, bit e is the sign bit
+                             of V (set: an element on the threshold holds +mu, else -mu) and
+                             bit 4 + e is set if |V| < mu (off the threshold); an item whose
+                             byte is below 16 is on the threshold in all four elements     */
   NLPR_REGION_COUNT = 6
 } nlpr_region;
 int nlpr_workspace_region(const nlpr_plan* plan, int region, size_t* offset, size_t* bytes);

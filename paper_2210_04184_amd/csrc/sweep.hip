@@ -43,6 +43,8 @@ namespace {
 #ifndef NLPR_SWEEP_NT
 #define NLPR_SWEEP_NT 1
 #endif
+// cache policy of a buffer access: non-temporal
+constexpr int kCacheNT = 2;
 __device__ __forceinline__ float4 ld_nt(const gfloat* p) {
 #if NLPR_SWEEP_NT
   const v4f_t v = __builtin_nontemporal_load((const gv4f*)p);
@@ -65,11 +67,14 @@ __device__ __forceinline__ float clampf(float v, float m) { return fminf(fmaxf(v
 // Storage of Sigma' (coded).  Every new dual value is -clip(V, +-mu), so an element that
 // reached the threshold (|V| >= mu) holds exactly -mu (V > 0) or +mu (V < 0): its value
 // follows from the threshold, which the sweep has at hand, and one sign bit.  Per float4
-// item of a plane the state keeps a code byte, bits (2e, 2e+1) for element e:
-//   bit 2e   on: |V| >= mu (false for a NaN), the value is -mu or +mu;
-//   bit 2e+1 the sign of V (V < 0: the value is +mu).
-// An item with any element off the threshold is "open": its four values are stored as a
-// float4, as clip(V, +-mu) = -Sigma' (so the next sweep adds them: V = g - Sigma').  Open items are packed per wave: the 64 items a wave owns in a plane (one 1 KB
+// item of a plane the state keeps a code byte, for element e:
+//   bit e     the sign bit of V (set: the value is +mu when on the threshold, else -mu);
+//   bit 4 + e off the threshold: the sign bit of |V| - mu, i.e. |V| < mu (a NaN V gives a
+//             NaN with the sign of |V|, so it counts as on; the NaN reaches C through A).
+// The bits are shifted in one at a time with alignbit.  An item with any element off the
+// threshold (byte >= 16) is "open": its four values are stored as a float4, as
+// clip(V, +-mu) = -Sigma' (so the next sweep adds them: V = g - Sigma').  Open items are
+// packed per wave: the 64 items a wave owns in a plane (one 1 KB
 // segment of the plane) keep the float4s of their open items at the start of that segment,
 // in lane order, so a wave reads and writes only as many 16-byte slots as it has open
 // items (mbcnt of the ballot gives each open lane its slot).  A wave reads its whole old
@@ -160,7 +165,83 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
         cbn[k2][m] = __builtin_nontemporal_load(cbp + (threadIdx.x + NT * m));
     }
   };
-  if (!FIRST && n_begin < n_end) load_codes(tile_off + (size_t)n_begin * tstride);
+  // the open items' float4s of a patch row, from the waves' packed runs: a wave with open
+  // items loads on every lane (lanes past the tile from the start of the segment): the closed
+  // lanes' slots lie inside the open run, so no extra line is read and no lane branches
+  auto load_open = [&](size_t row_off, const unsigned (&cbx)[KW][ITEMS],
+                       float4 (&sx)[KW][ITEMS]) {
+#pragma unroll
+    for (int k2 = 0; k2 < KW; ++k2) {
+      const gfloat* vb = sig + row_off + (size_t)k2 * kstride;
+#pragma unroll
+      for (int m = 0; m < ITEMS; ++m) {
+        const bool open = ok[m] && cbx[k2][m] >= 16u;
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(open);
+        const unsigned slot = __builtin_amdgcn_mbcnt_hi(
+            (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+        if (bal) sx[k2][m] = ld_nt(vb + (seg[m] + 4u * (ok[m] ? slot : 0u)));
+      }
+    }
+  };
+
+  // the shifts of this workgroup, one per lane, 64 at a time, packed as (tau1 << 16 | tau2):
+  // read before the planes' requests, since a load inside the shift loop would wait for
+  // every request issued before it
+  int tau_lane = 0;
+  auto tau_fetch = [&](int n0) {
+    const int j = n0 + (int)(threadIdx.x & 63);
+    const int2 tj = j < n_end ? tau_at(S, j) : make_int2(0, 0);
+    tau_lane = (tj.x << 16) | (tj.y & 0xffff);
+  };
+  tau_fetch(n_begin);
+
+  // With one item per thread the planes are software-pipelined.  The planes of a workgroup
+  // form one contiguous sequence over its shifts (plane x at base + x kstride); while plane x
+  // is updated, the open float4s of plane x + D and the code bytes of plane x + D + E are in
+  // flight.  These requests are issued on every path (a wave with no open item reads the
+  // start of its segment; past the last plane the last plane is read again, unused), so the
+  // number of memory operations after each is fixed and the wait for plane x leaves the later
+  // ones in flight.  A plane is read only before it is written: its own requests come D and
+  // D + E planes earlier, repeats of the last plane up to its own update.
+  constexpr bool PIPE = !FIRST && ITEMS == 1;
+  constexpr int D = K <= 1 ? 6 : 5, E = D;
+  const int nplanes = (n_end - n_begin) * NP;
+  const size_t base = tile_off + (size_t)n_begin * tstride;
+  unsigned cq[D + E + 1];  // code bytes of planes x .. x + D + E
+  float4 sb[D + 1];        // open float4s of planes x .. x + D
+  // the workgroup's code bytes as one buffer, plane x at byte x * cstride: a lane's byte is
+  // addressed by the plane offset (a scalar) and the thread index, with no vector arithmetic
+  // (accesses past the range would be dropped)
+  const unsigned cstride = (unsigned)(kstride >> 2);
+  const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(uint8_t*)(scode + (base >> 2)), (short)0, PIPE ? nplanes * (int)cstride : 0,
+      0x00020000);
+  auto pipe_codes = [&](int x) -> unsigned {
+    return __builtin_amdgcn_raw_buffer_load_b8(crs, threadIdx.x, min(x, nplanes - 1) * cstride,
+                                               kCacheNT);
+  };
+  // the ballot of a plain comparison is one instruction: the lanes past the tile are cleared
+  // with a mask taken once; each lane without an open item reads the slot after the open
+  // lanes below it, inside the segment
+  const unsigned long long okmask = __builtin_amdgcn_ballot_w64(ok[0]);
+  const unsigned segb = 4u * (unsigned)seg[0];  // byte offset of the wave's segment
+  auto pipe_open = [&](int x, unsigned cx) -> float4 {
+    const gfloat* pb = sig + base + (size_t)min(x, nplanes - 1) * kstride;
+    const unsigned long long bal = __builtin_amdgcn_ballot_w64(cx >= 16u) & okmask;
+    const unsigned slot = __builtin_amdgcn_mbcnt_hi(
+        (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+    return ld_nt((const gfloat*)((const gu8*)pb + (segb + 16u * slot)));
+  };
+  if constexpr (PIPE) {
+    if (nplanes > 0) {
+#pragma unroll
+      for (int i = 0; i < D + E; ++i) cq[i] = pipe_codes(i);
+#pragma unroll
+      for (int i = 0; i < D; ++i) sb[i] = pipe_open(i, cq[i]);
+    }
+  } else if (!FIRST && n_begin < n_end) {
+    load_codes(tile_off + (size_t)n_begin * tstride);
+  }
 
   // thresholds mu(., tau) of the tile rows and their K halo, (R + 2K) q4 float4s per shift.
   // When they fit MUR per thread their offsets in a mu plane are computed once (no integer
@@ -190,7 +271,9 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   if (MU_AHEAD && mu_hoist && n_begin < n_end) mu_fetch(n_begin);
 
   for (int n = n_begin; n < n_end; ++n) {
-    const int2 t = tau_at(S, n);
+    if (n > n_begin && ((n - n_begin) & 63) == 0) tau_fetch(n);
+    const int tpk = __builtin_amdgcn_readlane(tau_lane, (n - n_begin) & 63);
+    const int2 t = make_int2(tpk >> 16, (int)(short)(tpk & 0xffff));
     __syncthreads();  // the previous shift's reads of Ms and updates of Cs are done
     if (MU_AHEAD && mu_hoist) {
 #pragma unroll
@@ -198,11 +281,15 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
         if (mu_off[u] >= 0) reinterpret_cast<float4*>(Ms)[threadIdx.x + u * NT] = mv[u];
       if (n + 1 < n_end) mu_fetch(n + 1);
     } else if (mu_hoist) {
+      // all of a thread's requests first (lanes without a float4 read the plane's first),
+      // then the stores: one wait per shift
       const gfloat* mun = mu + (size_t)n * plane;
+      float4 mt[MUR];
+#pragma unroll
+      for (int u = 0; u < MUR; ++u) mt[u] = ldg4(mun + max(mu_off[u], 0));
 #pragma unroll
       for (int u = 0; u < MUR; ++u)
-        if (mu_off[u] >= 0)
-          reinterpret_cast<float4*>(Ms)[threadIdx.x + u * NT] = ldg4(mun + mu_off[u]);
+        if (mu_off[u] >= 0) reinterpret_cast<float4*>(Ms)[threadIdx.x + u * NT] = mt[u];
     } else {
       const gfloat* mun = mu + (size_t)n * plane;
       for (int e = threadIdx.x; e < mu_n4; e += NT) {
@@ -247,35 +334,19 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
         mw[m][8] = d.x; mw[m][9] = d.y; mw[m][10] = d.z; mw[m][11] = d.w;
       }
       const size_t row_off = n_off + (size_t)((k1 + K) * KW) * kstride;
-      // the old state of this patch row's planes: the code bytes (loaded with the previous
-      // row), then the open items' float4s from the waves' packed runs.  The next row's code
-      // bytes (or the next shift's first row) are requested before this row's values.
+      // without the pipeline (several items per thread), the old state of this patch row's
+      // planes: the code bytes (loaded with the previous row), then the open items' float4s
+      // from the waves' packed runs; the next row's code bytes (or the next shift's first
+      // row) are requested before this row's values
       unsigned cb[KW][ITEMS];
       float4 s[KW][ITEMS];
-      if (!FIRST) {
+      if (!FIRST && !PIPE) {
 #pragma unroll
         for (int k2 = 0; k2 < KW; ++k2)
 #pragma unroll
           for (int m = 0; m < ITEMS; ++m) cb[k2][m] = cbn[k2][m];
-        if (k1 < K)
-          load_codes(row_off + (size_t)KW * kstride);
-        else if (n + 1 < n_end)
-          load_codes(n_off + tstride);
-#pragma unroll
-        for (int k2 = 0; k2 < KW; ++k2) {
-          const gfloat* vb = sig + row_off + (size_t)k2 * kstride;
-#pragma unroll
-          for (int m = 0; m < ITEMS; ++m) {
-            const bool open = ok[m] && (cb[k2][m] & 0x55u) != 0x55u;
-            const unsigned long long bal = __builtin_amdgcn_ballot_w64(open);
-            const unsigned slot = __builtin_amdgcn_mbcnt_hi(
-                (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-            // a wave with open items loads on every lane (lanes past the tile from the start
-            // of the segment): the closed lanes' slots lie inside the open run, so no extra
-            // line is read and no lane branches
-            if (bal) s[k2][m] = ld_nt(vb + (seg[m] + 4u * (ok[m] ? slot : 0u)));
-          }
-        }
+        if (k1 < K || n + 1 < n_end) load_codes(row_off + (size_t)KW * kstride);
+        load_open(row_off, cb, s);
       }
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
@@ -287,43 +358,66 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
           const int o = 4 + (k2 - K);  // window index of column col + (k2 - K)
           const float mu4[4] = {mw[m][o + 0], mw[m][o + 1], mw[m][o + 2], mw[m][o + 3]};
           float sv[4];
+          unsigned cbv = 0;  // this plane's old code byte and open float4
+          float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+          const int x = (n - n_begin) * NP + (k1 + K) * KW + k2;  // plane of the workgroup
+          if constexpr (PIPE) {
+            cq[D + E] = pipe_codes(x + D + E);
+            sb[D] = pipe_open(x + D, cq[D]);
+            cbv = cq[0];
+            s4 = sb[0];
+#pragma unroll
+            for (int i = 0; i < D + E; ++i) cq[i] = cq[i + 1];
+#pragma unroll
+            for (int i = 0; i < D; ++i) sb[i] = sb[i + 1];
+          } else if (!FIRST) {
+            cbv = cb[k2][m];
+            s4 = s[k2][m];
+          }
           if (FIRST) {
             sv[0] = sv[1] = sv[2] = sv[3] = 0.f;
           } else {
             // sv = -Sigma' = clip(V_old, +-mu): the stored value, or on the threshold mu with
-            // the sign of V_old (bit 2e+1), i.e. mu's magnitude under that sign bit
-            const bool open = ok[m] && (cb[k2][m] & 0x55u) != 0x55u;
-            const float st[4] = {s[k2][m].x, s[k2][m].y, s[k2][m].z, s[k2][m].w};
+            // the sign of V_old (bit e), i.e. mu's magnitude under that sign bit
+            const bool open = ok[m] && cbv >= 16u;
+            const float st[4] = {s4.x, s4.y, s4.z, s4.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const float on = __uint_as_float(__builtin_amdgcn_ubfe(cb[k2][m], 2 * e + 1, 1) << 31 |
-                                               __float_as_uint(mu4[e]));
+              const float on = __uint_as_float((cbv >> e) << 31 | __float_as_uint(mu4[e]));
               sv[e] = open ? st[e] : on;
             }
           }
           const float gv[4] = {g[m].x, g[m].y, g[m].z, g[m].w};
           float nv[4], acc[4];
           unsigned code = 0, branch = 0;
+          float vv[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const float v = gv[e] + sv[e];
             const float cl = __builtin_amdgcn_fmed3f(v, -mu4[e], mu4[e]);
+            vv[e] = v;
             acc[e] = __builtin_fmaf(-2.f, cl, v);
             nv[e] = cl;
-            code |= (fabsf(v) >= mu4[e] ? 1u : 0u) << (2 * e);
-            code |= (__float_as_uint(v) >> 31) << (2 * e + 1);
             if (CODES) {
               const unsigned bc = fabsf(v) < mu4[e] ? 0u : (v > 0.f ? 1u : (v < 0.f ? 2u : 3u));
               branch |= bc << (2 * e);
             }
           }
+          // the code byte, shifted in one bit at a time (alignbit(c, x, 31) = c << 1 | x >> 31):
+          // the off flags (sign bits of |V| - mu) of elements 3..0, then the signs of V
+#pragma unroll
+          for (int e = 3; e >= 0; --e)
+            code = __builtin_amdgcn_alignbit(code, __float_as_uint(fabsf(vv[e]) - mu4[e]), 31);
+#pragma unroll
+          for (int e = 3; e >= 0; --e)
+            code = __builtin_amdgcn_alignbit(code, __float_as_uint(vv[e]), 31);
           if (ok[m]) {
             A[m].x += acc[0];
             A[m].y += acc[1];
             A[m].z += acc[2];
             A[m].w += acc[3];
           }
-          const bool opn = ok[m] && (code & 0x55u) != 0x55u;
+          const bool opn = ok[m] && code >= 16u;
           if (opn) {
             // inside the branch the execution mask is the ballot of the open lanes (every
             // lane of the wave reaches this point)
@@ -335,7 +429,11 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
           if (count)
             open_written += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(opn));
           if (ok[m]) {
-            __builtin_nontemporal_store((uint8_t)code, cbp + (threadIdx.x + NT * m));
+            if constexpr (PIPE)
+              __builtin_amdgcn_raw_buffer_store_b8((uint8_t)code, crs, threadIdx.x, x * cstride,
+                                                   kCacheNT);
+            else
+              __builtin_nontemporal_store((uint8_t)code, cbp + (threadIdx.x + NT * m));
             if (CODES) ((gu8*)codes)[(pl_off >> 2) + threadIdx.x + NT * m] = (uint8_t)branch;
           }
         }
@@ -541,8 +639,8 @@ sigma_expand_kernel(const SceneDesc* __restrict__ sd, const gfloat* __restrict__
   const bool ok = live && row < rows;
   const size_t pl_off = (((size_t)(c0 + cl) * ntiles + tile) * npairs + n) * npatch * ((size_t)R * q) +
                         (size_t)k * R * q;
-  const unsigned cb = ok ? scode[(pl_off >> 2) + it] : 0x55u;
-  const bool open = ok && (cb & 0x55u) != 0x55u;
+  const unsigned cb = ok ? scode[(pl_off >> 2) + it] : 0u;
+  const bool open = ok && cb >= 16u;
   const unsigned long long bal = __builtin_amdgcn_ballot_w64(open);
   const unsigned slot = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
@@ -557,7 +655,7 @@ sigma_expand_kernel(const SceneDesc* __restrict__ sd, const gfloat* __restrict__
     const gfloat* mun = mu + (size_t)n * p * q + (size_t)mr * q;
     for (int e = 0; e < 4; ++e) {
       const float m = mun[(col + e + k2 + q) % q];
-      v[e] = (cb >> (2 * e + 1)) & 1u ? m : -m;
+      v[e] = (cb >> e) & 1u ? m : -m;
     }
   }
   const size_t o = ((((size_t)cl * npairs + n) * npatch + k) * p + (r0 + row)) * q + col;
