@@ -83,12 +83,24 @@ __device__ __forceinline__ void block_sum256(double (&v)[N]) {
 //   A'(j) = 2 (C'(j) - C'(j - tau));  per k: c' = -Sigma''(j) - 2 A'(j);
 //   V' = A'(j) + [|V| < mu] c';  mu'(j + k) += [V >= mu] c' - [V <= -mu] c';
 //   Sigma''(j) := -V';  g'(j) = sum_k V';  X'(j) += g'(j),  X'(j - tau) -= g'(j).
-// Without X, mu and Sigma' the kernel needs 96 VGPRs at K = 1 (five workgroups per CU);
-// holding it to 80 or 64 (six or eight per CU, with spills) made the reverse pass slower.
-template <int K>
+// Coded Sigma'': outside the threshold the new Sigma''(j) = -(A'(j) + 0) depends on the shift
+// and the pixel only, so a float4 item is stored only if one of its elements is inside
+// (branch 0), packed per wave segment as the forward's open items (ballot and mbcnt give the
+// slots).  The next backward step, which has the branch codes of this step (pcodes) and this
+// step's C' (cbp_s), rebuilds the others with the same operations, so the values are exact.
+// FIRST: the first backward step, whose incoming Sigma'' is zero.
+// The planes of a workgroup are software-pipelined as in the forward sweep: the codes of this
+// step and Sigma'' of plane x + D, and the codes of the previous step of plane x + D + E
+// (which place the packed float4s), are in flight while plane x is updated.  The requests
+// are issued on every path (lanes past the tile read the plane's first item, a wave with no
+// stored item the start of its segment, and past the last plane the last plane again,
+// unused), so each wait leaves the later requests in flight.  A plane is read before it is
+// written.
+template <int K, bool FIRST>
 __global__ void __launch_bounds__(256)
 sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int cb_s,
-                 const uint8_t* codes, int sb_s, int xr_s, int halo_s, int mup_s) {
+                 const uint8_t* codes, int sb_s, int xr_s, int halo_s, int mup_s,
+                 const uint8_t* pcodes, int cbp_s) {
   constexpr int NT = 256;
   constexpr int KW = 2 * K + 1;
   constexpr int NP = KW * KW;
@@ -98,6 +110,7 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
             H = S.halo;
   const gfloat* Cb = gslot<const gfloat>(S, cb_s);
   const gu8* cod = (const gu8*)codes;
+  const gu8* pcod = (const gu8*)pcodes;
   gfloat* sb = gslot<gfloat>(S, sb_s);
   gfloat* mup = gslot<gfloat>(S, mup_s);
   extern __shared__ float4 lds4[];
@@ -108,6 +121,7 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
   float* Mb = lds;                        // ER x ms   mu' accumulator
   float* Cs = Mb + ER * ms;               // (R + H) x q   C'
   float* As = Cs + (R + H) * q;           // (R + H) x q   X' accumulator
+  float* Cps = As + (R + H) * q;          // (R + H) x q   C' of the previous step (not FIRST)
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
 
   // the forward sweep's work items, y = (tile * psplit + part) * L + band; the adjoint covers
@@ -120,11 +134,13 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
   const int rows = min(R, p - r0);
   const size_t plane = (size_t)p * q;
   const gfloat* Cc = Cb + (size_t)c * plane;
+  const gfloat* Cpc = FIRST ? Cc : gslot<const gfloat>(S, cbp_s) + (size_t)c * plane;
   for (int e = threadIdx.x; e < (R + H) * q4; e += NT) {
     const int rr = e / q4, c4 = e - rr * q4;
     const int gr = wrapg(r0 - H + rr, p);
     reinterpret_cast<float4*>(Cs)[e] = ldg4(Cc + (size_t)gr * q + 4 * c4);
     reinterpret_cast<float4*>(As)[e] = zero4;
+    if (!FIRST) reinterpret_cast<float4*>(Cps)[e] = ldg4(Cpc + (size_t)gr * q + 4 * c4);
   }
   __syncthreads();
 
@@ -132,6 +148,8 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
   const int col = (threadIdx.x - row * q4) * 4;
   const bool ok = row < rows;
   const float4 cv = ok ? *reinterpret_cast<const float4*>(Cs + (row + H) * q + col) : zero4;
+  const float4 cvp =
+      ok && !FIRST ? *reinterpret_cast<const float4*>(Cps + (row + H) * q + col) : zero4;
   float4 cp = zero4;
 
   const size_t kstride = (size_t)R * q;
@@ -139,50 +157,114 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
   const size_t tile_off = ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
   gfloat* mup_tile = mup + ((size_t)c * ntiles + tile) * (size_t)npairs * ER * q;
 
+  // the shifts, one per lane, 64 at a time, packed as (tau1 << 16 | tau2): a load inside the
+  // shift loop would wait for every request issued before it
+  int tau_lane = 0;
+  auto tau_fetch = [&](int n0) {
+    const int j = n0 + (int)(threadIdx.x & 63);
+    const int2 tj = j < npairs ? tau_at(S, j) : make_int2(0, 0);
+    tau_lane = (tj.x << 16) | (tj.y & 0xffff);
+  };
+  tau_fetch(0);
+
+  // an item with a zero 2-bit field (an element inside the threshold) is stored
+  auto stored = [](unsigned b) { return ((b | (b >> 1)) & 0x55u) != 0x55u; };
+  constexpr int D = 2, E = FIRST ? 0 : 2;
+  const int nplanes = npairs * NP;
+  const unsigned itm = ok ? threadIdx.x : 0u;               // the lane's item in a plane
+  const unsigned segf = 4u * (threadIdx.x & ~63u);          // float offset of its wave segment
+  const unsigned long long okmask = __builtin_amdgcn_ballot_w64(ok);
+  auto pbase = [&](int x) { return tile_off + (size_t)min(x, nplanes - 1) * kstride; };
+  unsigned cq[D + 1];          // this step's branch codes of planes x .. x + D
+  unsigned pq[D + E + 1];      // the previous step's codes of planes x .. x + D + E
+  float4 sq[D + 1];            // packed Sigma'' of planes x .. x + D
+  auto req_codes = [&](int x, unsigned& cw) { cw = (cod + (pbase(x) >> 2))[itm]; };
+  auto req_pcodes = [&](int x, unsigned& pw) { pw = (pcod + (pbase(x) >> 2))[itm]; };
+  auto req_sigma = [&](int x, unsigned pw, float4& sv) {
+    const unsigned long long bal = __builtin_amdgcn_ballot_w64(stored(pw)) & okmask;
+    const unsigned slot = __builtin_amdgcn_mbcnt_hi(
+        (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+    sv = ld4_nt((sb + pbase(x)) + (segf + 4u * slot));
+  };
+  if (nplanes > 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) req_codes(i, cq[i]);
+    if (!FIRST) {
+#pragma unroll
+      for (int i = 0; i < D + E; ++i) req_pcodes(i, pq[i]);
+#pragma unroll
+      for (int i = 0; i < D; ++i) req_sigma(i, pq[i], sq[i]);
+    }
+  }
+
   for (int n = 0; n < npairs; ++n) {
-    const int2 t = tau_at(S, n);
+    if (n > 0 && (n & 63) == 0) tau_fetch(n);
+    const int tpk = __builtin_amdgcn_readlane(tau_lane, n & 63);
+    const int2 t = make_int2(tpk >> 16, (int)(short)(tpk & 0xffff));
     __syncthreads();
     for (int e = threadIdx.x; e < ER * (ms >> 2); e += NT) reinterpret_cast<float4*>(Mb)[e] = zero4;
     __syncthreads();
-    // A' at the item's four pixels
-    float ab[4], gb[4] = {0.f, 0.f, 0.f, 0.f};
+    // A' at the item's four pixels, and the previous step's Sigma'' of the items it did not
+    // store, -(A'_prev + 0)
+    float ab[4], dv[4], gb[4] = {0.f, 0.f, 0.f, 0.f};
     {
       const float* cr = Cs + (row + H - t.x) * q;
+      const float* crp = Cps + (row + H - t.x) * q;
       const float ca[4] = {cv.x, cv.y, cv.z, cv.w};
+      const float cap[4] = {cvp.x, cvp.y, cvp.z, cvp.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         int cc = col + e - t.y;
         cc = cc < 0 ? cc + q : (cc >= q ? cc - q : cc);
         ab[e] = ok ? 2.f * (ca[e] - cr[cc]) : 0.f;
+        const float abp = ok && !FIRST ? 2.f * (cap[e] - crp[cc]) : 0.f;
+        dv[e] = -(abp + 0.f);
       }
     }
-    const size_t n_off = tile_off + (size_t)n * tstride;
 #pragma unroll
     for (int k1 = -K; k1 <= K; ++k1) {
-      unsigned cw[KW];
-      float4 sbv[KW];
 #pragma unroll
       for (int k2 = 0; k2 < KW; ++k2) {
-        const size_t off = n_off + (size_t)((k1 + K) * KW + k2) * kstride + (size_t)row * q + col;
-        cw[k2] = ok ? (unsigned)cod[off >> 2] : 0u;
-        sbv[k2] = ok ? ld4_nt(sb + off) : zero4;
-      }
+        const int x = n * NP + (k1 + K) * KW + k2;   // plane of the workgroup
+        req_codes(x + D, cq[D]);
+        if (!FIRST) {
+          req_pcodes(x + D + E, pq[D + E]);
+          req_sigma(x + D, pq[D], sq[D]);
+        }
+        const unsigned cw = ok ? cq[0] : 0u;
+        float b4[4] = {0.f, 0.f, 0.f, 0.f};
+        if (!FIRST) {
+          const bool ps = ok && stored(pq[0]);
+          const float st[4] = {sq[0].x, sq[0].y, sq[0].z, sq[0].w};
 #pragma unroll
-      for (int k2 = 0; k2 < KW; ++k2) {
+          for (int e = 0; e < 4; ++e) b4[e] = ps ? st[e] : dv[e];
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          cq[i] = cq[i + 1];
+          sq[i] = sq[i + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < D + E; ++i) pq[i] = pq[i + 1];
         const int o = 4 + (k2 - K);
-        const float b4[4] = {sbv[k2].x, sbv[k2].y, sbv[k2].z, sbv[k2].w};
         float vb[4], mb[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const unsigned code = (cw[k2] >> (2 * e)) & 3u;
+          const unsigned code = (cw >> (2 * e)) & 3u;
           const float cbar = -b4[e] - 2.f * ab[e];
           vb[e] = ab[e] + (code == 0u ? cbar : 0.f);
           mb[e] = code == 1u ? cbar : (code == 2u ? -cbar : 0.f);
           gb[e] += vb[e];
         }
         if (ok) {
-          const size_t off = n_off + (size_t)((k1 + K) * KW + k2) * kstride + (size_t)row * q + col;
-          st4_nt(sb + off, make_float4(-vb[0], -vb[1], -vb[2], -vb[3]));
+          if (stored(cw)) {
+            // inside the branch the execution mask is the ballot of the storing lanes
+            const unsigned long long bal = __builtin_amdgcn_read_exec();
+            const unsigned slot = __builtin_amdgcn_mbcnt_hi(
+                (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            st4_nt((sb + tile_off + (size_t)x * kstride) + (segf + 4u * slot),
+                   make_float4(-vb[0], -vb[1], -vb[2], -vb[3]));
+          }
           float* mrow = Mb + (row + K + k1) * ms + col + o;   // mu' at (row + k1, col + k2 - K + e)
 #pragma unroll
           for (int e = 0; e < 4; ++e) mrow[e] += mb[e];
@@ -201,15 +283,42 @@ sweep_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ item
       }
     }
     __syncthreads();
-    // fold the padded columns into their wrapped positions and accumulate the partial tile
+    // fold the padded columns into their wrapped positions and accumulate the partial tile,
+    // as float4s, a thread's first MP4 read before one wait: a row of Mb holds PADW = 4
+    // columns on either side, one float4 folded into the row's first and last float4
     gfloat* mpn = mup_tile + (size_t)n * ER * q;
-    for (int e = threadIdx.x; e < ER * q; e += NT) {
-      const int rr = e / q, cc = e - rr * q;
-      const float* mrow = Mb + rr * ms + PADW;
-      float v = mrow[cc];
-      if (cc < PADW) v += mrow[q + cc];            // columns q .. q + PADW - 1
-      if (cc >= q - PADW) v += mrow[cc - q];       // columns -PADW .. -1
-      mpn[e] += v;
+    const int mp_n4 = ER * q4;
+    auto folded = [&](int e4) {
+      const int rr = e4 / q4, c4 = e4 - rr * q4;
+      const float4* mrow = reinterpret_cast<const float4*>(Mb + rr * ms);
+      float4 v = mrow[1 + c4];
+      if (c4 == 0) {                               // columns q .. q + 3
+        const float4 w = mrow[1 + q4];
+        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+      }
+      if (c4 == q4 - 1) {                          // columns -4 .. -1
+        const float4 w = mrow[0];
+        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+      }
+      return v;
+    };
+    constexpr int MP4 = 2;
+    float4 mpv[MP4];
+#pragma unroll
+    for (int u = 0; u < MP4; ++u)
+      mpv[u] = ldg4(mpn + 4 * min((int)threadIdx.x + u * NT, mp_n4 - 1));
+#pragma unroll
+    for (int u = 0; u < MP4; ++u) {
+      const int e4 = threadIdx.x + u * NT;
+      if (e4 < mp_n4) {
+        const float4 v = folded(e4);
+        stg4(mpn + 4 * e4, make_float4(mpv[u].x + v.x, mpv[u].y + v.y, mpv[u].z + v.z,
+                                       mpv[u].w + v.w));
+      }
+    }
+    for (int e4 = threadIdx.x + MP4 * NT; e4 < mp_n4; e4 += NT) {
+      const float4 v = folded(e4), m = ldg4(mpn + 4 * e4);
+      stg4(mpn + 4 * e4, make_float4(m.x + v.x, m.y + v.y, m.z + v.z, m.w + v.w));
     }
   }
   __syncthreads();
@@ -608,17 +717,23 @@ int launch_kind(const Batch& B, Kind kind, const char* name, Kern kern, hipStrea
 
 template <int K>
 int launch_sbwd(const Batch& B, const Group& g, size_t lds, int cb, const uint8_t* codes, int sb,
-                int xr, int halo, int mup, hipStream_t s) {
-  auto kern = sweep_bwd_kernel<K>;
-  hipLaunchKernelGGL(kern, dim3(g.nitems), dim3(256), lds, s, B.d_desc, g.d_items, cb, codes, sb,
-                     xr, halo, mup);
+                int xr, int halo, int mup, const uint8_t* pcodes, int cbp, hipStream_t s) {
+  if (pcodes) {
+    hipLaunchKernelGGL((sweep_bwd_kernel<K, false>), dim3(g.nitems), dim3(256), lds, s,
+                       B.d_desc, g.d_items, cb, codes, sb, xr, halo, mup, pcodes, cbp);
+  } else {
+    hipLaunchKernelGGL((sweep_bwd_kernel<K, true>), dim3(g.nitems), dim3(256), lds, s,
+                       B.d_desc, g.d_items, cb, codes, sb, xr, halo, mup, codes, cb);
+  }
   NLPR_LAUNCH_CHECK("sweep_bwd_kernel");
   return NLPR_OK;
 }
 
 template <int K>
 int sbwd_attr() {
-  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K>),
+  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K, true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
+  NLPR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_bwd_kernel<K, false>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxSweepLds));
   return NLPR_OK;
 }
@@ -627,7 +742,7 @@ int sbwd_attr() {
 
 size_t sweep_bwd_lds(const Plan& P) {
   const int R = P.sweep.rows, H = P.sweep.halo, K = P.prm.K, q = P.prm.q;
-  return (size_t)((R + 2 * K) * (q + 2 * PADW) + 2 * (R + H) * q) * sizeof(float);
+  return (size_t)((R + 2 * K) * (q + 2 * PADW) + 3 * (R + H) * q) * sizeof(float);
 }
 size_t weights_bwd_lds(const Plan& P) {
   const int K = P.prm.K;
@@ -654,18 +769,18 @@ int sweep_bwd_prepare(int K) {
 }
 
 int launch_sweep_bwd(const Batch& B, int cb, const uint8_t* codes, int sb, int xr, int halo,
-                     int mup, hipStream_t s) {
+                     int mup, const uint8_t* pcodes, int cbp, hipStream_t s) {
   const Plan& P = *B.scenes[0];
   const size_t lds = sweep_bwd_lds(P);
   for (const Group& g : B.groups[KD_SWEEP]) {
     if (!g.nitems) continue;
     int rc;
     switch (g.key0) {
-      case 0: rc = launch_sbwd<0>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
-      case 1: rc = launch_sbwd<1>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
-      case 2: rc = launch_sbwd<2>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
-      case 3: rc = launch_sbwd<3>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
-      case 4: rc = launch_sbwd<4>(B, g, lds, cb, codes, sb, xr, halo, mup, s); break;
+      case 0: rc = launch_sbwd<0>(B, g, lds, cb, codes, sb, xr, halo, mup, pcodes, cbp, s); break;
+      case 1: rc = launch_sbwd<1>(B, g, lds, cb, codes, sb, xr, halo, mup, pcodes, cbp, s); break;
+      case 2: rc = launch_sbwd<2>(B, g, lds, cb, codes, sb, xr, halo, mup, pcodes, cbp, s); break;
+      case 3: rc = launch_sbwd<3>(B, g, lds, cb, codes, sb, xr, halo, mup, pcodes, cbp, s); break;
+      case 4: rc = launch_sbwd<4>(B, g, lds, cb, codes, sb, xr, halo, mup, pcodes, cbp, s); break;
       default:
         set_error("sweep adjoint: unsupported patch radius");
         return NLPR_ERR_UNSUPPORTED_SHAPE;

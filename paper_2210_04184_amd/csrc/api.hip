@@ -827,7 +827,7 @@ GradLayout grad_layout(const Plan& P) {
     G.off[slot] = off;
     off = align256(off + std::max<size_t>(bytes, 4));
   };
-  for (int k : {B_GC, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR}) take(k, pl);
+  for (int k : {B_GC, B_GCP, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR}) take(k, pl);
   const size_t mup = (size_t)P.npairs * P.prm.p * P.prm.q * sizeof(float);
   G.npix = pixel_blocks(P);
   G.nw = P.npairs ? weights_bwd_blocks(P) : 0;
@@ -961,9 +961,15 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
   char* gb = static_cast<char*>(gws);
   // X, B X and Lambda of each iteration are read from its checkpoint (slots re-pointed)
   SceneDesc d = solve_desc(P, base, Yl, Yh, reinterpret_cast<float*>(base + P.off[B_W2]));
-  for (int k : {B_GC, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR, B_GSIG, B_GHALO, B_GMUP,
-                B_GMU, B_GE, B_GPART})
+  for (int k : {B_GC, B_GCP, B_GL1, B_GL2, B_GX, B_GW1, B_GBX, B_GXP, B_GXR, B_GSIG, B_GHALO,
+                B_GMUP, B_GMU, B_GE, B_GPART})
     d.buf[k] = gb + G.off[k];
+  // C' alternates between two buffers, so that the sweep adjoint of step t still has the C'
+  // of step t + 1 (slot B_GCP), from which it rebuilds the Sigma'' that step did not store
+  const int T = B.iters;
+  char* cbuf[2] = {gb + G.off[B_GC], gb + G.off[B_GCP]};
+  d.buf[B_GC] = cbuf[(T - 1) & 1];
+  d.buf[B_GCP] = cbuf[T & 1];
   d.buf[B_GZ] = const_cast<float*>(dZ);
   d.buf[B_GYL] = dYl;
   d.buf[B_GYH] = dYh;
@@ -971,13 +977,11 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
   DeviceGuard dg(B.device);
   if ((rc = upload_desc(B, descs, s))) return rc;
   B.desc_valid = false;          // the checkpoint slots below change the device copy
-  const int T = B.iters;
   const bool reg = P.npairs > 0;
   const int p = P.prm.p, q = P.prm.q, d_ = P.prm.d;
   const size_t pl = (size_t)P.Lx * p * q * sizeof(float);
   NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GL1], 0, pl, s));
   NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GL2], 0, pl, s));
-  NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GSIG], 0, P.sz[B_SIGMA], s));
   if (reg)
     NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GMUP], 0, mubar_partial_elems(P) * sizeof(float), s));
   NLPR_HIP_TRY(hipMemsetAsync(gb + G.off[B_GPART], 0, 2 * (size_t)(G.npix + G.nw) * sizeof(double), s));
@@ -987,20 +991,29 @@ int grad_backward(Batch& B, const float* Yl, const float* Yh, const float* dZ, v
   // Z = X^T = solve(C^{T-1})
   if ((rc = launch_xsolve(B, B_GZ, B_GC, B_F, -1, s))) return rc;
   for (int t = T - 1; t >= 1; --t) {
-    SlotSet st;                  // X^t, B X^t and the Lambda entering iteration t
+    SlotSet st;                  // X^t, B X^t and the Lambda entering iteration t; C'
     for (int k = 0; k < 4; ++k) st.add(k == 0 ? B_Z : k == 1 ? B_BX : k == 2 ? B_L1 : B_L2,
                                        ck_plane(ck, G, t, k));
+    st.add(B_GC, cbuf[t & 1]);
+    st.add(B_GCP, cbuf[(t + 1) & 1]);
     if ((rc = launch_set_slots(B, st, s))) return rc;
     if ((rc = launch_conv(B, B_GC, B_GW1, false, -1, -1, -1, 0, s))) return rc;   // W1' = B C'
     if (reg && (rc = launch_sweep_bwd(B, B_GC, ck_codes(ck, G, T, t), B_GSIG, B_GXR, B_GHALO,
-                                      B_GMUP, s)))
+                                      B_GMUP, t + 1 < T ? ck_codes(ck, G, T, t + 1) : nullptr,
+                                      B_GCP, s)))
       return rc;
     if ((rc = launch_pupdate_bwd(B, B_Z, B_BX, B_YL, B_YH, B_L1, B_L2, B_GW1, B_GC, B_GL1, B_GL2,
                                  B_GBX, B_GXP, B_GYL, B_GYH, B_GPART, s)))
       return rc;
     // X' = B^T BX' + X'(P-update) + X'(sweep) (+ halo rows)
     if ((rc = launch_conv(B, B_GBX, B_GX, true, B_GXP, B_GXR, B_GHALO, 2, s))) return rc;
-    if ((rc = launch_xsolve(B, B_GX, B_GC, B_F, -1, s))) return rc;
+    if ((rc = launch_xsolve(B, B_GX, B_GCP, B_F, -1, s))) return rc;   // C' of step t - 1
+  }
+  if (T > 1) {                   // C' of the start was written into buffer 0
+    SlotSet st;
+    st.add(B_GC, cbuf[0]);
+    st.add(B_GCP, cbuf[1]);
+    if ((rc = launch_set_slots(B, st, s))) return rc;
   }
   // start: C^0 = B^T B X0 + X0, X0 = up(Y_l)
   if ((rc = launch_conv(B, B_GC, B_GW1, false, -1, -1, -1, 0, s))) return rc;

@@ -50,8 +50,9 @@ enum Slot {
   // reverse mode (single scene): adjoints of the iteration's variables and the outputs
   B_GZ,      // Z' (input)
   B_GC,      // C'
+  B_GCP,     // C' of the backward step before (the sweep adjoint rebuilds Sigma'' from it)
   B_GL1, B_GL2,   // Lambda1'', Lambda2''
-  B_GSIG,    // Sigma''
+  B_GSIG,    // Sigma'' (coded: float4 items with an element inside the threshold, packed)
   B_GX,      // X'
   B_GW1,     // W1' = B C'
   B_GBX,     // BX'
@@ -340,9 +341,11 @@ size_t weights_bwd_lds(const Plan& P);
 int weights_bwd_blocks(const Plan& P);
 size_t mubar_partial_elems(const Plan& P);
 int sweep_bwd_prepare(int K);
-// codes: the forward sweep's threshold branches of the iteration (launch_sweep's codes)
+// codes: the forward sweep's threshold branches of the iteration (launch_sweep's codes);
+// pcodes, cbp: those of the iteration whose backward step ran last and its C' (null on the
+// first backward step, whose incoming Sigma'' is zero)
 int launch_sweep_bwd(const Batch& B, int cb, const uint8_t* codes, int sb, int xr, int halo,
-                     int mup, hipStream_t s);
+                     int mup, const uint8_t* pcodes, int cbp, hipStream_t s);
 int launch_mubar_reduce(const Batch& B, int mup, int mub, hipStream_t s);
 int launch_pupdate_bwd(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1b,
                        int w2b, int l1b, int l2b, int bxb, int xp, int gyl, int gyh, int part,
