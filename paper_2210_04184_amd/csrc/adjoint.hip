@@ -414,7 +414,65 @@ __device__ __forceinline__ double pupdate_bwd_write(
   return acc;
 }
 
-template <int LHM, int PB_NC>
+// pupdate_bwd_write with the thread's W2' in registers and every read issued first.
+template <int LHM, int KB>
+__device__ __forceinline__ double pupdate_bwd_write_kept(
+    const gfloat* __restrict__ BX, const gfloat* __restrict__ Yl, const gfloat* __restrict__ L1,
+    const gfloat* __restrict__ W1b, const float (&w2k)[KB], gfloat* __restrict__ L1b,
+    gfloat* __restrict__ L2b, gfloat* __restrict__ BXb, gfloat* __restrict__ Xp,
+    gfloat* __restrict__ GYl, const gfloat* __restrict__ R, const float (&v)[LHM], size_t plane,
+    size_t lplane, size_t lj, bool sampled, int Lh, float inv, float rr, int c0, int c1, int j) {
+  float w1a[KB], l1ba[KB], yla[KB], bxa[KB], l1a[KB], gya[KB];
+#pragma unroll
+  for (int i = 0; i < KB; ++i)
+    if (c0 + i < c1) {
+      const int c = c0 + i;
+      const size_t o = (size_t)c * plane + j;
+      w1a[i] = W1b[o];
+      if (sampled) {
+        l1ba[i] = L1b[o];
+        yla[i] = Yl[c * lplane + lj];
+        bxa[i] = BX[o];
+        l1a[i] = L1[o];
+        gya[i] = GYl[c * lplane + lj];
+      }
+    }
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < KB; ++i)
+    if (c0 + i < c1) {
+      const int c = c0 + i;
+      const size_t o = (size_t)c * plane + j;
+      float corr = 0.f;
+#pragma unroll
+      for (int h = 0; h < LHM; ++h)
+        if (h < Lh) corr += v[h] * R[c * Lh + h];
+      const float xp = w2k[i] - corr;
+      Xp[o] = xp;
+      L2b[o] = -xp;
+      const float w1b = w1a[i];
+      if (sampled) {
+        const float l1b = l1ba[i];
+        const float p1b = 2.f * w1b + l1b;
+        const float y = yla[i];
+        BXb[o] = -w1b - l1b + p1b * rr;
+        L1b[o] = w1b + l1b - p1b * rr;
+        GYl[c * lplane + lj] = gya[i] + p1b * inv;
+        acc += (double)p1b * ((double)bxa[i] - (double)l1a[i] - (double)y) * (double)inv *
+               (double)inv;
+      } else {
+        BXb[o] = w1b;
+        L1b[o] = -w1b;
+      }
+    }
+  return acc;
+}
+
+// With at most kPbKeep bands per thread (KEEP), every read of a pass is issued before the
+// pass's arithmetic, and W2' is read once, kept in registers between the two passes; the
+// arithmetic and its order are those of the band loops.
+constexpr int kPbKeep = 8;
+template <int LHM, int PB_NC, bool KEEP>
 __global__ void __launch_bounds__(256 * PB_NC)
 pupdate_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, int x_s,
                    int bx_s, int yl_s, int yh_s, int l1_s, int l2_s, int w1b_s, int w2b_s,
@@ -440,7 +498,34 @@ pupdate_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ it
   float rp[LHM], sp[LHM];
 #pragma unroll
   for (int h = 0; h < LHM; ++h) rp[h] = sp[h] = 0.f;
-  if (act)
+  constexpr int KB = KEEP ? kPbKeep : 1;
+  float w2k[KB];                        // W2' of the thread's bands (KEEP)
+  if (KEEP && act) {
+    float xa[KB], l2a[KB], l2ba[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+      if (c0 + i < c1) {
+        const size_t o = (size_t)(c0 + i) * plane + j;
+        xa[i] = X[o];
+        l2a[i] = L2[o];
+        w2k[i] = W2b[o];
+        l2ba[i] = L2b[o];
+      }
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+      if (c0 + i < c1) {
+        const int c = c0 + i;
+        const float a0 = xa[i] - l2a[i];
+        const float p2b = 2.f * w2k[i] + l2ba[i];
+#pragma unroll
+        for (int h = 0; h < LHM; ++h)
+          if (h < Lh) {
+            rp[h] += a0 * R[c * Lh + h];
+            sp[h] += p2b * R[c * Lh + h];
+          }
+      }
+  }
+  if (!KEEP && act)
     for (int c = c0; c < c1; ++c) {      // this quarter's A0 R and P2' R
       const size_t o = (size_t)c * plane + j;
       const float a0 = X[o] - L2[o];
@@ -525,8 +610,13 @@ pupdate_bwd_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ it
       for (int h = 0; h < LHM; ++h)      // after every read of G (stores would order them)
         if (h < Lh) GYh[h * plane + j] += v[h];
     }
-    acc[0] = pupdate_bwd_write<LHM>(BX, Yl, L1, W1b, W2b, L1b, L2b, BXb, Xp, GYl, R, v, plane,
-                                    lplane, lj, sampled, Lh, inv, rr, c0, c1, j);
+    if constexpr (KEEP)
+      acc[0] = pupdate_bwd_write_kept<LHM, KB>(BX, Yl, L1, W1b, w2k, L1b, L2b, BXb, Xp, GYl, R,
+                                               v, plane, lplane, lj, sampled, Lh, inv, rr, c0,
+                                               c1, j);
+    else
+      acc[0] = pupdate_bwd_write<LHM>(BX, Yl, L1, W1b, W2b, L1b, L2b, BXb, Xp, GYl, R, v, plane,
+                                      lplane, lj, sampled, Lh, inv, rr, c0, c1, j);
   }
   block_sum_waves<2, 4 * PB_NC>(acc);
   if (threadIdx.x == 0) {
@@ -798,9 +888,15 @@ template <int LHM, int NC>
 void launch_pb(const Batch& B, const Group& g, int x, int bx, int yl, int yh, int l1, int l2,
                int w1b, int w2b, int l1b, int l2b, int bxb, int xp, int gyl, int gyh, int part,
                hipStream_t s) {
-  hipLaunchKernelGGL((pupdate_bwd_kernel<LHM, NC>), dim3(g.nitems), dim3(256 * NC), 0, s,
-                     B.d_desc, g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb, xp, gyl,
-                     gyh, part);
+  // the reverse mode takes one scene: its bands per thread decide the variant
+  if (ceil_div(B.scenes[0]->Lx, NC) <= kPbKeep)
+    hipLaunchKernelGGL((pupdate_bwd_kernel<LHM, NC, true>), dim3(g.nitems), dim3(256 * NC), 0,
+                       s, B.d_desc, g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb,
+                       xp, gyl, gyh, part);
+  else
+    hipLaunchKernelGGL((pupdate_bwd_kernel<LHM, NC, false>), dim3(g.nitems), dim3(256 * NC), 0,
+                       s, B.d_desc, g.d_items, x, bx, yl, yh, l1, l2, w1b, w2b, l1b, l2b, bxb,
+                       xp, gyl, gyh, part);
 }
 
 int launch_pupdate_bwd(const Batch& B, int x, int bx, int yl, int yh, int l1, int l2, int w1b,
