@@ -73,6 +73,7 @@ SHAPES = [
     (32, 24, 2, 1, 2, 1, 0, 2, 4),      # 1 x 1 patch (pixel differences)
     (24, 24, 1, 1, 2, 1, 3, 1, 3),      # 7 x 7 patch
     (18, 24, 1, 2, 2, 1, 4, 1, 3),      # 9 x 9 patch
+    (16, 384, 2, 1, 2, 1, 1, 1, 4),     # 768-pixel sweep tiles: one wave without an item
 ]
 
 

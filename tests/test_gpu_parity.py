@@ -2,7 +2,8 @@
 
 Inputs are the seeded synthetic scenes (rounded once to float32); the oracle reads the same
 float32 values as float64.  Shapes cover radix 2/3/4/8 transforms, several sweep tiles with
-a ragged last tile, a tile shorter than the halo, odd band counts and 1..4 guide bands.
+a ragged last tile, a tile shorter than the halo, a tile that leaves one wave of each sweep
+workgroup without an item, odd band counts and 1..4 guide bands.
 
 Tolerances.  The bar for the solve is a relative RMSE of 1e-4 on Z.  Single
 steps are held to what FP32 arithmetic gives: a few ulps times the depth of the sums.
@@ -24,6 +25,8 @@ SHAPES = {
     "radix3": (48, 36, 3, 3, 2, 1, 1, 1),
     "wide": (64, 512, 2, 4, 4, 4, 1, 3),
     "thin": (8, 2048, 2, 1, 2, 1, 0, 3),
+    # 768-pixel sweep tiles: the last wave of each workgroup has no item in the tile
+    "idle_wave": (16, 384, 3, 1, 2, 1, 2, 2),
 }
 
 
@@ -289,7 +292,7 @@ def test_sweep_split_rule():
         assert plan.info().sweep_split == want, (p, q, L, K, Sw, plan.info().sweep_split)
 
 
-@pytest.mark.parametrize("name", ["ragged", "radix3", "wide", "thin"])
+@pytest.mark.parametrize("name", ["ragged", "radix3", "wide", "thin", "idle_wave"])
 def test_solve_shapes_match_oracle(name):
     sc = scene_for(name, iters=12)
     z, _, _ = solve_gpu(sc)
@@ -350,7 +353,7 @@ def test_sigma_stays_within_thresholds_and_shrink_branch_is_exercised():
     assert 0.05 <= frac <= 0.95, frac
 
 
-@pytest.mark.parametrize("name", ["ragged", "wide", "radix3"])
+@pytest.mark.parametrize("name", ["ragged", "wide", "radix3", "idle_wave"])
 def test_coded_dual_state_counts_its_open_items(name):
     """Sigma' keeps only the float4 items with an element off the threshold (|Sigma'| < mu);
     the number the last sweep reports writing equals the number of such items in the
