@@ -45,6 +45,9 @@ namespace {
 #endif
 // cache policy of a buffer access: non-temporal
 constexpr int kCacheNT = 2;
+// last word of a raw byte-addressed buffer resource: 32-bit data format (bits 15-18 = 4),
+// no stride, no swizzle; offsets are bytes from the base
+constexpr int kRawBufferFlags = 0x00020000;
 __device__ __forceinline__ float4 ld_nt(const gfloat* p) {
 #if NLPR_SWEEP_NT
   const v4f_t v = __builtin_nontemporal_load((const gv4f*)p);
@@ -154,7 +157,8 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const size_t kstride = (size_t)R * q;             // between patch offsets
   const size_t tstride = (size_t)NP * kstride;      // between shifts
   const size_t tile_off = ((size_t)c * ntiles + tile) * (size_t)npairs * tstride;
-  // code bytes of the next patch row to process, requested one row ahead
+  // without the pipeline below (several items per thread): code bytes of the next patch
+  // row to process, requested one row ahead
   unsigned cbn[KW][ITEMS];
   auto load_codes = [&](size_t row_off) {
 #pragma unroll
@@ -215,7 +219,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const unsigned cstride = (unsigned)(kstride >> 2);
   const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(uint8_t*)(scode + (base >> 2)), (short)0, PIPE ? nplanes * (int)cstride : 0,
-      0x00020000);
+      kRawBufferFlags);
   auto pipe_codes = [&](int x) -> unsigned {
     return __builtin_amdgcn_raw_buffer_load_b8(crs, threadIdx.x, min(x, nplanes - 1) * cstride,
                                                kCacheNT);
