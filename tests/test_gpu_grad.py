@@ -74,6 +74,7 @@ SHAPES = [
     (24, 24, 1, 1, 2, 1, 3, 1, 3),      # 7 x 7 patch
     (18, 24, 1, 2, 2, 1, 4, 1, 3),      # 9 x 9 patch
     (16, 384, 2, 1, 2, 1, 1, 1, 4),     # 768-pixel sweep tiles: one wave without an item
+    (24, 24, 1, 1, 2, 1, 1, 6, 3),      # 13 x 13 window: 84 shifts, over 64 at a time
 ]
 
 
