@@ -211,7 +211,8 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   constexpr int D = K <= 1 ? 6 : 5, E = D;
   const int nplanes = (n_end - n_begin) * NP;
   const size_t base = tile_off + (size_t)n_begin * tstride;
-  unsigned cq[D + E + 1];  // code bytes of planes x .. x + D + E
+  uint8_t cq[D + E + 1];   // code bytes of planes x .. x + D + E (kept as bytes: a widening
+                           // at the loop's back edge would wait for the loads in flight)
   float4 sb[D + 1];        // open float4s of planes x .. x + D
   // the workgroup's code bytes as one buffer, plane x at byte x * cstride: a lane's byte is
   // addressed by the plane offset (a scalar) and the thread index, with no vector arithmetic
@@ -220,7 +221,7 @@ sweep_kernel(const SceneDesc* __restrict__ sd, const int2* __restrict__ items, i
   const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(uint8_t*)(scode + (base >> 2)), (short)0, PIPE ? nplanes * (int)cstride : 0,
       kRawBufferFlags);
-  auto pipe_codes = [&](int x) -> unsigned {
+  auto pipe_codes = [&](int x) -> uint8_t {
     return __builtin_amdgcn_raw_buffer_load_b8(crs, threadIdx.x, min(x, nplanes - 1) * cstride,
                                                kCacheNT);
   };
